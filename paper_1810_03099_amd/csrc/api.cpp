@@ -1,0 +1,360 @@
+// C ABI entry points of libmrc: argument checks, object life cycle, stage
+// sequencing on the caller's stream, and status reporting.
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+
+#include "common.h"
+
+using namespace mrc;
+
+namespace {
+
+constexpr uint64_t kErrOffsets = 1, kErrToken = 2, kErrSelection = 4;
+
+mrc_status check_ctx(mrc_ctx* ctx, const char* fn) {
+    if (!ctx) return fail(MRC_E_INVAL, std::string(fn) + ": ctx is NULL");
+    if (ctx->sticky != MRC_OK)
+        return fail(MRC_E_HIP, std::string(fn) + ": context unusable after an earlier HIP error");
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(ctx, e, "hipSetDevice", __FILE__, __LINE__);
+    // Drop an error another library left in the thread's last-error slot, so
+    // that the launch checks below report only this call's launches.
+    (void)hipGetLastError();
+    return MRC_OK;
+}
+
+mrc_status check_docs(const mrc_docs* d, const char* fn) {
+    if (!d) return fail(MRC_E_INVAL, std::string(fn) + ": docs is NULL");
+    if (d->n_docs < 0 || d->n_docs > 0x7FFFFFFFLL)
+        return fail(MRC_E_INVAL, std::string(fn) + ": n_docs out of range");
+    if (!d->offsets) return fail(MRC_E_INVAL, std::string(fn) + ": offsets is NULL");
+    if (d->n_docs > 0 && !d->tokens) return fail(MRC_E_INVAL, std::string(fn) + ": tokens is NULL");
+    return MRC_OK;
+}
+
+// Read the context flag words back after the stream drains; report input errors.
+mrc_status sync_flags(mrc_ctx* ctx, hipStream_t s, int n_words, const char* fn) {
+    MRC_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, n_words * sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, s));
+    MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
+    const uint64_t err = (uint64_t)ctx->h_flags[0];
+    if (err & kErrOffsets) return fail(MRC_E_INVAL, std::string(fn) + ": malformed offsets");
+    if (err & kErrToken) return fail(MRC_E_INVAL, std::string(fn) + ": token id outside [0, vocab)");
+    if (err & kErrSelection)
+        return fail(MRC_E_INVAL, std::string(fn) + ": reference selection holds fewer terms than k");
+    return MRC_OK;
+}
+
+void free_model(mrc_model* m) {
+    if (!m) return;
+    mrc_ctx* c = m->ctx;
+    size_t V = (size_t)m->vocab, k = (size_t)m->k;
+    dev_free(c, m->d_df, V * 4);
+    dev_free(c, m->d_idf, V * 4);
+    dev_free(c, m->d_term_at, V * 4);
+    dev_free(c, m->d_rank_of, V * 4);
+    dev_free(c, m->d_tinfo, V * sizeof(TermInfo));
+    dev_free(c, m->d_rnorm, k * 8);
+    dev_free(c, m->d_rinv, k * 8);
+    dev_free(c, m->d_hash, V * 8);
+    delete m;
+}
+
+mrc_status alloc_model(mrc_ctx* ctx, int32_t V, int32_t k, mrc_model** out) {
+    mrc_model* m = new mrc_model();
+    m->ctx = ctx;
+    m->vocab = V;
+    m->k = k;
+    mrc_status st = MRC_OK;
+    const size_t Vs = (size_t)V;
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_df, Vs * 4);
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_idf, Vs * 4);
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_term_at, Vs * 4);
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_rank_of, Vs * 4);
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_tinfo, Vs * sizeof(TermInfo));
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_rnorm, (size_t)k * 8);
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_rinv, (size_t)k * 8);
+    if (st != MRC_OK) {
+        free_model(m);
+        return st;
+    }
+    *out = m;
+    return MRC_OK;
+}
+
+mrc_status check_spec(const mrc_ref_spec* spec, int32_t V) {
+    if (!spec) return fail(MRC_E_INVAL, "spec is NULL");
+    if (spec->k < 1 || spec->k > 1024) return fail(MRC_E_INVAL, "k must lie in [1, 1024]");
+    if (spec->mode < MRC_SEL_ALL || spec->mode > MRC_SEL_DROP_TOP) return fail(MRC_E_INVAL, "bad selection mode");
+    if (spec->idf_mode != MRC_IDF_SMOOTH && spec->idf_mode != MRC_IDF_NONE) return fail(MRC_E_INVAL, "bad idf mode");
+    if (spec->ref_weight != MRC_REF_ONE && spec->ref_weight != MRC_REF_IDF) return fail(MRC_E_INVAL, "bad reference weight");
+    if (spec->mode == MRC_SEL_REGION && spec->lo < 0) return fail(MRC_E_INVAL, "region lo < 0");
+    if (spec->mode == MRC_SEL_RAREST && spec->m < 1) return fail(MRC_E_INVAL, "rarest m < 1");
+    if (spec->mode == MRC_SEL_DROP_TOP && (spec->drop_top_ppm < 0 || spec->drop_top_ppm > 1000000))
+        return fail(MRC_E_INVAL, "drop_top_ppm outside [0, 1e6]");
+    if (spec->k > V) return fail(MRC_E_INVAL, "k exceeds the vocabulary");
+    return MRC_OK;
+}
+
+uint64_t fnv1a(const void* p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= b[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+// ------------------------------------------------------------------ model
+
+mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
+                               const mrc_ref_spec* spec, mrc_model** out, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_build_vocab_idf"));
+    MRC_TRY(check_docs(corpus, "mrc_build_vocab_idf"));
+    if (!out) return fail(MRC_E_INVAL, "mrc_build_vocab_idf: out is NULL");
+    *out = nullptr;
+    if (vocab_size < 1 || vocab_size > (1 << 24)) return fail(MRC_E_INVAL, "vocab_size must lie in [1, 2^24]");
+    MRC_TRY(check_spec(spec, vocab_size));
+    hipStream_t s = (hipStream_t)hip_stream;
+    mrc_model* m = nullptr;
+    MRC_TRY(alloc_model(ctx, vocab_size, spec->k, &m));
+    m->n_docs = corpus->n_docs;
+    m->spec = *spec;
+    auto bail = [&](mrc_status st) {
+        (void)hipStreamSynchronize(s);
+        free_model(m);
+        return st;
+    };
+    DocBuckets b;
+    mrc_status st = launch_classify(ctx, corpus, vocab_size, &b, s);
+    if (st == MRC_OK) {
+        hipError_t e = hipMemsetAsync(m->d_df, 0, (size_t)vocab_size * 4, s);
+        if (e != hipSuccess) st = hip_fail(ctx, e, "memset df", __FILE__, __LINE__);
+    }
+    if (st == MRC_OK) st = launch_df(ctx, corpus, vocab_size, b, m->d_df, s);
+    if (st == MRC_OK) st = launch_model_tables(ctx, m, s);
+    if (st == MRC_OK) st = sync_flags(ctx, s, 9, "mrc_build_vocab_idf");
+    if (st != MRC_OK) return bail(st);
+    m->n_listed = ctx->h_flags[6];
+    m->lo = ctx->h_flags[7];
+    m->hi = ctx->h_flags[8];
+    *out = m;
+    return MRC_OK;
+}
+
+mrc_status mrc_model_destroy(mrc_model* model) {
+    if (!model) return MRC_OK;
+    (void)hipSetDevice(model->ctx->device);
+    (void)hipDeviceSynchronize();
+    free_model(model);
+    return MRC_OK;
+}
+
+mrc_status mrc_model_info(const mrc_model* m, int64_t* n_docs, int32_t* vocab, int32_t* k,
+                          int64_t* n_listed, int64_t* lo, int64_t* hi) {
+    if (!m) return fail(MRC_E_INVAL, "mrc_model_info: model is NULL");
+    if (n_docs) *n_docs = m->n_docs;
+    if (vocab) *vocab = m->vocab;
+    if (k) *k = m->k;
+    if (n_listed) *n_listed = m->n_listed;
+    if (lo) *lo = m->lo;
+    if (hi) *hi = m->hi;
+    return MRC_OK;
+}
+
+mrc_status mrc_model_get(const mrc_model* m, uint32_t* df, float* idf, int32_t* term_at, int32_t* rank_of,
+                         int32_t* part_of, double* rnorm) {
+    if (!m) return fail(MRC_E_INVAL, "mrc_model_get: model is NULL");
+    mrc_ctx* ctx = m->ctx;
+    MRC_TRY(check_ctx(ctx, "mrc_model_get"));
+    const size_t V = (size_t)m->vocab;
+    if (df) MRC_HIP_TRY(ctx, hipMemcpy(df, m->d_df, V * 4, hipMemcpyDeviceToHost));
+    if (idf) MRC_HIP_TRY(ctx, hipMemcpy(idf, m->d_idf, V * 4, hipMemcpyDeviceToHost));
+    if (term_at) MRC_HIP_TRY(ctx, hipMemcpy(term_at, m->d_term_at, V * 4, hipMemcpyDeviceToHost));
+    if (rank_of) MRC_HIP_TRY(ctx, hipMemcpy(rank_of, m->d_rank_of, V * 4, hipMemcpyDeviceToHost));
+    if (part_of) {
+        std::vector<TermInfo> ti(V);
+        MRC_HIP_TRY(ctx, hipMemcpy(ti.data(), m->d_tinfo, V * sizeof(TermInfo), hipMemcpyDeviceToHost));
+        for (size_t t = 0; t < V; ++t) part_of[t] = ti[t].part;
+    }
+    if (rnorm) MRC_HIP_TRY(ctx, hipMemcpy(rnorm, m->d_rnorm, (size_t)m->k * 8, hipMemcpyDeviceToHost));
+    return MRC_OK;
+}
+
+// File layout: magic "MRCMODEL", u32 version, header fields, then df[V],
+// idf[V], term_at[V], rank_of[V], tinfo[V], rnorm[k], rinv[k], u64 FNV-1a
+// checksum of everything before it.
+mrc_status mrc_model_save(const mrc_model* m, const char* path) {
+    if (!m || !path) return fail(MRC_E_INVAL, "mrc_model_save: NULL argument");
+    mrc_ctx* ctx = m->ctx;
+    MRC_TRY(check_ctx(ctx, "mrc_model_save"));
+    const size_t V = (size_t)m->vocab, k = (size_t)m->k;
+    std::vector<char> buf;
+    auto put = [&](const void* p, size_t n) {
+        const char* c = (const char*)p;
+        buf.insert(buf.end(), c, c + n);
+    };
+    const char magic[8] = {'M', 'R', 'C', 'M', 'O', 'D', 'E', 'L'};
+    const uint32_t version = 1;
+    put(magic, 8);
+    put(&version, 4);
+    put(&m->n_docs, 8);
+    put(&m->vocab, 4);
+    put(&m->spec, sizeof(mrc_ref_spec));
+    put(&m->k, 4);
+    put(&m->n_listed, 8);
+    put(&m->lo, 8);
+    put(&m->hi, 8);
+    std::vector<char> tmp(V * sizeof(TermInfo));
+    struct Arr { const void* d; size_t n; } arrs[] = {
+        {m->d_df, V * 4}, {m->d_idf, V * 4}, {m->d_term_at, V * 4}, {m->d_rank_of, V * 4},
+        {m->d_tinfo, V * sizeof(TermInfo)}, {m->d_rnorm, k * 8}, {m->d_rinv, k * 8}};
+    for (auto& a : arrs) {
+        MRC_HIP_TRY(ctx, hipMemcpy(tmp.data(), a.d, a.n, hipMemcpyDeviceToHost));
+        put(tmp.data(), a.n);
+    }
+    uint64_t h = fnv1a(buf.data(), buf.size());
+    put(&h, 8);
+    std::ofstream f(path, std::ios::binary);
+    if (!f) return fail(MRC_E_INVAL, std::string("mrc_model_save: cannot open ") + path);
+    f.write(buf.data(), (std::streamsize)buf.size());
+    if (!f) return fail(MRC_E_INVAL, "mrc_model_save: write failed");
+    return MRC_OK;
+}
+
+mrc_status mrc_model_load(mrc_ctx* ctx, const char* path, mrc_model** out) {
+    MRC_TRY(check_ctx(ctx, "mrc_model_load"));
+    if (!path || !out) return fail(MRC_E_INVAL, "mrc_model_load: NULL argument");
+    *out = nullptr;
+    std::ifstream f(path, std::ios::binary);
+    if (!f) return fail(MRC_E_INVAL, std::string("mrc_model_load: cannot open ") + path);
+    std::vector<char> buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+    size_t pos = 0;
+    auto get = [&](void* p, size_t n) {
+        if (pos + n > buf.size()) return false;
+        memcpy(p, buf.data() + pos, n);
+        pos += n;
+        return true;
+    };
+    char magic[8];
+    uint32_t version = 0;
+    int64_t n_docs = 0, n_listed = 0, lo = 0, hi = 0;
+    int32_t vocab = 0, k = 0;
+    mrc_ref_spec spec{};
+    if (!get(magic, 8) || memcmp(magic, "MRCMODEL", 8) != 0) return fail(MRC_E_INVAL, "mrc_model_load: not a model file");
+    if (!get(&version, 4) || version != 1) return fail(MRC_E_INVAL, "mrc_model_load: unsupported version");
+    bool ok = get(&n_docs, 8) && get(&vocab, 4) && get(&spec, sizeof spec) && get(&k, 4) && get(&n_listed, 8) &&
+              get(&lo, 8) && get(&hi, 8);
+    if (!ok || vocab < 1 || vocab > (1 << 24) || k < 1 || k > 1024 || spec.k != k)
+        return fail(MRC_E_INVAL, "mrc_model_load: corrupt header");
+    const size_t V = (size_t)vocab;
+    const size_t body = V * 16 + V * sizeof(TermInfo) + (size_t)k * 16;
+    if (buf.size() != pos + body + 8) return fail(MRC_E_INVAL, "mrc_model_load: truncated file");
+    uint64_t h_stored = 0;
+    memcpy(&h_stored, buf.data() + pos + body, 8);
+    if (fnv1a(buf.data(), pos + body) != h_stored) return fail(MRC_E_INVAL, "mrc_model_load: checksum mismatch");
+    mrc_model* m = nullptr;
+    MRC_TRY(alloc_model(ctx, vocab, k, &m));
+    m->n_docs = n_docs;
+    m->spec = spec;
+    m->n_listed = n_listed;
+    m->lo = lo;
+    m->hi = hi;
+    struct Arr { void* d; size_t n; } arrs[] = {
+        {m->d_df, V * 4}, {m->d_idf, V * 4}, {m->d_term_at, V * 4}, {m->d_rank_of, V * 4},
+        {m->d_tinfo, V * sizeof(TermInfo)}, {m->d_rnorm, (size_t)k * 8}, {m->d_rinv, (size_t)k * 8}};
+    for (auto& a : arrs) {
+        hipError_t e = hipMemcpy(a.d, buf.data() + pos, a.n, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            free_model(m);
+            return hip_fail(ctx, e, "model upload", __FILE__, __LINE__);
+        }
+        pos += a.n;
+    }
+    *out = m;
+    return MRC_OK;
+}
+
+// ------------------------------------------------------------------ signing
+
+mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float* sig_out,
+                    float* norm_out, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_sign"));
+    MRC_TRY(check_docs(docs, "mrc_sign"));
+    if (!model) return fail(MRC_E_INVAL, "mrc_sign: model is NULL");
+    if (model->ctx->device != ctx->device) return fail(MRC_E_INVAL, "mrc_sign: model lives on another device");
+    if (docs->n_docs > 0 && !sig_out) return fail(MRC_E_INVAL, "mrc_sign: sig_out is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    DocBuckets b;
+    MRC_TRY(launch_classify(ctx, docs, model->vocab, &b, s));
+    MRC_TRY(launch_sign(ctx, model, docs, b, sig_out, norm_out, s));
+    return sync_flags(ctx, s, 1, "mrc_sign");
+}
+
+// ------------------------------------------------------------------ comparison
+
+mrc_status mrc_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit_out,
+                         uint16_t* bf16_out, uint8_t* fp8_out, float* scale_out, float* err_out,
+                         void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_normalise"));
+    if (n < 0 || k < 1 || k > 1024) return fail(MRC_E_INVAL, "mrc_normalise: bad n or k");
+    if (n > 0 && !sig) return fail(MRC_E_INVAL, "mrc_normalise: sig is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_TRY(launch_normalise(ctx, sig, n, k, unit_out, bf16_out, fp8_out, scale_out, err_out, s));
+    MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
+    return MRC_OK;
+}
+
+mrc_status mrc_score_pairs(mrc_ctx* ctx, const float* unit, int64_t n, int32_t k, const int32_t* ii,
+                           const int32_t* jj, int64_t n_pairs, float* out, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_score_pairs"));
+    if (n < 0 || k < 1 || n_pairs < 0) return fail(MRC_E_INVAL, "mrc_score_pairs: bad sizes");
+    if (n_pairs > 0 && (!unit || !ii || !jj || !out)) return fail(MRC_E_INVAL, "mrc_score_pairs: NULL buffer");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_TRY(launch_score_pairs(ctx, unit, k, ii, jj, n_pairs, out, s));
+    MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
+    return MRC_OK;
+}
+
+mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const mrc_compare_opts* opts,
+                       mrc_pair* pairs_out, int64_t capacity, int64_t* n_found, mrc_compare_stats* stats,
+                       void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_compare"));
+    if (!opts || !n_found) return fail(MRC_E_INVAL, "mrc_compare: NULL opts or n_found");
+    if (n < 0 || n > 0x7FFFFFFFLL || k < 1 || k > 1024) return fail(MRC_E_INVAL, "mrc_compare: bad n or k");
+    if (n > 0 && !sig) return fail(MRC_E_INVAL, "mrc_compare: sig is NULL");
+    if (capacity < 0 || (capacity > 0 && !pairs_out)) return fail(MRC_E_INVAL, "mrc_compare: bad output buffer");
+    if (!(opts->tau == opts->tau) || opts->reserved != 0) return fail(MRC_E_INVAL, "mrc_compare: bad options");
+    if (opts->precision < MRC_PREC_FP32 || opts->precision > MRC_PREC_FP8)
+        return fail(MRC_E_INVAL, "mrc_compare: bad precision");
+    if (opts->precision != MRC_PREC_FP32 && !(opts->band >= 0.f))
+        return fail(MRC_E_INVAL, "mrc_compare: band must be >= 0");
+    hipStream_t s = (hipStream_t)hip_stream;
+    *n_found = 0;
+    mrc_compare_stats st{};
+    st.n_pairs_compared = n * (n - 1) / 2;
+    void* unit = nullptr;
+    MRC_TRY(scratch(ctx, "cmp_unit", (size_t)(n > 0 ? n : 1) * k * sizeof(float), &unit));
+    unsigned long long* counter = (unsigned long long*)(ctx->d_flags + 4);
+    if (opts->precision == MRC_PREC_FP32) {
+        MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 16 * sizeof(int64_t), s));
+        MRC_TRY(launch_normalise(ctx, sig, n, k, (float*)unit, nullptr, nullptr, nullptr, nullptr, s));
+        PairSink sink{pairs_out, capacity, counter};
+        MRC_TRY(launch_compare_f32(ctx, (const float*)unit, n, k, opts->tau, sink, s));
+        MRC_TRY(sync_flags(ctx, s, 16, "mrc_compare"));
+        const int64_t found = ctx->h_flags[4];
+        *n_found = found;
+        st.n_flagged = found;
+        if (stats) *stats = st;
+        if (found > capacity) return fail(MRC_E_OVERFLOW, "mrc_compare: more pairs than capacity");
+        return MRC_OK;
+    }
+    return fail(MRC_E_STATE, "mrc_compare: low-precision forms are built in compare_lowp");
+}
+
+}  // extern "C"

@@ -1,0 +1,261 @@
+// Internal definitions shared by the HIP translation units of libmrc.
+// Host-side: context, model and database objects, scratch arena, error and
+// timing helpers. Device-side: wavefront reductions and small utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/mrc.h"
+
+namespace mrc {
+
+// ---------------------------------------------------------------- errors
+
+void set_error(const std::string& msg);
+mrc_status fail(mrc_status code, const std::string& msg);
+
+#define MRC_HIP_TRY(ctx, expr)                                                         \
+    do {                                                                               \
+        hipError_t _e = (expr);                                                        \
+        if (_e != hipSuccess) return ::mrc::hip_fail((ctx), _e, #expr, __FILE__, __LINE__); \
+    } while (0)
+
+#define MRC_TRY(expr)                    \
+    do {                                 \
+        mrc_status _s = (expr);          \
+        if (_s != MRC_OK) return _s;     \
+    } while (0)
+
+// ---------------------------------------------------------------- objects
+
+// Per-term record the signing kernels gather once per token occurrence.
+struct TermInfo {
+    float idf;     // idf_t rounded to float
+    int32_t part;  // reference part of t, -1 when t is not in the selection
+};
+
+struct KernelTimer {
+    double total_ms = 0.0;
+    int64_t launches = 0;
+};
+
+}  // namespace mrc
+
+struct mrc_ctx {
+    int device = 0;
+    size_t budget = 0;
+    size_t used = 0;             // bytes held by scratch + owned objects
+    mrc_status sticky = MRC_OK;  // a HIP failure poisons the context
+    std::map<std::string, std::pair<void*, size_t>> scratch;
+    int64_t* d_flags = nullptr;  // small device word array: counters + error flags
+    int64_t* h_flags = nullptr;  // pinned host mirror
+    bool timing = false;
+    std::map<std::string, mrc::KernelTimer> timers;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> event_pool;
+    std::mutex mu;               // guards `used` (databases may be touched by server threads)
+};
+
+struct mrc_model {
+    mrc_ctx* ctx = nullptr;
+    int64_t n_docs = 0;
+    int32_t vocab = 0;
+    mrc_ref_spec spec{};
+    int32_t k = 0;
+    int64_t n_listed = 0, lo = 0, hi = 0;
+    uint32_t* d_df = nullptr;        // [V]
+    float* d_idf = nullptr;          // [V]
+    int32_t* d_term_at = nullptr;    // [V]
+    int32_t* d_rank_of = nullptr;    // [V]
+    mrc::TermInfo* d_tinfo = nullptr;  // [V]
+    double* d_rnorm = nullptr;       // [k]
+    double* d_rinv = nullptr;        // [k]  1 / |r_j|
+    uint64_t* d_hash = nullptr;      // [V]  MD5 term hashes (built on first use)
+    size_t bytes = 0;
+};
+
+struct mrc_db {
+    mrc_ctx* ctx = nullptr;
+    int64_t capacity = 0;
+    int32_t k = 0;
+    uint32_t precisions = 0;
+    int64_t size = 0;            // committed rows
+    float* d_unit = nullptr;     // [capacity][k]
+    uint16_t* d_bf16 = nullptr;  // [capacity][k]
+    uint8_t* d_fp8 = nullptr;    // [capacity][k]
+    float* d_scale = nullptr;    // [capacity]
+    float* d_err = nullptr;      // [2][capacity]: bf16 then fp8 row error bounds
+    size_t bytes = 0;
+    std::mutex mu;
+};
+
+namespace mrc {
+
+mrc_status hip_fail(mrc_ctx* ctx, hipError_t e, const char* what, const char* file, int line);
+
+// Device allocation accounted against the context budget.
+mrc_status dev_alloc(mrc_ctx* ctx, void** p, size_t bytes);
+void dev_free(mrc_ctx* ctx, void* p, size_t bytes);
+
+// Named, grow-only scratch buffer owned by the context.
+mrc_status scratch(mrc_ctx* ctx, const char* name, size_t bytes, void** p);
+
+// Kernel timing around launches (no-ops when timing is off).
+void timer_begin(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev_pair);
+void timer_end(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev_pair);
+void timer_collect(mrc_ctx* ctx);
+
+struct ScopedTimer {
+    mrc_ctx* ctx;
+    const char* name;
+    hipStream_t s;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ScopedTimer(mrc_ctx* c, const char* n, hipStream_t st) : ctx(c), name(n), s(st) {
+        timer_begin(ctx, name, s, ev);
+    }
+    ~ScopedTimer() { timer_end(ctx, name, s, ev); }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------- stage launchers
+// Each returns MRC_OK or an error; all work is enqueued on `s`.
+
+// Document pass: validate offsets/tokens and bucket documents by length.
+struct DocBuckets {
+    int32_t* d_lists = nullptr;   // [3][n] document ids per class
+    int64_t* d_counts = nullptr;  // [3] class sizes (device)
+};
+mrc_status launch_classify(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, DocBuckets* b,
+                           hipStream_t s);
+
+// df over a corpus (atomic integer increments, one per distinct (doc, term)).
+mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, const DocBuckets& b,
+                     uint32_t* d_df, hipStream_t s);
+
+// Model tables from df: idf, stable rank sort, selection, parts, reference norms.
+mrc_status launch_model_tables(mrc_ctx* ctx, mrc_model* m, hipStream_t s);
+
+// Signatures with a frozen model. unit_out optional: also write unit signatures.
+mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs,
+                       const DocBuckets& b, float* sig_out, float* norm_out, hipStream_t s);
+
+// Normalise + quantise rows.
+mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit,
+                            uint16_t* bf16, uint8_t* fp8, float* scale, float* err,
+                            hipStream_t s);
+
+// Pair output buffer shared by the all-pairs kernels.
+struct PairSink {
+    mrc_pair* pairs;          // may be null when capacity == 0
+    int64_t capacity;
+    unsigned long long* counter;  // device: number of pairs found
+};
+
+mrc_status launch_compare_f32(mrc_ctx* ctx, const float* unit, int64_t n, int32_t k, float tau,
+                              PairSink sink, hipStream_t s);
+
+struct BandSink {
+    int32_t* ij;              // [2][capacity]
+    float* s;                 // [capacity] low-precision score
+    int64_t capacity;
+    unsigned long long* counter;
+};
+mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const void* q, const float* scale,
+                               const float* err, int64_t n, int32_t k, float tau, float band,
+                               PairSink sink, BandSink bands, hipStream_t s);
+mrc_status launch_rescore(mrc_ctx* ctx, const float* unit, int32_t k, float tau, float band,
+                          BandSink bands, int64_t n_bands, PairSink sink,
+                          unsigned long long* d_stats, hipStream_t s);
+mrc_status launch_score_pairs(mrc_ctx* ctx, const float* unit, int32_t k, const int32_t* ii,
+                              const int32_t* jj, int64_t n_pairs, float* out, hipStream_t s);
+
+// Comparators.
+mrc_status launch_term_hashes(mrc_ctx* ctx, int32_t vocab, uint64_t* out, hipStream_t s);
+mrc_status launch_simhash(mrc_ctx* ctx, const mrc_docs* docs, const uint64_t* d_hash,
+                          uint64_t* out, hipStream_t s);
+mrc_status launch_hamming(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32_t max_dist,
+                          PairSink sink, hipStream_t s);
+mrc_status launch_exact_cosine(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs,
+                               const DocBuckets& b, float tau, PairSink sink, hipStream_t s);
+
+// Query top-k against a database.
+mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t db_rows, const mrc_model* m,
+                     const mrc_docs* q, int32_t topk, float tau, int32_t precision,
+                     mrc_hit* topk_out, int32_t* n_hits, hipStream_t s);
+
+// Normalise and append unit signatures to a database.
+mrc_status db_append(mrc_db* db, const float* sig, int64_t n, int64_t first, hipStream_t s);
+
+// Sizes of the length classes the document kernels use.
+constexpr int kShortMax = 512;    // one wavefront per document, LDS hash table
+constexpr int kMediumMax = 4096;  // one 256-thread workgroup per document, LDS hash table
+constexpr int kLongBlocks = 64;   // workgroups of the long-document pass (each owns a [V] table)
+constexpr int kFp64NormMin = 10000;  // norms of longer documents accumulate in float64
+
+}  // namespace mrc
+
+// ---------------------------------------------------------------- device helpers
+
+namespace mrc_dev {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Fixed-order wavefront sum (butterfly over 64 lanes). Every lane receives
+// the same value, computed by the same tree regardless of data.
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        T o = __shfl_xor(v, off, 64);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+// Exact fixed-point form of a non-negative float c with 2^-9 <= c < 2^24:
+// c * 2^32 is then an integer below 2^56, returned as uint64. Sums of such
+// values are exact and independent of order.
+__device__ __forceinline__ unsigned long long fixed32(float c) {
+    unsigned int hi = (unsigned int)c;          // truncation, exact integer part
+    float frac = c - (float)hi;                 // exact (same binade or below)
+    unsigned int lo = (unsigned int)(frac * 4294967296.0f);  // exact: power-of-two scale
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+__device__ __forceinline__ double unfixed32(unsigned long long v) {
+    return (double)v * 2.3283064365386963e-10;  // 2^-32
+}
+
+// Reserve `mine` consecutive output slots per lane with one atomic per
+// wavefront. Returns this lane's first slot. All 64 lanes must call it.
+__device__ __forceinline__ int64_t wave_reserve(unsigned long long* counter, int mine) {
+    const int lane = __lane_id();
+    int incl = mine;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int t = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += t;
+    }
+    const int total = __shfl(incl, 63, 64);
+    unsigned long long base = 0;
+    if (total > 0 && lane == 63) base = atomicAdd(counter, (unsigned long long)total);
+    base = __shfl(base, 63, 64);
+    return (int64_t)base + incl - mine;
+}
+
+}  // namespace mrc_dev

@@ -1,0 +1,377 @@
+// Per-document passes over the token CSR: length classification, document
+// frequency (model build) and MRC signing (Section 4: cosine of the TF-IDF
+// vector of a document against each of the k reference parts).
+//
+// Every pass turns a document's token stream into term counts with a hash
+// table: in LDS for documents up to kMediumMax tokens (one wavefront per
+// short document, one 256-thread workgroup per medium document), and in a
+// per-workgroup [V] count array in global memory for longer documents.
+//
+// Signing needs, per document d and part j,
+//   num_j = sum over occurrences p with part(t_p) = j of c_p,  c_p = idf_t * rho_t,
+//   |w_d|^2 = sum over occurrences p of tf(t_p) * idf(t_p)^2,
+// and sig_dj = num_j / (|w_d| |r_j|). num_j is accumulated in exact 64-bit
+// fixed point (c_p * 2^32 is an integer for the weights that occur), so it is
+// exact and independent of order; the norm sums in a fixed per-document order
+// (float32, float64 for documents longer than 10^4 tokens). A document's result
+// therefore depends only on its own tokens, never on the batch around it.
+#include "common.h"
+
+using namespace mrc;
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kEmpty = -1;
+
+enum : unsigned long long {
+    kErrOffsets = 1ull,
+    kErrToken = 2ull,
+};
+
+__device__ __forceinline__ int hash_slot(int t, int log2_slots) {
+    return (int)(((unsigned)t * 0x9E3779B1u) >> (32 - log2_slots));
+}
+
+template <int TEAM>
+__device__ __forceinline__ void team_sync() {
+    if constexpr (TEAM == 64) {
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    } else {
+        __syncthreads();
+    }
+}
+
+// Fixed-order sum over a team (one wavefront, or the 4 wavefronts of a block).
+template <int TEAM, typename T>
+__device__ __forceinline__ T team_sum(T v, T* red) {
+    v = mrc_dev::wave_sum(v);
+    if constexpr (TEAM == 64) {
+        return v;
+    } else {
+        const int w = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0) red[w] = v;
+        __syncthreads();
+        T r = red[0];
+#pragma unroll
+        for (int i = 1; i < TEAM / 64; ++i) r += red[i];
+        __syncthreads();
+        return r;
+    }
+}
+
+struct SignArgs {
+    const TermInfo* tinfo;
+    const double* rinv;
+    int k;
+    int ref_idf;       // 1: rho_t = idf_t, so c_p = idf^2
+    float* sig;
+    float* norm;
+};
+
+enum { MODE_DF = 0, MODE_SIGN = 1 };
+
+__global__ void k_classify(const int64_t* __restrict__ off, int64_t n, int32_t* __restrict__ lists,
+                           unsigned long long* __restrict__ counts,
+                           unsigned long long* __restrict__ err) {
+    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    if (d == 0 && off[0] != 0) atomicOr(err, kErrOffsets);
+    int64_t L = off[d + 1] - off[d];
+    if (L < 0) {
+        atomicOr(err, kErrOffsets);
+        return;
+    }
+    int c = L <= kShortMax ? 0 : (L <= kMediumMax ? 1 : 2);
+    unsigned long long idx = atomicAdd(&counts[c], 1ull);
+    lists[(int64_t)c * n + (int64_t)idx] = (int32_t)d;
+}
+
+// LDS layout of one team: bins u64[kpad] | keys i32[SLOTS] | cnt i32[SLOTS] |
+// used u16[SLOTS/2] | nused i32 | red (double[4])
+__host__ __device__ constexpr size_t team_lds_bytes(int kpad, int slots) {
+    return (size_t)kpad * 8 + (size_t)slots * 8 + (size_t)slots + 16 + 32;
+}
+
+template <int MODE, int TEAM, int LOG2_SLOTS, int MAXPER>
+__global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ off,
+                                                    const int32_t* __restrict__ tok,
+                                                    const int32_t* __restrict__ list,
+                                                    const unsigned long long* __restrict__ count_ptr,
+                                                    int32_t V, uint32_t* __restrict__ df,
+                                                    SignArgs sa, unsigned long long* __restrict__ err) {
+    constexpr int SLOTS = 1 << LOG2_SLOTS;
+    constexpr int TEAMS = kBlock / TEAM;
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
+    const size_t tbytes = team_lds_bytes(kpad, SLOTS);
+    const int team = threadIdx.x / TEAM;
+    const int tid = threadIdx.x % TEAM;
+    unsigned char* base = smem + (size_t)team * tbytes;
+    unsigned long long* bins = (unsigned long long*)base;
+    int* keys = (int*)(base + (size_t)kpad * 8);
+    int* cnt = keys + SLOTS;
+    unsigned short* used = (unsigned short*)(cnt + SLOTS);
+    int* nused = (int*)(used + SLOTS / 2);
+    double* red = (double*)(base + tbytes - 32);
+
+    for (int s = tid; s < SLOTS; s += TEAM) {
+        keys[s] = kEmpty;
+        cnt[s] = 0;
+    }
+    for (int j = tid; j < kpad; j += TEAM) bins[j] = 0ull;
+    if (tid == 0) *nused = 0;
+    team_sync<TEAM>();
+
+    const int64_t n_items = (int64_t)*count_ptr;
+    for (int64_t i = (int64_t)blockIdx.x * TEAMS + team; i < n_items; i += (int64_t)gridDim.x * TEAMS) {
+        const int d = list[i];
+        const int64_t o = off[d];
+        const int L = (int)(off[d + 1] - o);
+        int slot_r[MAXPER];
+        float idf_r[MAXPER];
+#pragma unroll
+        for (int r = 0; r < MAXPER; ++r) {
+            slot_r[r] = -1;
+            idf_r[r] = 0.f;
+            const int p = tid + r * TEAM;
+            if (p < L) {
+                const int t = tok[o + p];
+                if ((unsigned)t >= (unsigned)V) {
+                    atomicOr(err, kErrToken);
+                    continue;
+                }
+                int h = hash_slot(t, LOG2_SLOTS);
+                bool won = false;
+                while (true) {
+                    int prev = atomicCAS(&keys[h], kEmpty, t);
+                    if (prev == kEmpty) {
+                        won = true;
+                        break;
+                    }
+                    if (prev == t) break;
+                    h = (h + 1) & (SLOTS - 1);
+                }
+                int old = atomicAdd(&cnt[h], 1);
+                if (won) used[atomicAdd(nused, 1)] = (unsigned short)h;
+                if constexpr (MODE == MODE_DF) {
+                    if (old == 0) atomicAdd(&df[t], 1u);
+                } else {
+                    (void)old;
+                    TermInfo ti = sa.tinfo[t];
+                    slot_r[r] = h;
+                    idf_r[r] = ti.idf;
+                    if (ti.part >= 0) {
+                        float c = sa.ref_idf ? ti.idf * ti.idf : ti.idf;
+                        atomicAdd(&bins[ti.part], mrc_dev::fixed32(c));
+                    }
+                }
+            }
+        }
+        team_sync<TEAM>();
+        if constexpr (MODE == MODE_SIGN) {
+            float nacc = 0.f;
+#pragma unroll
+            for (int r = 0; r < MAXPER; ++r) {
+                if (slot_r[r] >= 0) nacc += (float)cnt[slot_r[r]] * (idf_r[r] * idf_r[r]);
+            }
+            float n2 = team_sum<TEAM, float>(nacc, (float*)red);
+            double nrm = (double)sqrtf(n2);
+            float* out = sa.sig + (int64_t)d * sa.k;
+            for (int j = tid; j < sa.k; j += TEAM) {
+                double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
+                out[j] = (float)v;
+            }
+            if (tid == 0 && sa.norm) sa.norm[d] = (float)nrm;
+        }
+        team_sync<TEAM>();
+        const int nu = *nused;
+        for (int u = tid; u < nu; u += TEAM) {
+            const int s = used[u];
+            keys[s] = kEmpty;
+            cnt[s] = 0;
+        }
+        for (int j = tid; j < kpad; j += TEAM) bins[j] = 0ull;
+        team_sync<TEAM>();
+        if (tid == 0) *nused = 0;
+        team_sync<TEAM>();
+    }
+}
+
+// Long documents: a [V] uint32 count table per workgroup in global memory
+// (all zero between documents).
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off,
+                                                       const int32_t* __restrict__ tok,
+                                                       const int32_t* __restrict__ list,
+                                                       const unsigned long long* __restrict__ count_ptr,
+                                                       int32_t V, uint32_t* __restrict__ df,
+                                                       SignArgs sa, uint32_t* __restrict__ tables,
+                                                       unsigned long long* __restrict__ err) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    unsigned long long* bins = (unsigned long long*)smem;
+    const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
+    double* red = (double*)(smem + (size_t)kpad * 8);
+    uint32_t* cnt = tables + (size_t)blockIdx.x * (size_t)V;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
+    __syncthreads();
+    const int64_t n_items = (int64_t)*count_ptr;
+    for (int64_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+        const int d = list[i];
+        const int64_t o = off[d];
+        const int64_t L = off[d + 1] - o;
+        for (int64_t p = tid; p < L; p += kBlock) {
+            const int t = tok[o + p];
+            if ((unsigned)t >= (unsigned)V) {
+                atomicOr(err, kErrToken);
+                continue;
+            }
+            unsigned old = atomicAdd(&cnt[t], 1u);
+            if constexpr (MODE == MODE_DF) {
+                if (old == 0) atomicAdd(&df[t], 1u);
+            } else {
+                (void)old;
+                TermInfo ti = sa.tinfo[t];
+                if (ti.part >= 0) {
+                    float c = sa.ref_idf ? ti.idf * ti.idf : ti.idf;
+                    atomicAdd(&bins[ti.part], mrc_dev::fixed32(c));
+                }
+            }
+        }
+        __threadfence();
+        __syncthreads();
+        if constexpr (MODE == MODE_SIGN) {
+            double nrm;
+            if (L > kFp64NormMin) {
+                double acc = 0.0;
+                for (int64_t p = tid; p < L; p += kBlock) {
+                    const int t = tok[o + p];
+                    if ((unsigned)t >= (unsigned)V) continue;
+                    unsigned tf = __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    double idf = (double)sa.tinfo[t].idf;
+                    acc += (double)tf * idf * idf;
+                }
+                nrm = sqrt(team_sum<kBlock, double>(acc, red));
+            } else {
+                float acc = 0.f;
+                for (int64_t p = tid; p < L; p += kBlock) {
+                    const int t = tok[o + p];
+                    if ((unsigned)t >= (unsigned)V) continue;
+                    unsigned tf = __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    float idf = sa.tinfo[t].idf;
+                    acc += (float)tf * (idf * idf);
+                }
+                nrm = (double)sqrtf(team_sum<kBlock, float>(acc, (float*)red));
+            }
+            float* out = sa.sig + (int64_t)d * sa.k;
+            for (int j = tid; j < sa.k; j += kBlock) {
+                double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
+                out[j] = (float)v;
+            }
+            if (tid == 0 && sa.norm) sa.norm[d] = (float)nrm;
+        }
+        __syncthreads();
+        for (int64_t p = tid; p < L; p += kBlock) {
+            const int t = tok[o + p];
+            if ((unsigned)t >= (unsigned)V) continue;
+            __hip_atomic_store(&cnt[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
+        __threadfence();
+        __syncthreads();
+    }
+}
+
+constexpr int kShortTeam = 64, kShortLog2 = 10, kShortPer = kShortMax / 64;      // 1024 slots
+constexpr int kMedTeam = 256, kMedLog2 = 13, kMedPer = kMediumMax / 256;         // 8192 slots
+static_assert((1 << kShortLog2) >= 2 * kShortMax, "short table load factor");
+static_assert((1 << kMedLog2) >= 2 * kMediumMax, "medium table load factor");
+
+int grid_for(int64_t n_items_upper, int teams_per_block, int cap) {
+    int64_t g = ceil_div(n_items_upper, teams_per_block);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (int)g;
+}
+
+template <int MODE>
+mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const DocBuckets& b,
+                       uint32_t* df, const SignArgs& sa, hipStream_t s, const char* name) {
+    const int64_t n = docs->n_docs;
+    if (n == 0) return MRC_OK;
+    unsigned long long* err = (unsigned long long*)ctx->d_flags;
+    const unsigned long long* counts = (const unsigned long long*)b.d_counts;
+    const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
+    ScopedTimer tm(ctx, name, s);
+    {
+        size_t lds = team_lds_bytes(kpad, 1 << kShortLog2) * (kBlock / kShortTeam);
+        int grid = grid_for(n, kBlock / kShortTeam, 256 * 16);
+        hipLaunchKernelGGL((k_doc_lds<MODE, kShortTeam, kShortLog2, kShortPer>), dim3(grid), dim3(kBlock),
+                           lds, s, docs->offsets, docs->tokens, b.d_lists, counts, V, df, sa, err);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+    }
+    {
+        size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
+        int grid = grid_for(n, 1, 256 * 2);
+        hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid), dim3(kBlock), lds, s,
+                           docs->offsets, docs->tokens, b.d_lists + n, counts + 1, V, df, sa, err);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+    }
+    {
+        const size_t table_bytes = (size_t)kLongBlocks * (size_t)V * sizeof(uint32_t);
+        auto it = ctx->scratch.find("long_tables");
+        bool fresh = it == ctx->scratch.end() || it->second.second < table_bytes;
+        void* tables = nullptr;
+        MRC_TRY(scratch(ctx, "long_tables", table_bytes, &tables));
+        if (fresh) MRC_HIP_TRY(ctx, hipMemsetAsync(tables, 0, ctx->scratch["long_tables"].second, s));
+        size_t lds = (size_t)kpad * 8 + 32;
+        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets,
+                           docs->tokens, b.d_lists + 2 * n, counts + 2, V, df, sa, (uint32_t*)tables, err);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+    }
+    return MRC_OK;
+}
+
+}  // namespace
+
+namespace mrc {
+
+mrc_status launch_classify(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, DocBuckets* b,
+                           hipStream_t s) {
+    (void)vocab;
+    const int64_t n = docs->n_docs;
+    void* lists = nullptr;
+    MRC_TRY(scratch(ctx, "class_lists", (size_t)(3 * (n > 0 ? n : 1)) * sizeof(int32_t), &lists));
+    b->d_lists = (int32_t*)lists;
+    b->d_counts = ctx->d_flags + 1;
+    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(int64_t), s));
+    if (n == 0) return MRC_OK;
+    ScopedTimer tm(ctx, "classify", s);
+    hipLaunchKernelGGL(k_classify, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, docs->offsets, n,
+                       b->d_lists, (unsigned long long*)b->d_counts, (unsigned long long*)ctx->d_flags);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, const DocBuckets& b,
+                     uint32_t* d_df, hipStream_t s) {
+    SignArgs sa{};
+    return run_docpass<MODE_DF>(ctx, docs, vocab, b, d_df, sa, s, "df");
+}
+
+mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const DocBuckets& b,
+                       float* sig_out, float* norm_out, hipStream_t s) {
+    SignArgs sa{};
+    sa.tinfo = m->d_tinfo;
+    sa.rinv = m->d_rinv;
+    sa.k = m->k;
+    sa.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
+    sa.sig = sig_out;
+    sa.norm = norm_out;
+    return run_docpass<MODE_SIGN>(ctx, docs, m->vocab, b, nullptr, sa, s, "sign");
+}
+
+}  // namespace mrc

@@ -1,0 +1,197 @@
+// Host runtime of libmrc: thread-local errors, budgeted device allocation,
+// named scratch buffers, and per-kernel HIP-event timing.
+#include <cstdio>
+
+#include "common.h"
+
+namespace mrc {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+mrc_status fail(mrc_status code, const std::string& msg) {
+    set_error(msg);
+    return code;
+}
+
+mrc_status hip_fail(mrc_ctx* ctx, hipError_t e, const char* what, const char* file, int line) {
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s at %s:%d", (int)e, hipGetErrorString(e),
+             what, file, line);
+    set_error(buf);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return MRC_E_NOMEM;
+    if (ctx) ctx->sticky = MRC_E_HIP;
+    return MRC_E_HIP;
+}
+
+mrc_status dev_alloc(mrc_ctx* ctx, void** p, size_t bytes) {
+    *p = nullptr;
+    if (bytes == 0) return MRC_OK;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        if (ctx->used + bytes > ctx->budget)
+            return fail(MRC_E_NOMEM, "device allocation of " + std::to_string(bytes) +
+                                         " bytes would exceed the context budget");
+        ctx->used += bytes;
+    }
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->used -= bytes;
+        *p = nullptr;
+        return fail(MRC_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    return MRC_OK;
+}
+
+void dev_free(mrc_ctx* ctx, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->used -= bytes;
+}
+
+mrc_status scratch(mrc_ctx* ctx, const char* name, size_t bytes, void** p) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    auto it = ctx->scratch.find(name);
+    if (it != ctx->scratch.end() && it->second.second >= bytes) {
+        *p = it->second.first;
+        return MRC_OK;
+    }
+    if (it != ctx->scratch.end()) {
+        // grow: the old buffer may still be in use by queued work
+        MRC_HIP_TRY(ctx, hipDeviceSynchronize());
+        dev_free(ctx, it->second.first, it->second.second);
+        ctx->scratch.erase(it);
+    }
+    size_t want = bytes + bytes / 4;  // headroom against repeated growth
+    void* q = nullptr;
+    mrc_status st = dev_alloc(ctx, &q, want);
+    if (st != MRC_OK) {
+        st = dev_alloc(ctx, &q, bytes);
+        if (st != MRC_OK) return st;
+        want = bytes;
+    }
+    ctx->scratch[name] = {q, want};
+    *p = q;
+    return MRC_OK;
+}
+
+static hipEvent_t take_event(mrc_ctx* ctx) {
+    if (!ctx->event_pool.empty()) {
+        hipEvent_t e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void timer_begin(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev) {
+    (void)name;
+    if (!ctx || !ctx->timing) return;
+    ev[0] = take_event(ctx);
+    ev[1] = take_event(ctx);
+    if (ev[0]) (void)hipEventRecord(ev[0], s);
+}
+
+void timer_end(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev) {
+    if (!ctx || !ctx->timing || !ev[0] || !ev[1]) return;
+    (void)hipEventRecord(ev[1], s);
+    ctx->pending.push_back({name, {ev[0], ev[1]}});
+}
+
+void timer_collect(mrc_ctx* ctx) {
+    for (auto& p : ctx->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            auto& t = ctx->timers[p.first];
+            t.total_ms += ms;
+            t.launches += 1;
+        }
+        ctx->event_pool.push_back(p.second.first);
+        ctx->event_pool.push_back(p.second.second);
+    }
+    ctx->pending.clear();
+}
+
+}  // namespace mrc
+
+using namespace mrc;
+
+extern "C" {
+
+const char* mrc_last_error(void) { return g_last_error.c_str(); }
+
+mrc_status mrc_ctx_create(mrc_ctx** out, int32_t device, size_t hbm_budget_bytes) {
+    if (!out) return fail(MRC_E_INVAL, "mrc_ctx_create: out is NULL");
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0)
+        return fail(MRC_E_HIP, "mrc_ctx_create: no HIP device");
+    if (device < 0 || device >= n) return fail(MRC_E_INVAL, "mrc_ctx_create: bad device index");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice", __FILE__, __LINE__);
+    size_t free_b = 0, total_b = 0;
+    e = hipMemGetInfo(&free_b, &total_b);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipMemGetInfo", __FILE__, __LINE__);
+    mrc_ctx* ctx = new mrc_ctx();
+    ctx->device = device;
+    ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (size_t)(0.8 * (double)total_b);
+    e = hipMalloc((void**)&ctx->d_flags, 64 * sizeof(int64_t));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_flags, 64 * sizeof(int64_t), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, 64 * sizeof(int64_t));
+    if (e != hipSuccess) {
+        mrc_status st = hip_fail(nullptr, e, "context flags", __FILE__, __LINE__);
+        if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+        if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+        delete ctx;
+        return st;
+    }
+    *out = ctx;
+    return MRC_OK;
+}
+
+mrc_status mrc_ctx_destroy(mrc_ctx* ctx) {
+    if (!ctx) return MRC_OK;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    timer_collect(ctx);
+    for (auto& kv : ctx->scratch) (void)hipFree(kv.second.first);
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    delete ctx;
+    return MRC_OK;
+}
+
+mrc_status mrc_ctx_memory(const mrc_ctx* ctx, size_t* used, size_t* budget) {
+    if (!ctx) return fail(MRC_E_INVAL, "mrc_ctx_memory: ctx is NULL");
+    if (used) *used = ctx->used;
+    if (budget) *budget = ctx->budget;
+    return MRC_OK;
+}
+
+mrc_status mrc_ctx_set_timing(mrc_ctx* ctx, int32_t enabled) {
+    if (!ctx) return fail(MRC_E_INVAL, "mrc_ctx_set_timing: ctx is NULL");
+    timer_collect(ctx);
+    ctx->timing = enabled != 0;
+    return MRC_OK;
+}
+
+mrc_status mrc_ctx_kernel_time(mrc_ctx* ctx, const char* kernel, double* total_ms,
+                               int64_t* launches, int32_t reset) {
+    if (!ctx || !kernel) return fail(MRC_E_INVAL, "mrc_ctx_kernel_time: NULL argument");
+    timer_collect(ctx);
+    auto it = ctx->timers.find(kernel);
+    if (total_ms) *total_ms = it == ctx->timers.end() ? 0.0 : it->second.total_ms;
+    if (launches) *launches = it == ctx->timers.end() ? 0 : it->second.launches;
+    if (reset && it != ctx->timers.end()) ctx->timers.erase(it);
+    return MRC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+"""GPU parity of the all-pairs signature comparison.
+
+FP32 plain path: every score is the fixed float32 multiply-add chain over the
+unit signatures, so the GPU's flagged set must equal, pair for pair, the set
+the oracle's C chain flags on the same unit signatures, with bit-identical
+scores. Against the float64 oracle the decisions agree except for pairs whose
+float64 score lies within DEC_TOL of tau (counted, not failed)."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from oracle import mrc as om
+from synth import corpus as synth
+from tests.gpu_util import device_docs, flush, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+DEC_TOL = 1e-4
+TAU = 0.9
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.mrc_ctx_create(0)
+
+
+def _signed(lib, ctx, cfg, n_docs, k):
+    c = synth.generate(cfg, n_docs=n_docs)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(k))
+    sig = lib.mrc_sign(ctx, gm, o, t)
+    return c, sig
+
+
+def all_pairs_score32(unit):
+    """Every pair i < j through the oracle's C chain (small n only)."""
+    n = unit.shape[0]
+    iu, ju = np.triu_indices(n, 1)
+    return iu, ju, om.score32_pairs(unit, iu, ju)
+
+
+@pytest.mark.parametrize("cfg,n_docs,k", [(0, None, 16), (1, 3000, 64), (1, 1000, 64), (2, 600, 256)])
+def test_fp32_decisions_equal_the_chain_and_the_oracle(lib, ctx, cfg, n_docs, k):
+    c, sig = _signed(lib, ctx, cfg, n_docs, k)
+    n = c.n_docs
+    flush(f"  compare fp32 n={n} k={k}")
+    pairs, stats = lib.mrc_compare(ctx, sig, TAU, lib.PREC_FP32)
+    gi, gj, gs, gf = lib.pairs_to_numpy(pairs)
+    assert stats["n_flagged"] == gi.size and stats["n_pairs_compared"] == n * (n - 1) // 2
+    assert np.all(gi < gj)
+    unit = lib.mrc_normalise(ctx, sig)["unit"].cpu().numpy()
+    iu, ju, s32 = all_pairs_score32(unit)
+    want = s32 >= np.float32(TAU)
+    got = set(zip(gi.tolist(), gj.tolist()))
+    assert got == set(zip(iu[want].tolist(), ju[want].tolist()))
+    # bit-identical scores
+    order = np.lexsort((gj, gi))
+    ref = om.score32_pairs(unit, gi[order], gj[order])
+    np.testing.assert_array_equal(gs[order].view(np.uint32), ref.view(np.uint32))
+    # against the float64 oracle
+    osig = om.sign(c.offsets, c.tokens, om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=k)))[0]
+    shat = om.normalise(osig)
+    s64 = np.einsum("pc,pc->p", shat[iu], shat[ju])
+    assert np.abs(s32.astype(np.float64) - s64).max() <= DEC_TOL
+    far = np.abs(s64 - TAU) > DEC_TOL
+    assert np.array_equal(want[far], (s64 >= TAU)[far])
+    flush(f"    flagged={gi.size} near-ties excluded={int((~far).sum())}")
+
+
+def test_fp32_overflow_protocol_and_tiny_inputs(lib, ctx):
+    import torch
+    c, sig = _signed(lib, ctx, 0, None, 16)
+    pairs, _ = lib.mrc_compare(ctx, sig, TAU)
+    total = pairs.shape[0]
+    assert total > 10
+    # explicit small capacity: the C call reports OVERFLOW with the exact count
+    buf = torch.empty((5, 4), dtype=torch.int32, device="cuda")
+    n = ctypes.c_int64()
+    opts = lib.MrcCompareOpts(TAU, lib.PREC_FP32, 0.02, 0)
+    st = lib.lib().mrc_compare(ctx, ctypes.c_void_p(sig.data_ptr()), sig.shape[0], sig.shape[1], ctypes.byref(opts),
+                               ctypes.c_void_p(buf.data_ptr()), 5, ctypes.byref(n), None,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == lib.MRC_E_OVERFLOW and n.value == total
+    for m in (0, 1, 2, 3, 129):
+        p, s = lib.mrc_compare(ctx, sig[:m].contiguous(), TAU)
+        want = {(i, j) for i, j in zip(*lib.pairs_to_numpy(pairs)[:2]) if j < m}
+        assert set(zip(*lib.pairs_to_numpy(p)[:2])) == want
+    # zero signatures never pair; identical rows score 1
+    z = torch.zeros((4, 16), device="cuda")
+    z[2] = sig[0]
+    z[3] = sig[0] * 3.0
+    p, _ = lib.mrc_compare(ctx, z, TAU)
+    assert set(zip(*lib.pairs_to_numpy(p)[:2])) == {(2, 3)}
+
+
+def test_score_pairs_matches_chain(lib, ctx):
+    import torch
+    c, sig = _signed(lib, ctx, 1, 500, 64)
+    unit = lib.mrc_normalise(ctx, sig)["unit"]
+    rng = np.random.default_rng(0)
+    ii = rng.integers(0, 500, 10_000).astype(np.int32)
+    jj = rng.integers(0, 500, 10_000).astype(np.int32)
+    out = lib.mrc_score_pairs(ctx, unit, torch.from_numpy(ii).cuda(), torch.from_numpy(jj).cuda()).cpu().numpy()
+    ref = om.score32_pairs(unit.cpu().numpy(), ii, jj)
+    np.testing.assert_array_equal(out.view(np.uint32), ref.view(np.uint32))
+
+
+def test_quantisers_match_oracle(lib, ctx):
+    c, sig = _signed(lib, ctx, 2, 800, 256)
+    q = lib.mrc_normalise(ctx, sig, unit=True, bf16=True, fp8=True, err=True)
+    unit = q["unit"].cpu().numpy()
+    osig = om.sign(c.offsets, c.tokens, om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=256)))[0]
+    assert np.abs(unit - om.normalise(osig)).max() <= 1e-5
+    np.testing.assert_array_equal(q["bf16"].cpu().numpy().view(np.uint16), om.bf16_codes(unit))
+    codes, scale = om.fp8_quantise_rows(unit)
+    np.testing.assert_array_equal(q["scale"].cpu().numpy(), scale)
+    np.testing.assert_array_equal(q["fp8"].cpu().numpy(), codes)
+    err = q["err"].cpu().numpy()
+    eb = om.row_quant_error(unit, om.bf16_value(om.bf16_codes(unit)))
+    e8 = om.row_quant_error(unit, om.fp8_dequantise_rows(codes, scale))
+    assert np.all(err[0] >= eb) and np.all(err[0] <= eb * (1 + 1e-6) + 1e-30)
+    assert np.all(err[1] >= e8) and np.all(err[1] <= e8 * (1 + 1e-6) + 1e-30)

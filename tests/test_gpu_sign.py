@@ -1,0 +1,165 @@
+"""GPU parity of the model build and signing against the CPU oracle.
+
+Integers (df, the sorted list, parts) bit-exact; idf bit-exact against the
+oracle's float64 idf rounded to float32; signatures within 1e-5 absolute of the
+float64 oracle (the stated tolerance for FP32 signatures)."""
+import numpy as np
+import pytest
+
+from oracle import mrc as om
+from synth import corpus as synth
+from tests.gpu_util import device_docs, flush, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+SIG_TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.mrc_ctx_create(0)
+
+
+def _spec_pair(lib, k, mode=om.SEL_DROP_TOP, **kw):
+    o = om.RefSpec(k=k, mode=mode, **kw)
+    g = lib.ref_spec(k, mode=mode, lo=o.lo, hi=o.hi, m=o.m, drop_top_ppm=o.drop_top_ppm,
+                     idf_mode=o.idf_mode, ref_weight=o.ref_weight)
+    return o, g
+
+
+def _check_model(lib, gm, om_model, vocab):
+    got = lib.mrc_model_get(gm)
+    np.testing.assert_array_equal(got["df"].astype(np.int64), om_model.df)
+    Vp = om_model.order.size
+    assert got["n_listed"] == Vp
+    assert (got["lo"], got["hi"]) == (om_model.lo, om_model.hi)
+    np.testing.assert_array_equal(got["term_at"][:Vp], om_model.order)
+    tail = np.sort(np.nonzero(om_model.df == 0)[0])
+    np.testing.assert_array_equal(got["term_at"][Vp:], tail)            # df = 0 terms, ascending id
+    np.testing.assert_array_equal(got["rank_of"][got["term_at"]], np.arange(vocab))
+    np.testing.assert_array_equal(got["part_of"], om_model.part_of)
+    np.testing.assert_array_equal(got["idf"], om_model.idf.astype(np.float32))
+    np.testing.assert_allclose(got["rnorm"], om_model.rnorm, rtol=1e-6)
+
+
+def _run(lib, ctx, c, k, mode=om.SEL_DROP_TOP, **kw):
+    ospec, gspec = _spec_pair(lib, k, mode, **kw)
+    o, t = device_docs(c)
+    flush(f"  build+sign n={c.n_docs} V={c.vocab} k={k} mode={mode} {kw}")
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    sig, norm = lib.mrc_sign(ctx, gm, o, t, with_norm=True)
+    omodel = om.build_model(c.offsets, c.tokens, c.vocab, ospec)
+    osig, onorm = om.sign(c.offsets, c.tokens, omodel)
+    return gm, omodel, sig.cpu().numpy(), norm.cpu().numpy(), osig, onorm
+
+
+@pytest.mark.parametrize("cfg,n_docs,k", [(0, None, 16), (1, 3000, 64), (2, 1500, 256)])
+def test_build_and_sign_match_oracle(lib, ctx, cfg, n_docs, k):
+    c = synth.generate(cfg, n_docs=n_docs)
+    gm, omodel, sig, norm, osig, onorm = _run(lib, ctx, c, k)
+    _check_model(lib, gm, omodel, c.vocab)
+    assert np.abs(sig - osig).max() <= SIG_TOL
+    np.testing.assert_allclose(norm, onorm, rtol=2e-6)
+
+
+@pytest.mark.parametrize("mode,kw", [
+    (om.SEL_ALL, {}),
+    (om.SEL_REGION, {"lo": 100, "hi": 2100}),
+    (om.SEL_RAREST, {"m": 1500}),
+    (om.SEL_DROP_TOP, {"idf_mode": om.IDF_NONE}),
+    (om.SEL_DROP_TOP, {"ref_weight": om.REF_IDF}),
+])
+def test_reference_modes(lib, ctx, mode, kw):
+    c = synth.generate(0, n_docs=700)
+    gm, omodel, sig, norm, osig, onorm = _run(lib, ctx, c, 30, mode, **kw)
+    _check_model(lib, gm, omodel, c.vocab)
+    assert np.abs(sig - osig).max() <= SIG_TOL
+
+
+def test_edge_documents(lib, ctx):
+    """Empty documents, one-token documents, the largest id, documents in every
+    length class (LDS wavefront / LDS workgroup / global table) and past 10^4
+    tokens (float64 norm), 50,000 repeats of one id."""
+    rng = np.random.default_rng(4)
+    V = 4096
+    docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
+    for L in (1, 63, 64, 65, 511, 512, 513, 4095, 4096, 4097, 9999, 10001, 30000):
+        docs.append(rng.zipf(1.3, L).astype(np.int64) % V)
+    docs.append(np.full(50_000, 7, np.int32))
+    docs.append(np.arange(V, dtype=np.int32))
+    docs += [rng.integers(0, V, int(rng.integers(0, 300))) for _ in range(200)]
+    c = synth.from_docs(docs, V)
+    gm, omodel, sig, norm, osig, onorm = _run(lib, ctx, c, 8, om.SEL_ALL)
+    _check_model(lib, gm, omodel, V)
+    assert np.abs(sig - osig).max() <= SIG_TOL
+    np.testing.assert_allclose(norm, onorm, rtol=2e-6)
+    assert np.all(sig[0] == 0) and norm[0] == 0
+
+
+def test_sign_is_deterministic_and_batch_independent(lib, ctx):
+    c = synth.generate(1, n_docs=2000)
+    _, gspec = _spec_pair(lib, 64)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    a = lib.mrc_sign(ctx, gm, o, t).cpu().numpy()
+    b = lib.mrc_sign(ctx, gm, o, t).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    rng = np.random.default_rng(1)
+    perm = rng.permutation(c.n_docs)[:500]
+    sub = c.subset(perm)
+    o2, t2 = device_docs(sub)
+    s2 = lib.mrc_sign(ctx, gm, o2, t2).cpu().numpy()
+    np.testing.assert_array_equal(s2, a[perm])          # alone vs in a different mix
+    one = c.subset([perm[0]])
+    o3, t3 = device_docs(one)
+    np.testing.assert_array_equal(lib.mrc_sign(ctx, gm, o3, t3).cpu().numpy()[0], a[perm[0]])
+
+
+def test_invalid_inputs_raise(lib, ctx):
+    import torch
+    c = synth.generate(0, n_docs=50)
+    _, gspec = _spec_pair(lib, 16)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    bad = t.clone()
+    bad[5] = c.vocab
+    with pytest.raises(lib.MrcError) as e:
+        lib.mrc_sign(ctx, gm, o, bad)
+    assert e.value.status == lib.MRC_E_INVAL
+    bad[5] = -3
+    with pytest.raises(lib.MrcError):
+        lib.mrc_build_vocab_idf(ctx, o, bad, c.vocab, gspec)
+    boff = o.clone()
+    boff[3] = boff[4] + 1          # decreasing offsets
+    with pytest.raises(lib.MrcError):
+        lib.mrc_sign(ctx, gm, boff, t)
+    with pytest.raises(lib.MrcError):                     # more parts than selected terms
+        lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(16, mode=lib.SEL_RAREST, m=10))
+    # the context stays usable after input errors
+    sig = lib.mrc_sign(ctx, gm, o, t)
+    assert torch.isfinite(sig).all()
+
+
+def test_model_save_load_roundtrip(lib, ctx, tmp_path):
+    c = synth.generate(0, n_docs=300)
+    _, gspec = _spec_pair(lib, 16)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    p = tmp_path / "m.bin"
+    lib.mrc_model_save(gm, p)
+    gm2 = lib.mrc_model_load(ctx, p)
+    a, b = lib.mrc_model_get(gm), lib.mrc_model_get(gm2)
+    for key in ("df", "idf", "term_at", "rank_of", "part_of", "rnorm"):
+        np.testing.assert_array_equal(a[key], b[key])
+    np.testing.assert_array_equal(lib.mrc_sign(ctx, gm, o, t).cpu().numpy(),
+                                  lib.mrc_sign(ctx, gm2, o, t).cpu().numpy())
+    raw = bytearray(p.read_bytes())
+    raw[100] ^= 1
+    p.write_bytes(bytes(raw))
+    with pytest.raises(lib.MrcError):
+        lib.mrc_model_load(ctx, p)
