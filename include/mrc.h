@@ -75,11 +75,14 @@ typedef struct mrc_server mrc_server;
 
 /* A batch of documents as a token CSR: document d owns
  * tokens[offsets[d] .. offsets[d+1]). offsets: device int64 [n_docs + 1],
- * offsets[0] = 0, non-decreasing. tokens: device int32 term ids. */
+ * offsets[0] = 0, non-decreasing, offsets[n_docs] <= n_tokens. tokens: device
+ * int32 term ids, n_tokens entries readable. Offsets are validated on the
+ * device before any token is read (MRC_E_INVAL when malformed). */
 typedef struct {
     int64_t n_docs;
     const int64_t* offsets;
     const int32_t* tokens;
+    int64_t n_tokens;
 } mrc_docs;
 
 /* How the reference is chosen and split (Section 4). k parts of equal length

@@ -29,7 +29,8 @@ mrc_status check_docs(const mrc_docs* d, const char* fn) {
     if (d->n_docs < 0 || d->n_docs > 0x7FFFFFFFLL)
         return fail(MRC_E_INVAL, std::string(fn) + ": n_docs out of range");
     if (!d->offsets) return fail(MRC_E_INVAL, std::string(fn) + ": offsets is NULL");
-    if (d->n_docs > 0 && !d->tokens) return fail(MRC_E_INVAL, std::string(fn) + ": tokens is NULL");
+    if (d->n_docs > 0 && !d->tokens && d->n_tokens > 0) return fail(MRC_E_INVAL, std::string(fn) + ": tokens is NULL");
+    if (d->n_tokens < 0) return fail(MRC_E_INVAL, std::string(fn) + ": n_tokens < 0");
     return MRC_OK;
 }
 
@@ -130,13 +131,7 @@ mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t voc
         free_model(m);
         return st;
     };
-    DocBuckets b;
-    mrc_status st = launch_classify(ctx, corpus, vocab_size, &b, s);
-    if (st == MRC_OK) {
-        hipError_t e = hipMemsetAsync(m->d_df, 0, (size_t)vocab_size * 4, s);
-        if (e != hipSuccess) st = hip_fail(ctx, e, "memset df", __FILE__, __LINE__);
-    }
-    if (st == MRC_OK) st = launch_df(ctx, corpus, vocab_size, b, m->d_df, s);
+    mrc_status st = launch_df(ctx, corpus, vocab_size, m->d_df, s);
     if (st == MRC_OK) st = launch_model_tables(ctx, m, s);
     if (st == MRC_OK) st = sync_flags(ctx, s, 9, "mrc_build_vocab_idf");
     if (st != MRC_OK) return bail(st);
@@ -290,9 +285,7 @@ mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, 
     if (model->ctx->device != ctx->device) return fail(MRC_E_INVAL, "mrc_sign: model lives on another device");
     if (docs->n_docs > 0 && !sig_out) return fail(MRC_E_INVAL, "mrc_sign: sig_out is NULL");
     hipStream_t s = (hipStream_t)hip_stream;
-    DocBuckets b;
-    MRC_TRY(launch_classify(ctx, docs, model->vocab, &b, s));
-    MRC_TRY(launch_sign(ctx, model, docs, b, sig_out, norm_out, s));
+    MRC_TRY(launch_sign(ctx, model, docs, sig_out, norm_out, s));
     return sync_flags(ctx, s, 1, "mrc_sign");
 }
 
@@ -338,14 +331,15 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
     *n_found = 0;
     mrc_compare_stats st{};
     st.n_pairs_compared = n * (n - 1) / 2;
-    void* unit = nullptr;
-    MRC_TRY(scratch(ctx, "cmp_unit", (size_t)(n > 0 ? n : 1) * k * sizeof(float), &unit));
     unsigned long long* counter = (unsigned long long*)(ctx->d_flags + 4);
     if (opts->precision == MRC_PREC_FP32) {
+        const int64_t n_pad = ceil_div(n > 0 ? n : 1, 64) * 64, kp = 16 * (int64_t)mfma_chunks(k);
+        void* umfma = nullptr;
+        MRC_TRY(scratch(ctx, "cmp_unit_mfma", (size_t)(n_pad * kp) * sizeof(float), &umfma));
         MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 16 * sizeof(int64_t), s));
-        MRC_TRY(launch_normalise(ctx, sig, n, k, (float*)unit, nullptr, nullptr, nullptr, nullptr, s));
+        MRC_TRY(launch_normalise(ctx, sig, n, k, nullptr, nullptr, nullptr, nullptr, nullptr, s, (float*)umfma));
         PairSink sink{pairs_out, capacity, counter};
-        MRC_TRY(launch_compare_f32(ctx, (const float*)unit, n, k, opts->tau, sink, s));
+        MRC_TRY(launch_compare_f32(ctx, (const float*)umfma, n, k, opts->tau, sink, s));
         MRC_TRY(sync_flags(ctx, s, 16, "mrc_compare"));
         const int64_t found = ctx->h_flags[4];
         *n_found = found;

@@ -61,6 +61,7 @@ struct mrc_ctx {
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> event_pool;
     std::mutex mu;               // guards `used` (databases may be touched by server threads)
+    int tile_order_nb = -1;      // the band table in scratch "tile_order" is for this many tile rows
 };
 
 struct mrc_model {
@@ -128,29 +129,23 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------- stage launchers
 // Each returns MRC_OK or an error; all work is enqueued on `s`.
 
-// Document pass: validate offsets/tokens and bucket documents by length.
-struct DocBuckets {
-    int32_t* d_lists = nullptr;   // [3][n] document ids per class
-    int64_t* d_counts = nullptr;  // [3] class sizes (device)
-};
-mrc_status launch_classify(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, DocBuckets* b,
-                           hipStream_t s);
-
-// df over a corpus (atomic integer increments, one per distinct (doc, term)).
-mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, const DocBuckets& b,
-                     uint32_t* d_df, hipStream_t s);
+// df over a corpus: one increment per distinct (document, term). Also checks
+// offsets and token ids (error bits in ctx->d_flags[0]).
+mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s);
 
 // Model tables from df: idf, stable rank sort, selection, parts, reference norms.
 mrc_status launch_model_tables(mrc_ctx* ctx, mrc_model* m, hipStream_t s);
 
 // Signatures with a frozen model. unit_out optional: also write unit signatures.
-mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs,
-                       const DocBuckets& b, float* sig_out, float* norm_out, hipStream_t s);
+mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, float* sig_out,
+                       float* norm_out, hipStream_t s);
 
 // Normalise + quantise rows.
+// umfma (optional): unit signatures in the matrix-core layout, [roundup(n,64)][roundup(k,16)]
+// with transposed 4x4 sub-blocks in each 16-column block and zero padding.
 mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit,
                             uint16_t* bf16, uint8_t* fp8, float* scale, float* err,
-                            hipStream_t s);
+                            hipStream_t s, float* umfma = nullptr);
 
 // Pair output buffer shared by the all-pairs kernels.
 struct PairSink {
@@ -159,7 +154,7 @@ struct PairSink {
     unsigned long long* counter;  // device: number of pairs found
 };
 
-mrc_status launch_compare_f32(mrc_ctx* ctx, const float* unit, int64_t n, int32_t k, float tau,
+mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
                               PairSink sink, hipStream_t s);
 
 struct BandSink {
@@ -183,8 +178,8 @@ mrc_status launch_simhash(mrc_ctx* ctx, const mrc_docs* docs, const uint64_t* d_
                           uint64_t* out, hipStream_t s);
 mrc_status launch_hamming(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32_t max_dist,
                           PairSink sink, hipStream_t s);
-mrc_status launch_exact_cosine(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs,
-                               const DocBuckets& b, float tau, PairSink sink, hipStream_t s);
+mrc_status launch_exact_cosine(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, float tau,
+                               PairSink sink, hipStream_t s);
 
 // Query top-k against a database.
 mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t db_rows, const mrc_model* m,
@@ -193,6 +188,69 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t db_rows, const mrc_
 
 // Normalise and append unit signatures to a database.
 mrc_status db_append(mrc_db* db, const float* sig, int64_t n, int64_t first, hipStream_t s);
+
+// Upper-triangle tile schedule for the all-pairs kernels. Tile rows are grouped
+// in bands of kBand rows; a band lists its tiles column by column (inside a
+// column, row by row), so consecutive tiles share the column panel and a band
+// reuses its row panels. Workgroups are dispatched round-robin over the 8
+// XCDs; the schedule gives each XCD a contiguous range of the band order, so
+// the panels a range touches stay in that XCD's L2.
+struct TileOrder {
+    int nb;                 // tile rows (= tile columns)
+    int n_bands;
+    int per_block;          // tiles per workgroup
+    int64_t n_tiles;
+    int64_t blocks;         // workgroups that carry tiles
+    int64_t per_xcd;        // ceil(blocks / 8)
+    const int64_t* band_start;  // device [n_bands + 1]: first tile index of each band
+    static constexpr int kBand = 8;
+
+    // Tile handled by (workgroup p, slot w); false when there is none.
+    __device__ __forceinline__ bool tile_of(int64_t p, int w, int* bi, int* bj) const {
+        const int64_t xcd = p % 8, j = p / 8;
+        const int64_t lb = xcd * per_xcd + j;          // logical workgroup
+        if (lb >= blocks) return false;
+        const int64_t t = lb * per_block + w;
+        if (t >= n_tiles) return false;
+        tile_at(t, bi, bj);
+        return true;
+    }
+
+    // Coordinates of tile t of the band order. Call with a wavefront-uniform t:
+    // everything here is then scalar.
+    __device__ __forceinline__ void tile_at(int64_t t, int* bi, int* bj) const {
+        int lo = 0, hi = n_bands - 1;                   // band: last start <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (band_start[mid] <= t) lo = mid; else hi = mid - 1;
+        }
+        const int r0 = lo * kBand;
+        const int h = min(kBand, nb - r0);
+        int q = (int)(t - band_start[lo]);              // < kBand * nb
+        const int tri = h * (h + 1) / 2;
+        if (q < tri) {                                  // columns r0 .. r0+h-1: J - r0 + 1 tiles each
+            int c = 0;
+            while ((c + 1) * (c + 2) / 2 <= q) ++c;
+            *bj = r0 + c;
+            *bi = r0 + (q - c * (c + 1) / 2);
+        } else {
+            q -= tri;
+            const int col = q / h;
+            *bj = r0 + h + col;
+            *bi = r0 + (q - col * h);
+        }
+    }
+};
+
+mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s);
+// Workgroups of a persistent launch: as many as are resident at once on the
+// device (occupancy x CUs), rounded down to a multiple of the 8 XCDs and at most
+// `cap`.
+int64_t persistent_grid(mrc_ctx* ctx, const void* kernel, int block, int64_t cap);
+
+// Number of 16-column chunks of the FP32 matrix-core layout for k components
+// (rounded up to an instantiated count); the layout has 16 * mfma_chunks(k) columns.
+int mfma_chunks(int k);
 
 // Sizes of the length classes the document kernels use.
 constexpr int kShortMax = 512;    // one wavefront per document, LDS hash table

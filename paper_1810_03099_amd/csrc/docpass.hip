@@ -23,6 +23,7 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kEmpty = -1;
+constexpr int kDfReplicas = 32;
 
 enum : unsigned long long {
     kErrOffsets = 1ull,
@@ -73,20 +74,18 @@ struct SignArgs {
 
 enum { MODE_DF = 0, MODE_SIGN = 1 };
 
-__global__ void k_classify(const int64_t* __restrict__ off, int64_t n, int32_t* __restrict__ lists,
-                           unsigned long long* __restrict__ counts,
-                           unsigned long long* __restrict__ err) {
-    int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d >= n) return;
-    if (d == 0 && off[0] != 0) atomicOr(err, kErrOffsets);
-    int64_t L = off[d + 1] - off[d];
-    if (L < 0) {
-        atomicOr(err, kErrOffsets);
-        return;
-    }
-    int c = L <= kShortMax ? 0 : (L <= kMediumMax ? 1 : 2);
-    unsigned long long idx = atomicAdd(&counts[c], 1ull);
-    lists[(int64_t)c * n + (int64_t)idx] = (int32_t)d;
+// Offsets check before any token is read: offsets[0] = 0, non-decreasing,
+// offsets[n] <= n_tokens. Sets kErrOffsets; the document kernels then return
+// at once.
+__global__ void k_validate_offsets(const int64_t* __restrict__ off, int64_t n, int64_t n_tokens,
+                                   unsigned long long* __restrict__ err) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d > n) return;
+    bool bad = false;
+    if (d == 0) bad = off[0] != 0;
+    else bad = off[d] < off[d - 1];
+    if (d == n) bad = bad || off[n] > n_tokens || off[n] < 0;
+    if (bad) atomicOr(err, kErrOffsets);
 }
 
 // LDS layout of one team: bins u64[kpad] | keys i32[SLOTS] | cnt i32[SLOTS] |
@@ -95,11 +94,14 @@ __host__ __device__ constexpr size_t team_lds_bytes(int kpad, int slots) {
     return (size_t)kpad * 8 + (size_t)slots * 8 + (size_t)slots + 16 + 32;
 }
 
+// Documents d with lo_len < L_d <= hi_len are this kernel's; every kernel scans
+// all offsets and skips the others (no lists, no atomics). df increments go to
+// one of kDfReplicas copies of the [V] counters (chosen by document), so that
+// frequent terms do not serialise on one address; the copies are summed later.
 template <int MODE, int TEAM, int LOG2_SLOTS, int MAXPER>
-__global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ off, int64_t n_docs,
+                                                    int lo_len, int hi_len,
                                                     const int32_t* __restrict__ tok,
-                                                    const int32_t* __restrict__ list,
-                                                    const unsigned long long* __restrict__ count_ptr,
                                                     int32_t V, uint32_t* __restrict__ df,
                                                     SignArgs sa, unsigned long long* __restrict__ err) {
     constexpr int SLOTS = 1 << LOG2_SLOTS;
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     int* nused = (int*)(used + SLOTS / 2);
     double* red = (double*)(base + tbytes - 32);
 
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrOffsets) return;
     for (int s = tid; s < SLOTS; s += TEAM) {
         keys[s] = kEmpty;
         cnt[s] = 0;
@@ -125,11 +128,14 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     if (tid == 0) *nused = 0;
     team_sync<TEAM>();
 
-    const int64_t n_items = (int64_t)*count_ptr;
-    for (int64_t i = (int64_t)blockIdx.x * TEAMS + team; i < n_items; i += (int64_t)gridDim.x * TEAMS) {
-        const int d = list[i];
+    for (int64_t d = (int64_t)blockIdx.x * TEAMS + team; d < n_docs; d += (int64_t)gridDim.x * TEAMS) {
         const int64_t o = off[d];
-        const int L = (int)(off[d + 1] - o);
+        const int64_t L64 = off[d + 1] - o;
+        if (L64 <= lo_len || L64 > hi_len) {
+            if (!(lo_len == 0 && L64 == 0)) continue;
+        }
+        const int L = (int)L64;
+        uint32_t* dfr = df ? df + (size_t)(d % kDfReplicas) * (size_t)V : nullptr;
         int slot_r[MAXPER];
         float idf_r[MAXPER];
 #pragma unroll
@@ -157,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
                 int old = atomicAdd(&cnt[h], 1);
                 if (won) used[atomicAdd(nused, 1)] = (unsigned short)h;
                 if constexpr (MODE == MODE_DF) {
-                    if (old == 0) atomicAdd(&df[t], 1u);
+                    if (old == 0) atomicAdd(&dfr[t], 1u);
                 } else {
                     (void)old;
                     TermInfo ti = sa.tinfo[t];
@@ -203,10 +209,9 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
 // Long documents: a [V] uint32 count table per workgroup in global memory
 // (all zero between documents).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off,
+__global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off, int64_t n_docs,
+                                                       int lo_len,
                                                        const int32_t* __restrict__ tok,
-                                                       const int32_t* __restrict__ list,
-                                                       const unsigned long long* __restrict__ count_ptr,
                                                        int32_t V, uint32_t* __restrict__ df,
                                                        SignArgs sa, uint32_t* __restrict__ tables,
                                                        unsigned long long* __restrict__ err) {
@@ -216,13 +221,14 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
     double* red = (double*)(smem + (size_t)kpad * 8);
     uint32_t* cnt = tables + (size_t)blockIdx.x * (size_t)V;
     const int tid = threadIdx.x;
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrOffsets) return;
     for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
     __syncthreads();
-    const int64_t n_items = (int64_t)*count_ptr;
-    for (int64_t i = blockIdx.x; i < n_items; i += gridDim.x) {
-        const int d = list[i];
+    for (int64_t d = blockIdx.x; d < n_docs; d += gridDim.x) {
         const int64_t o = off[d];
         const int64_t L = off[d + 1] - o;
+        if (L <= lo_len) continue;
+        uint32_t* dfr = df ? df + (size_t)(d % kDfReplicas) * (size_t)V : nullptr;
         for (int64_t p = tid; p < L; p += kBlock) {
             const int t = tok[o + p];
             if ((unsigned)t >= (unsigned)V) {
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
             }
             unsigned old = atomicAdd(&cnt[t], 1u);
             if constexpr (MODE == MODE_DF) {
-                if (old == 0) atomicAdd(&df[t], 1u);
+                if (old == 0) atomicAdd(&dfr[t], 1u);
             } else {
                 (void)old;
                 TermInfo ti = sa.tinfo[t];
@@ -297,27 +303,46 @@ int grid_for(int64_t n_items_upper, int teams_per_block, int cap) {
     return (int)g;
 }
 
+__global__ void k_df_reduce(const uint32_t* __restrict__ rep, int32_t V, uint32_t* __restrict__ df) {
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V) return;
+    uint32_t s = 0;
+#pragma unroll 8
+    for (int r = 0; r < kDfReplicas; ++r) s += rep[(size_t)r * V + t];
+    df[t] = s;
+}
+
 template <int MODE>
-mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const DocBuckets& b,
-                       uint32_t* df, const SignArgs& sa, hipStream_t s, const char* name) {
+mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* df, const SignArgs& sa,
+                       hipStream_t s, const char* name) {
     const int64_t n = docs->n_docs;
-    if (n == 0) return MRC_OK;
     unsigned long long* err = (unsigned long long*)ctx->d_flags;
-    const unsigned long long* counts = (const unsigned long long*)b.d_counts;
+    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(int64_t), s));
+    if (n == 0) return MRC_OK;
+    hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, docs->offsets, n,
+                       docs->n_tokens, err);
+    MRC_HIP_TRY(ctx, hipGetLastError());
     const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
+    const size_t rep_bytes = (size_t)kDfReplicas * (size_t)V * sizeof(uint32_t);
+    void* rep = nullptr;
+    if (MODE == MODE_DF) {
+        MRC_TRY(scratch(ctx, "df_replicas", rep_bytes, &rep));
+        MRC_HIP_TRY(ctx, hipMemsetAsync(rep, 0, rep_bytes, s));
+    }
+    uint32_t* dfk = (uint32_t*)rep;
     ScopedTimer tm(ctx, name, s);
     {
         size_t lds = team_lds_bytes(kpad, 1 << kShortLog2) * (kBlock / kShortTeam);
-        int grid = grid_for(n, kBlock / kShortTeam, 256 * 16);
+        int grid = grid_for(n, kBlock / kShortTeam, 256 * 8);
         hipLaunchKernelGGL((k_doc_lds<MODE, kShortTeam, kShortLog2, kShortPer>), dim3(grid), dim3(kBlock),
-                           lds, s, docs->offsets, docs->tokens, b.d_lists, counts, V, df, sa, err);
+                           lds, s, docs->offsets, n, 0, kShortMax, docs->tokens, V, dfk, sa, err);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
         size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
         int grid = grid_for(n, 1, 256 * 2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid), dim3(kBlock), lds, s,
-                           docs->offsets, docs->tokens, b.d_lists + n, counts + 1, V, df, sa, err);
+                           docs->offsets, n, kShortMax, kMediumMax, docs->tokens, V, dfk, sa, err);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
@@ -328,8 +353,13 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const DocB
         MRC_TRY(scratch(ctx, "long_tables", table_bytes, &tables));
         if (fresh) MRC_HIP_TRY(ctx, hipMemsetAsync(tables, 0, ctx->scratch["long_tables"].second, s));
         size_t lds = (size_t)kpad * 8 + 32;
-        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets,
-                           docs->tokens, b.d_lists + 2 * n, counts + 2, V, df, sa, (uint32_t*)tables, err);
+        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets, n,
+                           kMediumMax, docs->tokens, V, dfk, sa, (uint32_t*)tables, err);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+    }
+    if (MODE == MODE_DF) {
+        hipLaunchKernelGGL(k_df_reduce, dim3((unsigned)ceil_div(V, 256)), dim3(256), 0, s, (const uint32_t*)rep,
+                           V, df);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     return MRC_OK;
@@ -339,31 +369,13 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const DocB
 
 namespace mrc {
 
-mrc_status launch_classify(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, DocBuckets* b,
-                           hipStream_t s) {
-    (void)vocab;
-    const int64_t n = docs->n_docs;
-    void* lists = nullptr;
-    MRC_TRY(scratch(ctx, "class_lists", (size_t)(3 * (n > 0 ? n : 1)) * sizeof(int32_t), &lists));
-    b->d_lists = (int32_t*)lists;
-    b->d_counts = ctx->d_flags + 1;
-    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 4 * sizeof(int64_t), s));
-    if (n == 0) return MRC_OK;
-    ScopedTimer tm(ctx, "classify", s);
-    hipLaunchKernelGGL(k_classify, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, docs->offsets, n,
-                       b->d_lists, (unsigned long long*)b->d_counts, (unsigned long long*)ctx->d_flags);
-    MRC_HIP_TRY(ctx, hipGetLastError());
-    return MRC_OK;
-}
-
-mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, const DocBuckets& b,
-                     uint32_t* d_df, hipStream_t s) {
+mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s) {
     SignArgs sa{};
-    return run_docpass<MODE_DF>(ctx, docs, vocab, b, d_df, sa, s, "df");
+    return run_docpass<MODE_DF>(ctx, docs, vocab, d_df, sa, s, "df");
 }
 
-mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const DocBuckets& b,
-                       float* sig_out, float* norm_out, hipStream_t s) {
+mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, float* sig_out,
+                       float* norm_out, hipStream_t s) {
     SignArgs sa{};
     sa.tinfo = m->d_tinfo;
     sa.rinv = m->d_rinv;
@@ -371,7 +383,7 @@ mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, c
     sa.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
     sa.sig = sig_out;
     sa.norm = norm_out;
-    return run_docpass<MODE_SIGN>(ctx, docs, m->vocab, b, nullptr, sa, s, "sign");
+    return run_docpass<MODE_SIGN>(ctx, docs, m->vocab, nullptr, sa, s, "sign");
 }
 
 }  // namespace mrc

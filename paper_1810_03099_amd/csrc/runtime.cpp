@@ -1,5 +1,6 @@
 // Host runtime of libmrc: thread-local errors, budgeted device allocation,
 // named scratch buffers, and per-kernel HIP-event timing.
+#include <algorithm>
 #include <cstdio>
 
 #include "common.h"
@@ -117,6 +118,52 @@ void timer_collect(mrc_ctx* ctx) {
         ctx->event_pool.push_back(p.second.second);
     }
     ctx->pending.clear();
+}
+
+mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s) {
+    const int B = TileOrder::kBand;
+    const int n_bands = (nb + B - 1) / B;
+    std::vector<int64_t> start(n_bands + 1);
+    int64_t t = 0;
+    for (int b = 0; b < n_bands; ++b) {
+        start[b] = t;
+        const int r0 = b * B, h = std::min(B, nb - r0);
+        t += (int64_t)h * (h + 1) / 2 + (int64_t)h * (nb - r0 - h);
+    }
+    start[n_bands] = t;
+    void* d = nullptr;
+    auto it = ctx->scratch.find("tile_order");
+    const bool cached = ctx->tile_order_nb == nb && it != ctx->scratch.end();
+    MRC_TRY(scratch(ctx, "tile_order", (size_t)(n_bands + 1) * sizeof(int64_t), &d));
+    if (!cached) {
+        MRC_HIP_TRY(ctx, hipMemcpyAsync(d, start.data(), (n_bands + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
+        MRC_HIP_TRY(ctx, hipStreamSynchronize(s));  // the host vector must outlive the copy
+        ctx->tile_order_nb = nb;
+    }
+    ord->nb = nb;
+    ord->n_bands = n_bands;
+    ord->per_block = per_block;
+    ord->n_tiles = t;
+    ord->blocks = (t + per_block - 1) / per_block;
+    ord->per_xcd = (ord->blocks + 7) / 8;
+    ord->band_start = (const int64_t*)d;
+    *grid = ord->per_xcd * 8;
+    if (*grid > 0x7FFFFFFFLL) return fail(MRC_E_INVAL, "too many tiles for one launch");
+    return MRC_OK;
+}
+
+int64_t persistent_grid(mrc_ctx* ctx, const void* kernel, int block, int64_t cap) {
+    int per_cu = 1, cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+        per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
+        cus = 256;
+    (void)hipGetLastError();
+    int64_t g = (int64_t)per_cu * cus;
+    cap = (cap + 7) / 8 * 8;
+    if (g > cap) g = cap;
+    g = g / 8 * 8;
+    return g < 8 ? 8 : g;
 }
 
 }  // namespace mrc

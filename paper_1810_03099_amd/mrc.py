@@ -52,7 +52,7 @@ class MrcError(RuntimeError):
 
 
 class MrcDocs(C.Structure):
-    _fields_ = [("n_docs", C.c_int64), ("offsets", C.c_void_p), ("tokens", C.c_void_p)]
+    _fields_ = [("n_docs", C.c_int64), ("offsets", C.c_void_p), ("tokens", C.c_void_p), ("n_tokens", C.c_int64)]
 
 
 class MrcRefSpec(C.Structure):
@@ -182,7 +182,8 @@ def _dptr(t, dtype=None, name="tensor"):
 
 def _docs(offsets, tokens):
     n = int(offsets.numel()) - 1
-    d = MrcDocs(n, _dptr(offsets, torch.int64, "offsets"), _dptr(tokens, torch.int32, "tokens"))
+    d = MrcDocs(n, _dptr(offsets, torch.int64, "offsets"), _dptr(tokens, torch.int32, "tokens"),
+                int(tokens.numel()))
     return d, (offsets, tokens)
 
 

@@ -138,6 +138,14 @@ def test_invalid_inputs_raise(lib, ctx):
     boff[3] = boff[4] + 1          # decreasing offsets
     with pytest.raises(lib.MrcError):
         lib.mrc_sign(ctx, gm, boff, t)
+    boff = o.clone()
+    boff[-1] = t.numel() + 1       # past the token buffer: rejected before any token is read
+    with pytest.raises(lib.MrcError):
+        lib.mrc_sign(ctx, gm, boff, t)
+    boff = o.clone()
+    boff[0] = 1
+    with pytest.raises(lib.MrcError):
+        lib.mrc_build_vocab_idf(ctx, boff, t, c.vocab, gspec)
     with pytest.raises(lib.MrcError):                     # more parts than selected terms
         lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(16, mode=lib.SEL_RAREST, m=10))
     # the context stays usable after input errors
