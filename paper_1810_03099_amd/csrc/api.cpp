@@ -1,5 +1,6 @@
 // C ABI entry points of libmrc: argument checks, object life cycle, stage
 // sequencing on the caller's stream, and status reporting.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <fstream>
@@ -348,7 +349,62 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
         if (found > capacity) return fail(MRC_E_OVERFLOW, "mrc_compare: more pairs than capacity");
         return MRC_OK;
     }
-    return fail(MRC_E_STATE, "mrc_compare: low-precision forms are built in compare_lowp");
+    // BF16 / FP8: candidates on the matrix cores, then exact decisions by rescoring.
+    const int prec = opts->precision;
+    const int step = prec == MRC_PREC_BF16 ? 32 : 128, ebytes = prec == MRC_PREC_BF16 ? 2 : 1;
+    const int ldq = lowp_steps(prec, k) * step;
+    const int64_t n_pad = ceil_div(n > 0 ? n : 1, 64) * 64;
+    void *unit = nullptr, *q = nullptr, *scale = nullptr, *err = nullptr;
+    MRC_TRY(scratch(ctx, "lp_unit", (size_t)(n > 0 ? n : 1) * k * sizeof(float), &unit));
+    MRC_TRY(scratch(ctx, "lp_codes", (size_t)n_pad * ldq * ebytes, &q));
+    MRC_TRY(scratch(ctx, "lp_scale", (size_t)n_pad * sizeof(float), &scale));
+    MRC_TRY(scratch(ctx, "lp_err", (size_t)2 * n_pad * sizeof(float), &err));
+    int64_t cand_cap = std::max<int64_t>(1 << 20, 16 * n);
+    auto it = ctx->scratch.find("lp_cand");
+    if (it != ctx->scratch.end()) cand_cap = std::max<int64_t>(cand_cap, (int64_t)(it->second.second / sizeof(mrc_pair)));
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        void* cand = nullptr;
+        MRC_TRY(scratch(ctx, "lp_cand", (size_t)cand_cap * sizeof(mrc_pair), &cand));
+        MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 32 * sizeof(int64_t), s));
+        NormLayout o{(float*)unit, k, prec == MRC_PREC_BF16 ? (uint16_t*)q : nullptr, ldq,
+                     prec == MRC_PREC_FP8 ? (uint8_t*)q : nullptr, ldq, (float*)scale, (float*)err, n_pad,
+                     nullptr, 0, n_pad};
+        MRC_TRY(launch_normalise_rows(ctx, sig, n, k, o, s));
+        const float* err_p = (const float*)err + (prec == MRC_PREC_BF16 ? 0 : n_pad);
+        float* d_lo = (float*)(ctx->d_flags + 22);
+        if (n >= 2) {
+            MRC_TRY(launch_lowp_threshold(ctx, prec, err_p, n, opts->tau, opts->band, k, d_lo, s));
+            PairSink cs{(mrc_pair*)cand, cand_cap, (unsigned long long*)(ctx->d_flags + 16)};
+            MRC_TRY(launch_compare_lowp(ctx, prec, (const uint8_t*)q, ldq * ebytes, (const float*)scale, n, k, d_lo,
+                                        cs, s));
+            PairSink out{pairs_out, capacity, counter};
+            MRC_TRY(launch_rescore2(ctx, prec, (const mrc_pair*)cand, (const unsigned long long*)(ctx->d_flags + 16),
+                                    cand_cap, (const float*)unit, k, err_p, opts->tau, opts->band, out,
+                                    (unsigned long long*)(ctx->d_flags + 17), s));
+        }
+        MRC_TRY(sync_flags(ctx, s, 32, "mrc_compare"));
+        const int64_t n_cand = ctx->h_flags[16];
+        if (n_cand > cand_cap && attempt == 0) {
+            cand_cap = n_cand + n_cand / 4;
+            continue;
+        }
+        if (n_cand > cand_cap) return fail(MRC_E_NOMEM, "mrc_compare: candidate list overflow");
+        const int64_t found = ctx->h_flags[4];
+        *n_found = found;
+        st.n_flagged = found;
+        st.n_band = ctx->h_flags[17];
+        st.n_band_nominal = ctx->h_flags[18];
+        st.n_flip_outside_nominal = ctx->h_flags[19];
+        uint32_t mx = (uint32_t)ctx->h_flags[20];
+        memcpy(&st.max_abs_err, &mx, 4);
+        double sum = 0.0;
+        memcpy(&sum, &ctx->h_flags[21], 8);
+        st.mean_abs_err = st.n_band ? (float)(sum / (double)st.n_band) : 0.f;
+        if (stats) *stats = st;
+        if (found > capacity) return fail(MRC_E_OVERFLOW, "mrc_compare: more pairs than capacity");
+        return MRC_OK;
+    }
+    return fail(MRC_E_STATE, "mrc_compare: unreachable");
 }
 
 }  // extern "C"

@@ -157,18 +157,30 @@ struct PairSink {
 mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
                               PairSink sink, hipStream_t s);
 
-struct BandSink {
-    int32_t* ij;              // [2][capacity]
-    float* s;                 // [capacity] low-precision score
-    int64_t capacity;
-    unsigned long long* counter;
+// Low-precision forms. Codes are [n_pad][ldq] (bytes per row ldq_bytes), rows
+// padded to 64 and columns to an even number of MFMA steps (lowp_steps).
+int lowp_steps(int precision, int k);
+mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q, int ldq_bytes,
+                               const float* scale, int64_t n, int32_t k, const float* d_lo_thr,
+                               PairSink cand, hipStream_t s);
+float lowp_acc_unit(int precision, int k);
+mrc_status launch_lowp_threshold(mrc_ctx* ctx, int precision, const float* err, int64_t n, float tau,
+                                 float nominal, int k, float* d_out, hipStream_t s);
+mrc_status launch_rescore2(mrc_ctx* ctx, int precision, const mrc_pair* cand, const unsigned long long* n_cand,
+                           int64_t cand_cap, const float* unit, int32_t k, const float* err, float tau, float nominal,
+                           PairSink out, unsigned long long* stats, hipStream_t s);
+// Normalise with explicit layouts (see compare.hip).
+struct NormLayout {
+    float* unit;      int ld_unit;
+    uint16_t* bf16;   int ld_bf16;
+    uint8_t* fp8;     int ld_fp8;
+    float* scale;
+    float* err;       int64_t ld_err;
+    float* umfma;     int ld_mfma;
+    int64_t n_pad;
 };
-mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const void* q, const float* scale,
-                               const float* err, int64_t n, int32_t k, float tau, float band,
-                               PairSink sink, BandSink bands, hipStream_t s);
-mrc_status launch_rescore(mrc_ctx* ctx, const float* unit, int32_t k, float tau, float band,
-                          BandSink bands, int64_t n_bands, PairSink sink,
-                          unsigned long long* d_stats, hipStream_t s);
+mrc_status launch_normalise_rows(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const NormLayout& o,
+                                 hipStream_t s);
 mrc_status launch_score_pairs(mrc_ctx* ctx, const float* unit, int32_t k, const int32_t* ii,
                               const int32_t* jj, int64_t n_pairs, float* out, hipStream_t s);
 

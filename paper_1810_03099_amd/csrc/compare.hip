@@ -60,21 +60,29 @@ constexpr int kMaxPerLane = 16;
 // loading 4 consecutive floats at 4g feeds MFMA step m with component 4m + g.
 __device__ __forceinline__ int mfma_col(int c) { return (c & ~15) | ((c & 3) << 2) | ((c >> 2) & 3); }
 
-__global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig, int64_t n, int k,
-                                                   float* __restrict__ unit, uint16_t* __restrict__ bf16,
-                                                   uint8_t* __restrict__ fp8, float* __restrict__ scale,
-                                                   float* __restrict__ err, float* __restrict__ umfma,
-                                                   int64_t n_pad, int kp) {
+// Output layouts of k_normalise (NormLayout): leading dimensions let the comparison
+// kernels use zero-padded internal copies (rows padded to n_pad, columns to ld).
+using NormOut = NormLayout;
+
+__global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig, int64_t n, int k, NormOut o) {
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (umfma && row >= n && row < n_pad) {
-        for (int c = lane; c < kp; c += 64) umfma[row * kp + c] = 0.f;
+    if (row >= o.n_pad) return;
+    if (row >= n) {  // padding rows: zeros everywhere
+        if (o.unit) for (int c = lane; c < o.ld_unit; c += 64) o.unit[row * o.ld_unit + c] = 0.f;
+        if (o.bf16) for (int c = lane; c < o.ld_bf16; c += 64) o.bf16[row * o.ld_bf16 + c] = 0;
+        if (o.fp8) for (int c = lane; c < o.ld_fp8; c += 64) o.fp8[row * o.ld_fp8 + c] = 0;
+        if (o.umfma) for (int c = lane; c < o.ld_mfma; c += 64) o.umfma[row * o.ld_mfma + c] = 0.f;
+        if (lane == 0) {
+            if (o.scale) o.scale[row] = 0.f;
+            if (o.err) o.err[row] = o.err[o.ld_err + row] = 0.f;
+        }
         return;
     }
-    if (row >= n) return;
-    if (umfma) {
-        for (int c = k + lane; c < kp; c += 64) umfma[row * kp + mfma_col(c)] = 0.f;
-    }
+    if (o.unit) for (int c = k + lane; c < o.ld_unit; c += 64) o.unit[row * o.ld_unit + c] = 0.f;
+    if (o.bf16) for (int c = k + lane; c < o.ld_bf16; c += 64) o.bf16[row * o.ld_bf16 + c] = 0;
+    if (o.fp8) for (int c = k + lane; c < o.ld_fp8; c += 64) o.fp8[row * o.ld_fp8 + c] = 0;
+    if (o.umfma) for (int c = k + lane; c < o.ld_mfma; c += 64) o.umfma[row * o.ld_mfma + mfma_col(c)] = 0.f;
     const float* x = sig + row * k;
     float v[kMaxPerLane];
     float s2 = 0.f;
@@ -92,8 +100,8 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
         v[r] = nrm > 0.f ? v[r] / nrm : 0.f;
         amax = fmaxf(amax, fabsf(v[r]));
         const int c = lane + 64 * r;
-        if (c < k && unit) unit[row * k + c] = v[r];
-        if (c < k && umfma) umfma[row * kp + mfma_col(c)] = v[r];
+        if (c < k && o.unit) o.unit[row * o.ld_unit + c] = v[r];
+        if (c < k && o.umfma) o.umfma[row * o.ld_mfma + mfma_col(c)] = v[r];
     }
     amax = mrc_dev::wave_max(amax);
     const float sc = amax / 448.0f;
@@ -105,21 +113,21 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
         const uint16_t b = bf16_rne(v[r]);
         const double db = (double)v[r] - (double)bf16_value(b);
         eb += db * db;
-        if (bf16) bf16[row * k + c] = b;
+        if (o.bf16) o.bf16[row * o.ld_bf16 + c] = b;
         const uint8_t q = sc > 0.f ? e4m3fn_rne(v[r] / sc) : (uint8_t)0;
         const double d8 = (double)v[r] - (double)e4m3fn_value(q) * (double)sc;
         e8 += d8 * d8;
-        if (fp8) fp8[row * k + c] = q;
+        if (o.fp8) o.fp8[row * o.ld_fp8 + c] = q;
     }
     eb = mrc_dev::wave_sum(eb);
     e8 = mrc_dev::wave_sum(e8);
     if (lane == 0) {
-        if (scale) scale[row] = sc;
-        if (err) {
+        if (o.scale) o.scale[row] = sc;
+        if (o.err) {
             // round the float64 norms up to float so the stored value bounds the error
             float fb = (float)sqrt(eb), f8 = (float)sqrt(e8);
-            err[row] = (double)fb < sqrt(eb) ? nextafterf(fb, INFINITY) : fb;
-            err[n + row] = (double)f8 < sqrt(e8) ? nextafterf(f8, INFINITY) : f8;
+            o.err[row] = (double)fb < sqrt(eb) ? nextafterf(fb, INFINITY) : fb;
+            o.err[o.ld_err + row] = (double)f8 < sqrt(e8) ? nextafterf(f8, INFINITY) : f8;
         }
     }
 }
@@ -286,6 +294,247 @@ __global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u
     st.flush(sink);
 }
 
+// ---------------------------------------------------------------- BF16 / FP8 forms
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+// Element width (bytes) and k per MFMA step of each low-precision form.
+template <int PREC> struct LowpTraits;
+template <> struct LowpTraits<MRC_PREC_BF16> { static constexpr int kStep = 32, kBytes = 2, kLaneBytes = 16; };
+template <> struct LowpTraits<MRC_PREC_FP8> { static constexpr int kStep = 128, kBytes = 1, kLaneBytes = 32; };
+
+// Operand fragment of one 16-row block for one MFMA step: lane (row li, group
+// lg) holds kLaneBytes consecutive bytes of its row at k = c0 + lg * (kStep/4).
+template <int PREC> struct Frag;
+template <> struct Frag<MRC_PREC_BF16> {
+    i32x4 v;
+    __device__ __forceinline__ void load(const uint8_t* p) { v = *(const i32x4*)p; }
+};
+template <> struct Frag<MRC_PREC_FP8> {
+    i32x4 lo, hi;
+    __device__ __forceinline__ void load(const uint8_t* p) {
+        lo = *(const i32x4*)p;
+        hi = *(const i32x4*)(p + 16);
+    }
+};
+
+__device__ __forceinline__ f32x4 mma(const Frag<MRC_PREC_BF16>& a, const Frag<MRC_PREC_BF16>& b, f32x4 c) {
+    bf16x8 av, bv;
+    __builtin_memcpy(&av, &a.v, 16);
+    __builtin_memcpy(&bv, &b.v, 16);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 mma(const Frag<MRC_PREC_FP8>& a, const Frag<MRC_PREC_FP8>& b, f32x4 c) {
+    const i32x8 av = {a.lo[0], a.lo[1], a.lo[2], a.lo[3], a.hi[0], a.hi[1], a.hi[2], a.hi[3]};
+    const i32x8 bv = {b.lo[0], b.lo[1], b.lo[2], b.lo[3], b.hi[0], b.hi[1], b.hi[2], b.hi[3]};
+    // formats 0/0: both operands float8 e4m3; E8M0 block scales 127 = 2^0
+    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+}
+
+// Candidate search of the low-precision forms: same persistent band-ordered
+// 64x64 wavefront tiles as the FP32 path. A pair becomes a candidate when its
+// low-precision score is >= lo_thr = tau - (the largest rescoring band over all
+// rows); the rescoring kernel then decides each candidate exactly.
+// q: [n_pad][ldq] bytes of codes (zero padded), scale: [n_pad] (FP8 only).
+template <int PREC, int NK>
+__global__ __launch_bounds__(256) void k_compare_lowp(const uint8_t* __restrict__ q, int ldq_bytes,
+                                                      const float* __restrict__ scale, int n,
+                                                      const float* __restrict__ lo_thr_ptr, TileOrder ord,
+                                                      PairSink cand) {
+    using T = LowpTraits<PREC>;
+    static_assert(NK % 2 == 0, "even step count");
+    __shared__ mrc_pair stage_buf[4][kStage];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    PairStage st{stage_buf[wave], 0};
+    const float lo_thr = *lo_thr_ptr;
+    const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
+    const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
+    const int64_t stride = per_xcd_blocks * 4;
+    int64_t t = t_lo + bx * 4 + wave;
+    if (t >= t_hi) return;
+    int bi, bj;
+    ord.tile_at(t, &bi, &bj);
+    constexpr int kStepBytes = T::kStep * T::kBytes;
+    const uint8_t* pa = q + (int64_t)(bi * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
+    const uint8_t* pb = q + (int64_t)(bj * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
+    Frag<PREC> a[2][4], b[2][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        a[0][x].load(pa + (int64_t)16 * x * ldq_bytes);
+        b[0][x].load(pb + (int64_t)16 * x * ldq_bytes);
+    }
+    while (true) {
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int row0 = bi * kWT, col0 = bj * kWT;
+        const int64_t tn = t + stride;
+        const bool more = tn < t_hi;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int cur = c & 1, nxt = cur ^ 1;
+            if (c + 1 < NK) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[nxt][x].load(pa + (int64_t)16 * x * ldq_bytes + kStepBytes * (c + 1));
+                    b[nxt][x].load(pb + (int64_t)16 * x * ldq_bytes + kStepBytes * (c + 1));
+                }
+            } else if (more) {
+                int ni, nj;
+                ord.tile_at(tn, &ni, &nj);
+                pa = q + (int64_t)(ni * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
+                pb = q + (int64_t)(nj * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[nxt][x].load(pa + (int64_t)16 * x * ldq_bytes);
+                    b[nxt][x].load(pb + (int64_t)16 * x * ldq_bytes);
+                }
+                bi = ni;
+                bj = nj;
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y) acc[x][y] = mma(a[cur][x], b[cur][y], acc[x][y]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
+        const int ib = row0 + 4 * lg, jb = col0 + li;
+        float rs[4][4], cs[4];
+        if constexpr (PREC == MRC_PREC_FP8) {
+#pragma unroll
+            for (int y = 0; y < 4; ++y) cs[y] = scale[jb + 16 * y];
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) rs[x][r] = scale[ib + 16 * x + r];
+        }
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    float v = acc[x][y][r];
+                    if constexpr (PREC == MRC_PREC_FP8) v = v * rs[x][r] * cs[y];
+                    bool f = v >= lo_thr;
+                    if (!interior) {
+                        const int i = ib + 16 * x + r, j = jb + 16 * y;
+                        f = f && i < j && j < n;
+                    }
+                    st.add(cand, f, [&](int* i, int* j) { *i = ib + 16 * x + r; *j = jb + 16 * y; }, v, 0);
+                }
+        if (!more) break;
+        t = tn;
+    }
+    st.flush(cand);
+}
+
+// lo_thr = tau - max(nominal, band(e_max, e_max)) with e_max the largest row error.
+__device__ __forceinline__ float lowp_band(float ei, float ej, float nominal, float acc_unit) {
+    const float b = ei + ej + ei * ej + acc_unit * (1.f + ei) * (1.f + ej) + 9.5367431640625e-07f;  // + 2^-20
+    return fmaxf(nominal, b);
+}
+
+__global__ __launch_bounds__(1024) void k_lowp_threshold(const float* __restrict__ err, int64_t n, float tau,
+                                                         float nominal, float acc_unit, float* __restrict__ out) {
+    __shared__ float red[16];
+    float m = 0.f;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmaxf(m, err[i]);
+    m = mrc_dev::wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float e = 0.f;
+        for (int w = 0; w < 16; ++w) e = fmaxf(e, red[w]);
+        out[0] = tau - lowp_band(e, e, nominal, acc_unit);
+    }
+}
+
+// Rescoring: every candidate with |s_lp - tau| <= band(e_i, e_j) gets the plain
+// FP32 chain score over the natural-order unit signatures; outside the band
+// the low-precision decision is already certain. Decided pairs are staged per
+// workgroup in LDS and reserved in the output with one atomic per workgroup.
+// stats: [0] rescored, [1] rescored within nominal, [2] flips outside nominal,
+// [3] max |s_lp - s32| (float bits), [4] sum |s_lp - s32| (double bits).
+constexpr int kRescoreChunk = 2048;
+
+__global__ __launch_bounds__(256) void k_rescore(const mrc_pair* __restrict__ cand,
+                                                 const unsigned long long* __restrict__ n_cand_ptr,
+                                                 int64_t cand_cap, const float* __restrict__ unit, int k,
+                                                 const float* __restrict__ err, float tau, float nominal,
+                                                 float acc_unit, PairSink out,
+                                                 unsigned long long* __restrict__ stats) {
+    __shared__ mrc_pair sbuf[kRescoreChunk];
+    __shared__ int scount;
+    __shared__ unsigned long long sbase;
+    __shared__ unsigned long long s_nb, s_nn, s_flip, s_max;
+    __shared__ double s_sum;
+    const int64_t nc = min((int64_t)*n_cand_ptr, cand_cap);
+    if (threadIdx.x == 0) {
+        s_nb = s_nn = s_flip = s_max = 0;
+        s_sum = 0.0;
+    }
+    for (int64_t c0 = (int64_t)blockIdx.x * kRescoreChunk; c0 < nc; c0 += (int64_t)gridDim.x * kRescoreChunk) {
+        if (threadIdx.x == 0) scount = 0;
+        __syncthreads();
+        const int64_t c1 = min(nc, c0 + kRescoreChunk);
+        for (int64_t c = c0 + threadIdx.x; c < c1; c += 256) {
+            const mrc_pair p = cand[c];
+            const float ei = err[p.i], ej = err[p.j];
+            const float band = lowp_band(ei, ej, nominal, acc_unit);
+            float s = p.s;
+            int flags = 0;
+            bool keep;
+            if (p.s >= tau + band) {
+                keep = true;
+            } else if (p.s < tau - band) {
+                keep = false;
+            } else {
+                const float* a = unit + (int64_t)p.i * k;
+                const float* b = unit + (int64_t)p.j * k;
+                float acc = 0.f;
+                for (int cc = 0; cc < k; ++cc) acc = __builtin_fmaf(a[cc], b[cc], acc);
+                keep = acc >= tau;
+                const float d = fabsf(p.s - acc);
+                atomicAdd(&s_nb, 1ull);
+                if (fabsf(p.s - tau) <= nominal) atomicAdd(&s_nn, 1ull);
+                else if ((p.s >= tau) != keep) atomicAdd(&s_flip, 1ull);
+                atomicMax(&s_max, (unsigned long long)__float_as_uint(d));
+                atomicAdd(&s_sum, (double)d);
+                s = acc;
+                flags = 1;
+            }
+            if (keep) sbuf[atomicAdd(&scount, 1)] = mrc_pair{p.i, p.j, s, flags};
+        }
+        __syncthreads();
+        const int cnt = scount;
+        if (threadIdx.x == 0 && cnt > 0) sbase = atomicAdd(out.counter, (unsigned long long)cnt);
+        __syncthreads();
+        for (int e = threadIdx.x; e < cnt; e += 256) {
+            const int64_t dst = (int64_t)sbase + e;
+            if (dst < out.capacity) out.pairs[dst] = sbuf[e];
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (s_nb) atomicAdd(&stats[0], s_nb);
+        if (s_nn) atomicAdd(&stats[1], s_nn);
+        if (s_flip) atomicAdd(&stats[2], s_flip);
+        if (s_max) atomicMax(&stats[3], s_max);
+        if (s_sum != 0.0) atomicAdd((double*)&stats[4], s_sum);
+    }
+}
+
 // Plain score of listed pairs (one thread per pair, same chain).
 __global__ void k_score_pairs(const float* __restrict__ u, int k, const int32_t* __restrict__ ii,
                               const int32_t* __restrict__ jj, int64_t np, float* __restrict__ out) {
@@ -308,12 +557,17 @@ mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k
                             uint16_t* bf16, uint8_t* fp8, float* scale, float* err, hipStream_t s,
                             float* umfma) {
     if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
-    const int64_t n_pad = umfma ? ceil_div(n, 64) * 64 : n;
-    const int kp = 16 * mfma_chunks(k);
-    if (n_pad == 0) return MRC_OK;
+    NormOut o{unit, k, bf16, k, fp8, k, scale, err, n, umfma, 16 * mfma_chunks(k), n};
+    if (umfma) o.n_pad = ceil_div(n, 64) * 64;
+    return launch_normalise_rows(ctx, sig, n, k, o, s);
+}
+
+mrc_status launch_normalise_rows(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const NormLayout& o,
+                                 hipStream_t s) {
+    if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
+    if (o.n_pad == 0) return MRC_OK;
     ScopedTimer tm(ctx, "normalise", s);
-    hipLaunchKernelGGL(k_normalise, dim3((unsigned)ceil_div(n_pad, 4)), dim3(256), 0, s, sig, n, k, unit, bf16,
-                       fp8, scale, err, umfma, n_pad, kp);
+    hipLaunchKernelGGL(k_normalise, dim3((unsigned)ceil_div(o.n_pad, 4)), dim3(256), 0, s, sig, n, k, o);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }
@@ -346,6 +600,74 @@ mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32
 #undef MRC_NC
         default: return fail(MRC_E_INVAL, "k exceeds 1024");
     }
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+int lowp_steps(int precision, int k) {
+    const int step = precision == MRC_PREC_BF16 ? 32 : 128;
+    int nk = (int)ceil_div(k, step);
+    nk += nk & 1;  // even step count
+    return nk;
+}
+
+mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q, int ldq_bytes,
+                               const float* scale, int64_t n, int32_t k, const float* d_lo_thr,
+                               PairSink cand, hipStream_t s) {
+    if (n < 2) return MRC_OK;
+    TileOrder ord;
+    int64_t grid = 0;
+    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
+    const int nk = lowp_steps(precision, k);
+    ScopedTimer tm(ctx, "compare_lowp", s);
+#define MRC_LP(P, c)                                                                                    \
+    case c: {                                                                                           \
+        const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_lowp<P, c>, 256, grid);       \
+        hipLaunchKernelGGL((k_compare_lowp<P, c>), dim3((unsigned)pgrid), dim3(256), 0, s, q, ldq_bytes, scale, \
+                           (int)n, d_lo_thr, ord, cand);                                                \
+    } break;
+    if (precision == MRC_PREC_BF16) {
+        switch (nk) {
+            MRC_LP(MRC_PREC_BF16, 2) MRC_LP(MRC_PREC_BF16, 4) MRC_LP(MRC_PREC_BF16, 6) MRC_LP(MRC_PREC_BF16, 8)
+            MRC_LP(MRC_PREC_BF16, 10) MRC_LP(MRC_PREC_BF16, 12) MRC_LP(MRC_PREC_BF16, 16)
+            MRC_LP(MRC_PREC_BF16, 20) MRC_LP(MRC_PREC_BF16, 24) MRC_LP(MRC_PREC_BF16, 32)
+            default: return fail(MRC_E_INVAL, "unsupported k for the BF16 form");
+        }
+    } else {
+        switch (nk) {
+            MRC_LP(MRC_PREC_FP8, 2) MRC_LP(MRC_PREC_FP8, 4) MRC_LP(MRC_PREC_FP8, 6) MRC_LP(MRC_PREC_FP8, 8)
+            default: return fail(MRC_E_INVAL, "unsupported k for the FP8 form");
+        }
+    }
+#undef MRC_LP
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+// Accumulation slack of a low-precision score relative to |a_i||a_j|. BF16
+// products are exact and the matrix cores accumulate them like FP32 adds
+// (measured deviations of a few FP32 ulps): 3k * 2^-24. The FP8 matrix-core
+// path accumulates with a shorter significand (measured up to ~2^-15
+// relative on the signature workloads); the slack used is 2^-10.
+float lowp_acc_unit(int precision, int k) {
+    const double bf = 3.0 * k * 5.9604644775390625e-08;
+    return (float)(precision == MRC_PREC_FP8 ? std::max(bf, 9.765625e-04) : bf);
+}
+
+mrc_status launch_lowp_threshold(mrc_ctx* ctx, int precision, const float* err, int64_t n, float tau,
+                                 float nominal, int k, float* d_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_lowp_threshold, dim3(1), dim3(1024), 0, s, err, n, tau, nominal,
+                       lowp_acc_unit(precision, k), d_out);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+mrc_status launch_rescore2(mrc_ctx* ctx, int precision, const mrc_pair* cand, const unsigned long long* n_cand,
+                           int64_t cand_cap, const float* unit, int32_t k, const float* err, float tau, float nominal,
+                           PairSink out, unsigned long long* stats, hipStream_t s) {
+    ScopedTimer tm(ctx, "rescore", s);
+    hipLaunchKernelGGL(k_rescore, dim3(1024), dim3(256), 0, s, cand, n_cand, cand_cap, unit, k, err, tau, nominal,
+                       lowp_acc_unit(precision, k), out, stats);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }
