@@ -407,4 +407,49 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
     return fail(MRC_E_STATE, "mrc_compare: unreachable");
 }
 
+// ------------------------------------------------------------------ comparators
+
+static mrc_status ensure_hashes(mrc_ctx* ctx, const mrc_model* model, hipStream_t s) {
+    mrc_model* m = const_cast<mrc_model*>(model);
+    if (m->d_hash) return MRC_OK;
+    MRC_TRY(dev_alloc(ctx, (void**)&m->d_hash, (size_t)m->vocab * 8));
+    return launch_term_hashes(ctx, m->vocab, m->d_hash, s);
+}
+
+mrc_status mrc_term_hashes(mrc_ctx* ctx, const mrc_model* model, uint64_t* out, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_term_hashes"));
+    if (!model || !out) return fail(MRC_E_INVAL, "mrc_term_hashes: NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_TRY(ensure_hashes(ctx, model, s));
+    MRC_HIP_TRY(ctx, hipMemcpyAsync(out, model->d_hash, (size_t)model->vocab * 8, hipMemcpyDeviceToDevice, s));
+    MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
+    return MRC_OK;
+}
+
+mrc_status mrc_simhash(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, uint64_t* out, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_simhash"));
+    MRC_TRY(check_docs(docs, "mrc_simhash"));
+    if (!model || (docs->n_docs > 0 && !out)) return fail(MRC_E_INVAL, "mrc_simhash: NULL argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_TRY(ensure_hashes(ctx, model, s));
+    MRC_TRY(launch_simhash(ctx, docs, model->vocab, model->d_hash, out, s));
+    return sync_flags(ctx, s, 1, "mrc_simhash");
+}
+
+mrc_status mrc_hamming_pairs(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32_t max_dist, mrc_pair* pairs_out,
+                             int64_t capacity, int64_t* n_found, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_hamming_pairs"));
+    if (!n_found || n < 0 || n > 0x7FFFFFFFLL || (n > 0 && !sim) || max_dist < 0 || capacity < 0 ||
+        (capacity > 0 && !pairs_out))
+        return fail(MRC_E_INVAL, "mrc_hamming_pairs: bad argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 8 * sizeof(int64_t), s));
+    PairSink sink{pairs_out, capacity, (unsigned long long*)(ctx->d_flags + 4)};
+    MRC_TRY(launch_hamming(ctx, sim, n, max_dist, sink, s));
+    MRC_TRY(sync_flags(ctx, s, 8, "mrc_hamming_pairs"));
+    *n_found = ctx->h_flags[4];
+    if (*n_found > capacity) return fail(MRC_E_OVERFLOW, "mrc_hamming_pairs: more pairs than capacity");
+    return MRC_OK;
+}
+
 }  // extern "C"

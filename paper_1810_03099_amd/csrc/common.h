@@ -129,6 +129,10 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------- stage launchers
 // Each returns MRC_OK or an error; all work is enqueued on `s`.
 
+// Clear the error word and check offsets on the device (kErrOffsets = bit 0);
+// the document kernels return at once when it is set.
+mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s);
+
 // df over a corpus: one increment per distinct (document, term). Also checks
 // offsets and token ids (error bits in ctx->d_flags[0]).
 mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s);
@@ -186,7 +190,7 @@ mrc_status launch_score_pairs(mrc_ctx* ctx, const float* unit, int32_t k, const 
 
 // Comparators.
 mrc_status launch_term_hashes(mrc_ctx* ctx, int32_t vocab, uint64_t* out, hipStream_t s);
-mrc_status launch_simhash(mrc_ctx* ctx, const mrc_docs* docs, const uint64_t* d_hash,
+mrc_status launch_simhash(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, const uint64_t* d_hash,
                           uint64_t* out, hipStream_t s);
 mrc_status launch_hamming(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32_t max_dist,
                           PairSink sink, hipStream_t s);

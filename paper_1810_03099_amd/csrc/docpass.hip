@@ -317,11 +317,8 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* 
                        hipStream_t s, const char* name) {
     const int64_t n = docs->n_docs;
     unsigned long long* err = (unsigned long long*)ctx->d_flags;
-    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(int64_t), s));
+    MRC_TRY(launch_validate_offsets(ctx, docs, s));
     if (n == 0) return MRC_OK;
-    hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, docs->offsets, n,
-                       docs->n_tokens, err);
-    MRC_HIP_TRY(ctx, hipGetLastError());
     const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
     const size_t rep_bytes = (size_t)kDfReplicas * (size_t)V * sizeof(uint32_t);
     void* rep = nullptr;
@@ -368,6 +365,16 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* 
 }  // namespace
 
 namespace mrc {
+
+mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s) {
+    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(int64_t), s));
+    const int64_t n = docs->n_docs;
+    if (n == 0) return MRC_OK;
+    hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, docs->offsets, n,
+                       docs->n_tokens, (unsigned long long*)ctx->d_flags);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
 
 mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s) {
     SignArgs sa{};

@@ -4,9 +4,6 @@
 using namespace mrc;
 
 extern "C" {
-mrc_status mrc_simhash(mrc_ctx*, const mrc_model*, const mrc_docs*, uint64_t*, void*) { return fail(MRC_E_STATE, "mrc_simhash: not available"); }
-mrc_status mrc_term_hashes(mrc_ctx*, const mrc_model*, uint64_t*, void*) { return fail(MRC_E_STATE, "mrc_term_hashes: not available"); }
-mrc_status mrc_hamming_pairs(mrc_ctx*, const uint64_t*, int64_t, int32_t, mrc_pair*, int64_t, int64_t*, void*) { return fail(MRC_E_STATE, "not available"); }
 mrc_status mrc_exact_cosine(mrc_ctx*, const mrc_model*, const mrc_docs*, float, mrc_pair*, int64_t, int64_t*, void*) { return fail(MRC_E_STATE, "not available"); }
 mrc_status mrc_db_create(mrc_ctx*, int64_t, int32_t, uint32_t, mrc_db**) { return fail(MRC_E_STATE, "not available"); }
 mrc_status mrc_db_destroy(mrc_db*) { return fail(MRC_E_STATE, "not available"); }

@@ -1,0 +1,84 @@
+"""GPU parity of the comparators: MD5 term hashes, Simhash-64 words and
+Hamming pairs (integers, bit-exact against the oracle), and exact cosine."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import comparators as oc
+from oracle import mrc as om
+from synth import corpus as synth
+from tests.gpu_util import device_docs, flush, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.mrc_ctx_create(0)
+
+
+def _model(lib, ctx, c, k=16):
+    o, t = device_docs(c)
+    return lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(k, mode=lib.SEL_ALL)), o, t
+
+
+def test_md5_term_hashes_bit_exact(lib, ctx):
+    c = synth.generate(1, n_docs=300)
+    gm, _, _ = _model(lib, ctx, c)
+    got = lib.mrc_term_hashes(ctx, gm).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, oc.md5_term_hashes(c.vocab))
+
+
+@pytest.mark.parametrize("cfg,n_docs", [(0, None), (1, 2500)])
+def test_simhash_bit_exact(lib, ctx, cfg, n_docs):
+    c = synth.generate(cfg, n_docs=n_docs)
+    gm, o, t = _model(lib, ctx, c)
+    got = lib.mrc_simhash(ctx, gm, o, t).cpu().numpy().view(np.uint64)
+    np.testing.assert_array_equal(got, oc.simhash64(c.offsets, c.tokens, c.vocab))
+
+
+def test_simhash_edge_documents(lib, ctx):
+    rng = np.random.default_rng(2)
+    V = 5000
+    docs = [np.zeros(0, np.int32), np.array([V - 1]), np.array([3, 9]), np.full(50_000, 11), rng.integers(0, V, 9000),
+            rng.integers(0, V, 65), rng.integers(0, V, 64), rng.integers(0, V, 63)]
+    c = synth.from_docs(docs, V)
+    gm, o, t = _model(lib, ctx, c, k=4)
+    got = lib.mrc_simhash(ctx, gm, o, t).cpu().numpy().view(np.uint64)
+    h = oc.md5_term_hashes(V)
+    np.testing.assert_array_equal(got, oc.simhash64(c.offsets, c.tokens, V, h))
+    assert got[0] == 0 and got[1] == h[V - 1] and got[2] == (h[3] & h[9])
+
+
+@pytest.mark.parametrize("n,max_dist", [(2000, 3), (5000, 6), (1, 3), (2, 3), (257, 0)])
+def test_hamming_pairs_exact(lib, ctx, n, max_dist):
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 2 ** 63, n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, n, dtype=np.uint64)
+    for a in range(0, n - 1, 7):     # planted near copies
+        flip = rng.integers(0, 64, int(rng.integers(0, 5)))
+        m = np.uint64(0)
+        for f in flip:
+            m |= np.uint64(1) << np.uint64(int(f))
+        x[a + 1] = x[a] ^ m
+    got = lib.mrc_hamming_pairs(ctx, torch.from_numpy(x.view(np.int64)).cuda(), max_dist)
+    gi, gj, gd, _ = lib.pairs_to_numpy(got)
+    oi, oj, od = oc.hamming_pairs(x, max_dist)
+    assert set(zip(gi.tolist(), gj.tolist(), gd.astype(np.int64).tolist())) == \
+        set(zip(oi.tolist(), oj.tolist(), od.tolist()))
+
+
+def test_simhash_hamming_on_corpus(lib, ctx):
+    c = synth.generate(0)
+    gm, o, t = _model(lib, ctx, c)
+    sim = lib.mrc_simhash(ctx, gm, o, t)
+    got = lib.mrc_hamming_pairs(ctx, sim, 3)
+    gi, gj, gd, _ = lib.pairs_to_numpy(got)
+    osim = oc.simhash64(c.offsets, c.tokens, c.vocab)
+    oi, oj, od = oc.hamming_pairs(osim, 3)
+    assert set(zip(gi.tolist(), gj.tolist())) == set(zip(oi.tolist(), oj.tolist()))
+    flush(f"  simhash pairs <= 3: {gi.size}")
