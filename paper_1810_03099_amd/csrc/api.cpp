@@ -11,7 +11,7 @@ using namespace mrc;
 
 namespace {
 
-constexpr uint64_t kErrOffsets = 1, kErrToken = 2, kErrSelection = 4;
+constexpr uint64_t kErrOffsets = 1, kErrToken = 2, kErrSelection = 4, kErrTailCap = 8;
 
 mrc_status check_ctx(mrc_ctx* ctx, const char* fn) {
     if (!ctx) return fail(MRC_E_INVAL, std::string(fn) + ": ctx is NULL");
@@ -45,6 +45,8 @@ mrc_status sync_flags(mrc_ctx* ctx, hipStream_t s, int n_words, const char* fn) 
     if (err & kErrToken) return fail(MRC_E_INVAL, std::string(fn) + ": token id outside [0, vocab)");
     if (err & kErrSelection)
         return fail(MRC_E_INVAL, std::string(fn) + ": reference selection holds fewer terms than k");
+    if (err & kErrTailCap)
+        return fail(MRC_E_INVAL, std::string(fn) + ": a document has more than 16384 distinct terms past the dense head");
     return MRC_OK;
 }
 
@@ -449,6 +451,22 @@ mrc_status mrc_hamming_pairs(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32
     MRC_TRY(sync_flags(ctx, s, 8, "mrc_hamming_pairs"));
     *n_found = ctx->h_flags[4];
     if (*n_found > capacity) return fail(MRC_E_OVERFLOW, "mrc_hamming_pairs: more pairs than capacity");
+    return MRC_OK;
+}
+
+mrc_status mrc_exact_cosine(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float tau, mrc_pair* pairs_out,
+                            int64_t capacity, int64_t* n_found, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_exact_cosine"));
+    MRC_TRY(check_docs(docs, "mrc_exact_cosine"));
+    if (!model || !n_found || capacity < 0 || (capacity > 0 && !pairs_out) || !(tau == tau))
+        return fail(MRC_E_INVAL, "mrc_exact_cosine: bad argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 8 * sizeof(int64_t), s));
+    PairSink sink{pairs_out, capacity, (unsigned long long*)(ctx->d_flags + 4)};
+    MRC_TRY(launch_exact_cosine(ctx, model, docs, tau, sink, s));
+    MRC_TRY(sync_flags(ctx, s, 8, "mrc_exact_cosine"));
+    *n_found = ctx->h_flags[4];
+    if (*n_found > capacity) return fail(MRC_E_OVERFLOW, "mrc_exact_cosine: more pairs than capacity");
     return MRC_OK;
 }
 

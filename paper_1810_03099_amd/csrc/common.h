@@ -137,6 +137,19 @@ mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream
 // offsets and token ids (error bits in ctx->d_flags[0]).
 mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s);
 
+// Unit TF-IDF vectors of a batch for the exact-cosine comparator: ranks < H in
+// a dense [n_pad][ldh] matrix (matrix-core layout), the rest listed per
+// document at its token offset.
+struct CsrOut {
+    int H, ldh;
+    float* wh;
+    int32_t* ent_rank;
+    float* ent_w;
+    int32_t* nnz_tail;
+    uint32_t* pcount;   // [V - H] entries per tail rank
+};
+mrc_status launch_csr(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const CsrOut& c, hipStream_t s);
+
 // Model tables from df: idf, stable rank sort, selection, parts, reference norms.
 mrc_status launch_model_tables(mrc_ctx* ctx, mrc_model* m, hipStream_t s);
 
@@ -281,6 +294,11 @@ constexpr int kFp64NormMin = 10000;  // norms of longer documents accumulate in 
 namespace mrc_dev {
 
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Column position of component c in the FP32 matrix-core layout: inside each
+// block of 16 components the 4x4 sub-blocks are transposed, so that lane group
+// g loading 4 consecutive floats at 4g feeds MFMA step m with component 4m + g.
+__host__ __device__ __forceinline__ int mfma_col(int c) { return (c & ~15) | ((c & 3) << 2) | ((c >> 2) & 3); }
 
 // Fixed-order wavefront sum (butterfly over 64 lanes). Every lane receives
 // the same value, computed by the same tree regardless of data.

@@ -55,10 +55,7 @@ __device__ __forceinline__ float e4m3fn_value(uint8_t c) {
 // One wavefront per row; k <= 64 * kMaxPerLane.
 constexpr int kMaxPerLane = 16;
 
-// Column position of component c in the matrix-core layout: inside each block
-// of 16 components the 4x4 sub-blocks are transposed, so that lane group g
-// loading 4 consecutive floats at 4g feeds MFMA step m with component 4m + g.
-__device__ __forceinline__ int mfma_col(int c) { return (c & ~15) | ((c & 3) << 2) | ((c >> 2) & 3); }
+using mrc_dev::mfma_col;
 
 // Output layouts of k_normalise (NormLayout): leading dimensions let the comparison
 // kernels use zero-padded internal copies (rows padded to n_pad, columns to ld).

@@ -70,9 +70,36 @@ struct SignArgs {
     int ref_idf;       // 1: rho_t = idf_t, so c_p = idf^2
     float* sig;
     float* norm;
+    // MODE_CSR: unit TF-IDF weights w = tf * idf / |w_d| of each distinct term.
+    // Ranks below H go to the dense head matrix (matrix-core layout, ld ldh);
+    // the others are listed at the document's token offset (ent_*), counted
+    // per rank in pcount, and their number stored in nnz_tail.
+    const int32_t* rank_of;
+    int H;
+    int ldh;
+    float* wh;
+    int32_t* ent_rank;
+    float* ent_w;
+    int32_t* nnz_tail;
+    uint32_t* pcount;
 };
 
-enum { MODE_DF = 0, MODE_SIGN = 1 };
+enum { MODE_DF = 0, MODE_SIGN = 1, MODE_CSR = 2 };
+
+// Emit one distinct term of document d (MODE_CSR).
+__device__ __forceinline__ void csr_emit(const SignArgs& sa, int64_t d, int64_t o, int t, unsigned tf, double nrm,
+                                         int* tcount) {
+    const float w = (float)((double)tf * (double)sa.tinfo[t].idf / nrm);
+    const int r = sa.rank_of[t];
+    if (r < sa.H) {
+        sa.wh[d * sa.ldh + mrc_dev::mfma_col(r)] = w;
+    } else {
+        const int e = atomicAdd(tcount, 1);
+        sa.ent_rank[o + e] = r;
+        sa.ent_w[o + e] = w;
+        atomicAdd(&sa.pcount[r - sa.H], 1u);
+    }
+}
 
 // Offsets check before any token is read: offsets[0] = 0, non-decreasing,
 // offsets[n] <= n_tokens. Sets kErrOffsets; the document kernels then return
@@ -169,7 +196,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
                     TermInfo ti = sa.tinfo[t];
                     slot_r[r] = h;
                     idf_r[r] = ti.idf;
-                    if (ti.part >= 0) {
+                    if (MODE == MODE_SIGN && ti.part >= 0) {
                         float c = sa.ref_idf ? ti.idf * ti.idf : ti.idf;
                         atomicAdd(&bins[ti.part], mrc_dev::fixed32(c));
                     }
@@ -177,14 +204,17 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
             }
         }
         team_sync<TEAM>();
-        if constexpr (MODE == MODE_SIGN) {
+        double nrm = 0.0;
+        if constexpr (MODE != MODE_DF) {
             float nacc = 0.f;
 #pragma unroll
             for (int r = 0; r < MAXPER; ++r) {
                 if (slot_r[r] >= 0) nacc += (float)cnt[slot_r[r]] * (idf_r[r] * idf_r[r]);
             }
             float n2 = team_sum<TEAM, float>(nacc, (float*)red);
-            double nrm = (double)sqrtf(n2);
+            nrm = (double)sqrtf(n2);
+        }
+        if constexpr (MODE == MODE_SIGN) {
             float* out = sa.sig + (int64_t)d * sa.k;
             for (int j = tid; j < sa.k; j += TEAM) {
                 double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
@@ -194,6 +224,18 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
         }
         team_sync<TEAM>();
         const int nu = *nused;
+        if constexpr (MODE == MODE_CSR) {
+            int* tcount = (int*)red;
+            if (tid == 0) *tcount = 0;
+            team_sync<TEAM>();
+            for (int u = tid; u < nu; u += TEAM) {
+                const int sl = used[u];
+                csr_emit(sa, d, o, keys[sl], (unsigned)cnt[sl], nrm, tcount);
+            }
+            team_sync<TEAM>();
+            if (tid == 0) sa.nnz_tail[d] = *tcount;
+            team_sync<TEAM>();
+        }
         for (int u = tid; u < nu; u += TEAM) {
             const int s = used[u];
             keys[s] = kEmpty;
@@ -238,7 +280,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
             unsigned old = atomicAdd(&cnt[t], 1u);
             if constexpr (MODE == MODE_DF) {
                 if (old == 0) atomicAdd(&dfr[t], 1u);
-            } else {
+            } else if constexpr (MODE == MODE_SIGN) {
                 (void)old;
                 TermInfo ti = sa.tinfo[t];
                 if (ti.part >= 0) {
@@ -249,7 +291,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
         }
         __threadfence();
         __syncthreads();
-        if constexpr (MODE == MODE_SIGN) {
+        if constexpr (MODE != MODE_DF) {
             double nrm;
             if (L > kFp64NormMin) {
                 double acc = 0.0;
@@ -272,12 +314,27 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
                 }
                 nrm = (double)sqrtf(team_sum<kBlock, float>(acc, (float*)red));
             }
-            float* out = sa.sig + (int64_t)d * sa.k;
-            for (int j = tid; j < sa.k; j += kBlock) {
-                double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
-                out[j] = (float)v;
+            if constexpr (MODE == MODE_SIGN) {
+                float* out = sa.sig + (int64_t)d * sa.k;
+                for (int j = tid; j < sa.k; j += kBlock) {
+                    double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
+                    out[j] = (float)v;
+                }
+                if (tid == 0 && sa.norm) sa.norm[d] = (float)nrm;
+            } else {
+                // each distinct term once: the first occurrence to swap its count out emits it
+                int* tcount = (int*)(red + 2);
+                if (tid == 0) *tcount = 0;
+                __syncthreads();
+                for (int64_t p = tid; p < L; p += kBlock) {
+                    const int t = tok[o + p];
+                    if ((unsigned)t >= (unsigned)V) continue;
+                    const unsigned tf = atomicExch(&cnt[t], 0u);
+                    if (tf > 0) csr_emit(sa, d, o, t, tf, nrm, tcount);
+                }
+                __syncthreads();
+                if (tid == 0) sa.nnz_tail[d] = *tcount;
             }
-            if (tid == 0 && sa.norm) sa.norm[d] = (float)nrm;
         }
         __syncthreads();
         for (int64_t p = tid; p < L; p += kBlock) {
@@ -379,6 +436,20 @@ mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream
 mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s) {
     SignArgs sa{};
     return run_docpass<MODE_DF>(ctx, docs, vocab, d_df, sa, s, "df");
+}
+
+mrc_status launch_csr(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const CsrOut& c, hipStream_t s) {
+    SignArgs sa{};
+    sa.tinfo = m->d_tinfo;
+    sa.rank_of = m->d_rank_of;
+    sa.H = c.H;
+    sa.ldh = c.ldh;
+    sa.wh = c.wh;
+    sa.ent_rank = c.ent_rank;
+    sa.ent_w = c.ent_w;
+    sa.nnz_tail = c.nnz_tail;
+    sa.pcount = c.pcount;
+    return run_docpass<MODE_CSR>(ctx, docs, m->vocab, nullptr, sa, s, "csr");
 }
 
 mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, float* sig_out,

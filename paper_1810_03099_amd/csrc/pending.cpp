@@ -4,7 +4,6 @@
 using namespace mrc;
 
 extern "C" {
-mrc_status mrc_exact_cosine(mrc_ctx*, const mrc_model*, const mrc_docs*, float, mrc_pair*, int64_t, int64_t*, void*) { return fail(MRC_E_STATE, "not available"); }
 mrc_status mrc_db_create(mrc_ctx*, int64_t, int32_t, uint32_t, mrc_db**) { return fail(MRC_E_STATE, "not available"); }
 mrc_status mrc_db_destroy(mrc_db*) { return fail(MRC_E_STATE, "not available"); }
 mrc_status mrc_db_insert(mrc_db*, const float*, int64_t, int64_t*, void*) { return fail(MRC_E_STATE, "not available"); }

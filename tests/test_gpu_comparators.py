@@ -82,3 +82,43 @@ def test_simhash_hamming_on_corpus(lib, ctx):
     oi, oj, od = oc.hamming_pairs(osim, 3)
     assert set(zip(gi.tolist(), gj.tolist())) == set(zip(oi.tolist(), oj.tolist()))
     flush(f"  simhash pairs <= 3: {gi.size}")
+
+
+@pytest.mark.parametrize("cfg,n_docs,tau", [(0, None, 0.9), (1, 3000, 0.9), (1, 1500, 0.5), (0, 300, 0.2)])
+def test_exact_cosine_matches_oracle(lib, ctx, cfg, n_docs, tau):
+    """GPU FP32 exact cosine vs the FP64 oracle: same pair set except pairs
+    within 1e-5 of tau, scores within 1e-5."""
+    c = synth.generate(cfg, n_docs=n_docs)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(16))
+    got = lib.mrc_exact_cosine(ctx, gm, o, t, tau)
+    gi, gj, gs, _ = lib.pairs_to_numpy(got)
+    omodel = om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=16))
+    oi, oj, os_ = oc.exact_cosine_pairs(c.offsets, c.tokens, omodel, tau)
+    g = set(zip(gi.tolist(), gj.tolist()))
+    w = set(zip(oi.tolist(), oj.tolist()))
+    diff = g ^ w
+    if diff:
+        di = np.array([p[0] for p in diff])
+        dj = np.array([p[1] for p in diff])
+        s64 = oc.exact_cosine_scores(c.offsets, c.tokens, omodel, di, dj)
+        assert np.all(np.abs(s64 - tau) <= 1e-5), "pair sets differ away from the threshold"
+    s64 = oc.exact_cosine_scores(c.offsets, c.tokens, omodel, gi, gj)
+    assert np.abs(gs - s64).max() <= 1e-5
+    flush(f"  exact cosine n={c.n_docs} tau={tau}: {gi.size} pairs, {len(diff)} near-tie differences")
+
+
+def test_exact_cosine_edge_documents(lib, ctx):
+    rng = np.random.default_rng(8)
+    V = 3000
+    base = rng.integers(0, V, 300)
+    docs = [np.zeros(0, np.int32), base, base.copy(), rng.permutation(base), np.array([5]), np.array([5]),
+            rng.integers(0, V, 6000), rng.integers(0, V, 50)]
+    c = synth.from_docs(docs, V)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, V, lib.ref_spec(4))
+    got = lib.mrc_exact_cosine(ctx, gm, o, t, 0.999)
+    gi, gj, gs, _ = lib.pairs_to_numpy(got)
+    pairs = set(zip(gi.tolist(), gj.tolist()))
+    assert {(1, 2), (1, 3), (2, 3), (4, 5)} <= pairs
+    assert not any(0 in p for p in pairs)            # empty document pairs with nothing
