@@ -85,14 +85,15 @@ struct mrc_model {
 struct mrc_db {
     mrc_ctx* ctx = nullptr;
     int64_t capacity = 0;
+    int64_t cap_pad = 0;         // capacity rounded up to 64 rows (padding rows stay zero)
     int32_t k = 0;
     uint32_t precisions = 0;
     int64_t size = 0;            // committed rows
-    float* d_unit = nullptr;     // [capacity][k]
-    uint16_t* d_bf16 = nullptr;  // [capacity][k]
-    uint8_t* d_fp8 = nullptr;    // [capacity][k]
-    float* d_scale = nullptr;    // [capacity]
-    float* d_err = nullptr;      // [2][capacity]: bf16 then fp8 row error bounds
+    float* d_unit = nullptr;     // [cap_pad][kp] unit signatures, FP32 matrix-core layout
+    uint16_t* d_bf16 = nullptr;  // [cap_pad][ldb]
+    uint8_t* d_fp8 = nullptr;    // [cap_pad][ld8]
+    float* d_scale = nullptr;    // [cap_pad]
+    float* d_err = nullptr;      // [2][cap_pad]: bf16 then fp8 row error bounds
     size_t bytes = 0;
     std::mutex mu;
 };
@@ -209,6 +210,14 @@ mrc_status launch_hamming(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32_t 
                           PairSink sink, hipStream_t s);
 mrc_status launch_exact_cosine(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, float tau,
                                PairSink sink, hipStream_t s);
+
+// Leading dimensions (elements) of the database / query layouts for k.
+struct DbLayout {
+    int kp;    // FP32 matrix-core layout
+    int ldb;   // BF16 codes
+    int ld8;   // FP8 codes
+};
+DbLayout db_layout(int32_t k);
 
 // Query top-k against a database.
 mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t db_rows, const mrc_model* m,

@@ -1,0 +1,542 @@
+// Query against a resident signature database (Section 1: each new page is
+// compared with all stored pages through the signatures).
+//
+// For every query: the topk database rows of highest MRC (score descending,
+// id ascending) and the number of rows with MRC >= tau.
+//
+// Queries go in groups of 16 as the B operand of 16x16 matrix-core tiles
+// whose A operand is 64 database rows, so lane (li, lg) of a wavefront holds
+// the scores of query li against 16 of the 64 rows; it keeps a private
+// top-16 list in registers while the wavefront streams its share of the
+// database. Lists are merged per workgroup in LDS, then per query.
+//
+// FP32 scores are the plain chain (exact). For BF16/FP8 a first pass gives
+// the low-precision 16th score L16; a second pass collects every row whose
+// low-precision score is >= min(L16 - 2 delta, tau - delta) (delta: the
+// largest rescoring band), which provably contains the exact top-16 and all
+// rows >= tau; those candidates are rescored with the FP32 chain.
+#include <algorithm>
+
+#include "common.h"
+
+using namespace mrc;
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kTop = 16;
+constexpr int kTileRows = 64;
+
+template <int PREC> struct QT;
+template <> struct QT<MRC_PREC_FP32> {
+    static constexpr int kChunkBytes = 64, kLaneBytes = 16;
+    struct F { f32x4 v; };
+    __device__ static F load(const uint8_t* p) { return F{*(const f32x4*)p}; }
+    __device__ static f32x4 mma(const F& a, const F& b, f32x4 c) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a.v[m], b.v[m], c, 0, 0, 0);
+        return c;
+    }
+};
+template <> struct QT<MRC_PREC_BF16> {
+    static constexpr int kChunkBytes = 64, kLaneBytes = 16;
+    struct F { i32x4 v; };
+    __device__ static F load(const uint8_t* p) { return F{*(const i32x4*)p}; }
+    __device__ static f32x4 mma(const F& a, const F& b, f32x4 c) {
+        bf16x8 av, bv;
+        __builtin_memcpy(&av, &a.v, 16);
+        __builtin_memcpy(&bv, &b.v, 16);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    }
+};
+template <> struct QT<MRC_PREC_FP8> {
+    static constexpr int kChunkBytes = 128, kLaneBytes = 32;
+    struct F { i32x4 lo, hi; };
+    __device__ static F load(const uint8_t* p) { return F{*(const i32x4*)p, *(const i32x4*)(p + 16)}; }
+    __device__ static f32x4 mma(const F& a, const F& b, f32x4 c) {
+        const i32x8 av = {a.lo[0], a.lo[1], a.lo[2], a.lo[3], a.hi[0], a.hi[1], a.hi[2], a.hi[3]};
+        const i32x8 bv = {b.lo[0], b.lo[1], b.lo[2], b.lo[3], b.hi[0], b.hi[1], b.hi[2], b.hi[3]};
+        return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+    }
+};
+
+// (s, id) ordering of the results: score descending, id ascending.
+__device__ __forceinline__ bool better(float s1, int64_t i1, float s2, int64_t i2) {
+    return s1 > s2 || (s1 == s2 && i1 < i2);
+}
+
+// Insert (v, j) into a list sorted best first; precondition: it beats the last.
+__device__ __forceinline__ void top_insert(float (&s)[kTop], int (&id)[kTop], float v, int j) {
+    bool placed = false;
+#pragma unroll
+    for (int p = kTop - 1; p > 0; --p) {
+        if (!placed) {
+            if (better(v, j, s[p - 1], id[p - 1])) {
+                s[p] = s[p - 1];
+                id[p] = id[p - 1];
+            } else {
+                s[p] = v;
+                id[p] = j;
+                placed = true;
+            }
+        }
+    }
+    if (!placed) {
+        s[0] = v;
+        id[0] = j;
+    }
+}
+
+struct ScanArgs {
+    const uint8_t* db;        // [rows_pad][ld_db] codes (FP32: matrix-core layout floats)
+    int ld_db;                // bytes per row
+    const float* db_scale;    // FP8 row scales
+    int64_t rows;             // database snapshot
+    const uint8_t* q;         // [nq_pad][ld_q] query codes, same layout
+    int ld_q;
+    const float* q_scale;
+    int nq;
+    float tau;
+    // MODE_TOP: per-workgroup top lists and hit counts
+    float* part_s;            // [nq][gx][kTop]
+    int32_t* part_id;
+    int32_t* hits;            // [nq] (FP32 only), zeroed
+    // MODE_COLLECT: candidates with score >= thr[q]
+    const float* thr;
+    int64_t* cand;            // [nq][cap] packed (id << 32 | float bits)
+    int32_t* ccount;          // [nq]
+    int cap;
+};
+
+enum { MODE_TOP = 0, MODE_COLLECT = 1 };
+
+template <int PREC, int NK, int MODE>
+__global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
+    using T = QT<PREC>;
+    __shared__ float ls[16][16][kTop];    // [query][list = wave*4 + lg][entry]
+    __shared__ int lid[16][16][kTop];
+    __shared__ int lhits[16];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    const int q = blockIdx.y * 16 + li;
+    const bool qvalid = q < a.nq;
+    if (threadIdx.x < 16) lhits[threadIdx.x] = 0;
+    __syncthreads();
+    // query fragments for every chunk stay in registers
+    typename T::F qb[NK];
+    const uint8_t* pq = a.q + (int64_t)(blockIdx.y * 16 + li) * a.ld_q + lg * T::kLaneBytes;
+#pragma unroll
+    for (int c = 0; c < NK; ++c) qb[c] = T::load(pq + c * T::kChunkBytes);
+    const float qsc = (PREC == MRC_PREC_FP8) ? a.q_scale[blockIdx.y * 16 + li] : 1.f;
+    const float thr = (MODE == MODE_COLLECT && qvalid) ? a.thr[q] : 0.f;
+    float ts[kTop];
+    int tid_[kTop];
+#pragma unroll
+    for (int p = 0; p < kTop; ++p) {
+        ts[p] = -INFINITY;
+        tid_[p] = 0x7fffffff;
+    }
+    int hits = 0;
+    const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += stride) {
+        const int64_t row0 = t * kTileRows;
+        const uint8_t* pa = a.db + (row0 + li) * a.ld_db + lg * T::kLaneBytes;
+        f32x4 acc[4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) acc[x] = f32x4{0.f, 0.f, 0.f, 0.f};
+        typename T::F fa[2][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x) fa[0][x] = T::load(pa + (int64_t)16 * x * a.ld_db);
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            const int cur = c & 1, nxt = cur ^ 1;
+            if (c + 1 < NK) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x) fa[nxt][x] = T::load(pa + (int64_t)16 * x * a.ld_db + (c + 1) * T::kChunkBytes);
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x) acc[x] = T::mma(fa[cur][x], qb[c], acc[x]);
+        }
+        // lane holds query li against rows row0 + 16x + 4lg + r (ascending ids in this order)
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = row0 + 16 * x + 4 * lg + r;
+                float v = acc[x][r];
+                if (PREC == MRC_PREC_FP8) v = v * a.db_scale[row] * qsc;
+                const bool ok = qvalid && row < a.rows;
+                if (MODE == MODE_TOP) {
+                    if (ok && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1])) top_insert(ts, tid_, v, (int)row);
+                    if (PREC == MRC_PREC_FP32) hits += (ok && v >= a.tau) ? 1 : 0;
+                } else if (ok && v >= thr) {
+                    const int e = atomicAdd(&a.ccount[q], 1);
+                    if (e < a.cap) a.cand[(int64_t)q * a.cap + e] = ((int64_t)row << 32) | (int64_t)__float_as_uint(v);
+                }
+            }
+    }
+    if (MODE == MODE_COLLECT) return;
+    // workgroup merge: 16 lists (4 wavefronts x 4 lane groups) per query
+#pragma unroll
+    for (int p = 0; p < kTop; ++p) {
+        ls[li][wave * 4 + lg][p] = ts[p];
+        lid[li][wave * 4 + lg][p] = tid_[p];
+    }
+    if (PREC == MRC_PREC_FP32 && hits) atomicAdd(&lhits[li], hits);
+    __syncthreads();
+    if (threadIdx.x < 16) {
+        const int qq = blockIdx.y * 16 + threadIdx.x;
+        if (qq < a.nq) {
+            int head[16];
+#pragma unroll
+            for (int l = 0; l < 16; ++l) head[l] = 0;
+            float* os = a.part_s + ((int64_t)qq * gridDim.x + blockIdx.x) * kTop;
+            int32_t* oi = a.part_id + ((int64_t)qq * gridDim.x + blockIdx.x) * kTop;
+            for (int p = 0; p < kTop; ++p) {
+                int bl = 0;
+                float bs = -INFINITY;
+                int bidx = 0x7fffffff;
+                for (int l = 0; l < 16; ++l) {
+                    if (head[l] < kTop) {
+                        const float s = ls[threadIdx.x][l][head[l]];
+                        const int id = lid[threadIdx.x][l][head[l]];
+                        if (better(s, id, bs, bidx)) {
+                            bs = s;
+                            bidx = id;
+                            bl = l;
+                        }
+                    }
+                }
+                os[p] = bs;
+                oi[p] = bidx;
+                head[bl] += 1;
+            }
+            if (PREC == MRC_PREC_FP32 && lhits[threadIdx.x]) atomicAdd(&a.hits[qq], lhits[threadIdx.x]);
+        }
+    }
+}
+
+// Per query: merge the workgroup lists into the final top list (one wavefront
+// per query; each lane first reduces its share of the lists).
+__global__ __launch_bounds__(256) void k_query_merge(const float* __restrict__ part_s, const int32_t* __restrict__ part_id,
+                                                     int gx, int nq, int topk, const int32_t* __restrict__ hits,
+                                                     mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
+                                                     float* __restrict__ l16) {
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    float ts[kTop];
+    int ti[kTop];
+#pragma unroll
+    for (int p = 0; p < kTop; ++p) {
+        ts[p] = -INFINITY;
+        ti[p] = 0x7fffffff;
+    }
+    const int64_t total = (int64_t)gx * kTop;
+    for (int64_t e = lane; e < total; e += 64) {
+        const float v = part_s[(int64_t)q * total + e];
+        const int id = part_id[(int64_t)q * total + e];
+        if (id != 0x7fffffff && better(v, id, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, v, id);
+    }
+    // wavefront merge: repeatedly take the best head across lanes
+    int h = 0;
+    for (int p = 0; p < kTop; ++p) {
+        float hs = -INFINITY;
+        int hi = 0x7fffffff;
+#pragma unroll
+        for (int x = 0; x < kTop; ++x)
+            if (x == h) {
+                hs = ts[x];
+                hi = ti[x];
+            }
+        float bs = hs;
+        int bi = hi;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float os = __shfl_xor(bs, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (better(os, oi, bs, bi)) {
+                bs = os;
+                bi = oi;
+            }
+        }
+        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;   // ids are unique: one lane pops
+        if (lane == 0) {
+            if (p < topk) {
+                out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
+                out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
+                out[(int64_t)q * topk + p].flags = 0;
+            }
+            if (l16 && p == kTop - 1) l16[q] = bs;
+        }
+    }
+    if (lane == 0 && n_hits && hits) n_hits[q] = hits[q];
+}
+
+// thr[q] = min(L16[q] - 2 delta, tau - delta)
+__global__ void k_query_thr(const float* __restrict__ l16, int nq, float tau, const float* __restrict__ delta,
+                            float* __restrict__ thr) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nq) return;
+    const float d = *delta;
+    const float a = l16[q] - 2.f * d;
+    thr[q] = fminf(a, tau - d);
+}
+
+// Exact decisions for the collected candidates of each query (one workgroup
+// per query): FP32 chain over the natural-order query unit vector and the
+// database row in matrix-core layout, then top list and hit count.
+__global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__ cand, const int32_t* __restrict__ ccount,
+                                                     int cap, const float* __restrict__ qunit, int k,
+                                                     const float* __restrict__ db_umfma, int kp, float tau, int topk,
+                                                     mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
+                                                     unsigned long long* __restrict__ err) {
+    __shared__ float ss[4][kTop];
+    __shared__ int si[4][kTop];
+    __shared__ int shits;
+    const int q = blockIdx.x;
+    const int nc = ccount[q];
+    if (nc > cap) {
+        if (threadIdx.x == 0) atomicOr(err, 16ull);
+        return;
+    }
+    if (threadIdx.x == 0) shits = 0;
+    __syncthreads();
+    float ts[kTop];
+    int ti[kTop];
+#pragma unroll
+    for (int p = 0; p < kTop; ++p) {
+        ts[p] = -INFINITY;
+        ti[p] = 0x7fffffff;
+    }
+    int hits = 0;
+    const float* qu = qunit + (int64_t)q * k;
+    for (int e = threadIdx.x; e < nc; e += 256) {
+        const int64_t pk = cand[(int64_t)q * cap + e];
+        const int row = (int)(pk >> 32);
+        const float* dr = db_umfma + (int64_t)row * kp;
+        float acc = 0.f;
+        for (int c = 0; c < k; ++c) acc = __builtin_fmaf(qu[c], dr[mrc_dev::mfma_col(c)], acc);
+        hits += acc >= tau ? 1 : 0;
+        if (better(acc, row, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, acc, row);
+    }
+    // merge 256 lists: within each wavefront, then across the 4 in LDS
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int h = 0;
+    for (int p = 0; p < kTop; ++p) {
+        float hs = -INFINITY;
+        int hi = 0x7fffffff;
+#pragma unroll
+        for (int x = 0; x < kTop; ++x)
+            if (x == h) {
+                hs = ts[x];
+                hi = ti[x];
+            }
+        float bs = hs;
+        int bi = hi;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float os = __shfl_xor(bs, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (better(os, oi, bs, bi)) {
+                bs = os;
+                bi = oi;
+            }
+        }
+        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;
+        if (lane == 0) {
+            ss[w][p] = bs;
+            si[w][p] = bi;
+        }
+    }
+    hits = mrc_dev::wave_sum(hits);
+    if (lane == 0) atomicAdd(&shits, hits);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int hd[4] = {0, 0, 0, 0};
+        for (int p = 0; p < topk; ++p) {
+            int bw = 0;
+            float bs = -INFINITY;
+            int bi = 0x7fffffff;
+            for (int x = 0; x < 4; ++x) {
+                if (hd[x] < kTop && better(ss[x][hd[x]], si[x][hd[x]], bs, bi)) {
+                    bs = ss[x][hd[x]];
+                    bi = si[x][hd[x]];
+                    bw = x;
+                }
+            }
+            hd[bw] += 1;
+            out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
+            out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
+            out[(int64_t)q * topk + p].flags = 1;
+        }
+        n_hits[q] = shits;
+    }
+}
+
+__global__ void k_max_err(const float* __restrict__ e1, int64_t n1, const float* __restrict__ e2, int64_t n2,
+                          float nominal, float acc_unit, float* __restrict__ delta) {
+    __shared__ float red[16];
+    float m = 0.f;
+    for (int64_t i = threadIdx.x; i < n1; i += 1024) m = fmaxf(m, e1[i]);
+    for (int64_t i = threadIdx.x; i < n2; i += 1024) m = fmaxf(m, e2[i]);
+    m = mrc_dev::wave_max(m);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float e = 0.f;
+        for (int w = 0; w < 16; ++w) e = fmaxf(e, red[w]);
+        const float b = e + e + e * e + acc_unit * (1.f + e) * (1.f + e) + 9.5367431640625e-07f;
+        delta[0] = fmaxf(nominal, b);
+    }
+}
+
+template <int PREC, int MODE>
+mrc_status launch_scan(mrc_ctx* ctx, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+#define MRC_Q(c) case c: hipLaunchKernelGGL((k_query_scan<PREC, c, MODE>), grid, dim3(256), 0, s, a); break;
+    if (PREC == MRC_PREC_FP32) {
+        switch (nk) {
+            MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) MRC_Q(24) MRC_Q(32)
+            default: return fail(MRC_E_INVAL, "query: unsupported k");
+        }
+    } else if (PREC == MRC_PREC_BF16) {
+        switch (nk) {
+            MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(10) MRC_Q(12) MRC_Q(16)
+            default: return fail(MRC_E_INVAL, "query: unsupported k");
+        }
+    } else {
+        switch (nk) {
+            MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8)
+            default: return fail(MRC_E_INVAL, "query: unsupported k");
+        }
+    }
+#undef MRC_Q
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+}  // namespace
+
+namespace mrc {
+
+// Database layouts (shared with the insert path).
+DbLayout db_layout(int32_t k) {
+    DbLayout L;
+    L.kp = 16 * mfma_chunks(k);
+    L.ldb = lowp_steps(MRC_PREC_BF16, k) * 32;
+    L.ld8 = lowp_steps(MRC_PREC_FP8, k) * 128;
+    return L;
+}
+
+mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_model* m, const mrc_docs* qd,
+                     int32_t topk, float tau, int32_t precision, mrc_hit* topk_out, int32_t* n_hits, hipStream_t s) {
+    const int64_t nq = qd->n_docs;
+    const int k = db->k;
+    const DbLayout L = db_layout(k);
+    const int64_t nq_pad = ceil_div(nq > 0 ? nq : 1, 64) * 64;
+    // sign and normalise the queries into every layout the scan needs
+    void *sig, *unit, *umf, *qb, *q8, *qsc, *qerr;
+    MRC_TRY(scratch(ctx, "q_sig", (size_t)nq_pad * k * 4, &sig));
+    MRC_TRY(scratch(ctx, "q_unit", (size_t)nq_pad * k * 4, &unit));
+    MRC_TRY(scratch(ctx, "q_umfma", (size_t)nq_pad * L.kp * 4, &umf));
+    MRC_TRY(scratch(ctx, "q_bf16", (size_t)nq_pad * L.ldb * 2, &qb));
+    MRC_TRY(scratch(ctx, "q_fp8", (size_t)nq_pad * L.ld8, &q8));
+    MRC_TRY(scratch(ctx, "q_scale", (size_t)nq_pad * 4, &qsc));
+    MRC_TRY(scratch(ctx, "q_err", (size_t)2 * nq_pad * 4, &qerr));
+    MRC_TRY(launch_sign(ctx, m, qd, (float*)sig, nullptr, s));
+    NormLayout o{(float*)unit, k, (uint16_t*)qb, L.ldb, (uint8_t*)q8, L.ld8, (float*)qsc, (float*)qerr, nq_pad,
+                 (float*)umf, L.kp, nq_pad};
+    MRC_TRY(launch_normalise_rows(ctx, (const float*)sig, nq, k, o, s));
+    if (nq == 0) return MRC_OK;
+    const int groups = (int)ceil_div(nq, 16);
+    const int64_t tiles = std::max<int64_t>(1, ceil_div(rows, kTileRows));
+    int gx = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), ceil_div(tiles, 4)));
+    dim3 grid(gx, groups);
+    void *ps, *pi, *hits;
+    MRC_TRY(scratch(ctx, "q_part_s", (size_t)nq * gx * kTop * 4, &ps));
+    MRC_TRY(scratch(ctx, "q_part_id", (size_t)nq * gx * kTop * 4, &pi));
+    MRC_TRY(scratch(ctx, "q_hits", (size_t)nq * 4, &hits));
+    MRC_HIP_TRY(ctx, hipMemsetAsync(hits, 0, (size_t)nq * 4, s));
+    ScanArgs a{};
+    a.rows = rows;
+    a.nq = (int)nq;
+    a.tau = tau;
+    a.part_s = (float*)ps;
+    a.part_id = (int32_t*)pi;
+    a.hits = (int32_t*)hits;
+    ScopedTimer tm(ctx, "query", s);
+    if (precision == MRC_PREC_FP32) {
+        a.db = (const uint8_t*)db->d_unit;
+        a.ld_db = L.kp * 4;
+        a.q = (const uint8_t*)umf;
+        a.ld_q = L.kp * 4;
+        MRC_TRY((launch_scan<MRC_PREC_FP32, MODE_TOP>(ctx, L.kp / 16, a, grid, s)));
+        hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
+                           (const int32_t*)pi, gx, (int)nq, topk, (const int32_t*)hits, topk_out, n_hits,
+                           (float*)nullptr);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+        return MRC_OK;
+    }
+    if ((precision == MRC_PREC_BF16 && !db->d_bf16) || (precision == MRC_PREC_FP8 && !db->d_fp8))
+        return fail(MRC_E_STATE, "mrc_query: the database holds no copy in this precision");
+    const bool bf = precision == MRC_PREC_BF16;
+    a.db = bf ? (const uint8_t*)db->d_bf16 : db->d_fp8;
+    a.ld_db = bf ? L.ldb * 2 : L.ld8;
+    a.db_scale = db->d_scale;
+    a.q = bf ? (const uint8_t*)qb : (const uint8_t*)q8;
+    a.ld_q = a.ld_db;
+    a.q_scale = (const float*)qsc;
+    const int nk = bf ? L.ldb / 32 : L.ld8 / 128;
+    void *l16, *thr, *delta, *cand, *cc, *mtop;
+    MRC_TRY(scratch(ctx, "q_l16", (size_t)nq * 4, &l16));
+    MRC_TRY(scratch(ctx, "q_thr", (size_t)nq * 4, &thr));
+    MRC_TRY(scratch(ctx, "q_delta", 256, &delta));
+    MRC_TRY(scratch(ctx, "q_top_lp", (size_t)nq * kTop * sizeof(mrc_hit), &mtop));
+    // pass 1: low-precision top-16 -> L16
+    if (bf) MRC_TRY((launch_scan<MRC_PREC_BF16, MODE_TOP>(ctx, nk, a, grid, s)));
+    else MRC_TRY((launch_scan<MRC_PREC_FP8, MODE_TOP>(ctx, nk, a, grid, s)));
+    hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
+                       (const int32_t*)pi, gx, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
+                       (int32_t*)nullptr, (float*)l16);
+    const float* db_err = db->d_err + (bf ? 0 : db->cap_pad);
+    const float* q_err = (const float*)qerr + (bf ? 0 : nq_pad);
+    hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db_err, rows, q_err, nq, 0.02f,
+                       lowp_acc_unit(precision, k), (float*)delta);
+    hipLaunchKernelGGL(k_query_thr, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s, (const float*)l16, (int)nq,
+                       tau, (const float*)delta, (float*)thr);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    // pass 2: collect candidates, rescore exactly; grow the per-query capacity on overflow
+    int cap = 2048;
+    auto it = ctx->scratch.find("q_cand");
+    if (it != ctx->scratch.end()) cap = std::max<int64_t>(cap, (int64_t)(it->second.second / 8 / nq));
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        MRC_TRY(scratch(ctx, "q_cand", (size_t)nq * cap * 8, &cand));
+        MRC_TRY(scratch(ctx, "q_ccount", (size_t)nq * 4, &cc));
+        MRC_HIP_TRY(ctx, hipMemsetAsync(cc, 0, (size_t)nq * 4, s));
+        MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 8, s));
+        a.thr = (const float*)thr;
+        a.cand = (int64_t*)cand;
+        a.ccount = (int32_t*)cc;
+        a.cap = cap;
+        if (bf) MRC_TRY((launch_scan<MRC_PREC_BF16, MODE_COLLECT>(ctx, nk, a, grid, s)));
+        else MRC_TRY((launch_scan<MRC_PREC_FP8, MODE_COLLECT>(ctx, nk, a, grid, s)));
+        hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)cand,
+                           (const int32_t*)cc, cap, (const float*)unit, k, db->d_unit, L.kp, tau, topk, topk_out,
+                           n_hits, (unsigned long long*)ctx->d_flags);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+        int64_t flag = 0;
+        MRC_HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flags, 8, hipMemcpyDeviceToHost, s));
+        MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (!(flag & 16)) return MRC_OK;
+        std::vector<int32_t> counts(nq);
+        MRC_HIP_TRY(ctx, hipMemcpy(counts.data(), cc, (size_t)nq * 4, hipMemcpyDeviceToHost));
+        cap = std::max(cap, *std::max_element(counts.begin(), counts.end()));
+    }
+    return fail(MRC_E_NOMEM, "mrc_query: candidate capacity");
+}
+
+}  // namespace mrc

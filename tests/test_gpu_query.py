@@ -1,0 +1,119 @@
+"""GPU parity of the resident database and batched queries.
+
+FP32 query results (top-16 ids and scores, hit counts) must equal, bit for
+bit, the exact top lists computed with the oracle's FP32 chain on the same
+unit vectors (score descending, id ascending); BF16 and FP8 queries must
+return exactly the FP32 results; scores agree with the FP64 oracle within
+1e-4."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mrc as om
+from synth import corpus as synth
+from tests.gpu_util import device_docs, flush, require_gpu
+
+pytestmark = pytest.mark.gpu
+TAU = 0.9
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return require_gpu()
+
+
+@pytest.fixture(scope="module")
+def ctx(lib):
+    return lib.mrc_ctx_create(0)
+
+
+def chain_topk(qunit, dbunit, topk, tau):
+    nq, ndb = qunit.shape[0], dbunit.shape[0]
+    ii = np.repeat(np.arange(nq), ndb)
+    jj = np.tile(np.arange(ndb), nq)
+    both = np.concatenate([qunit, dbunit]).astype(np.float32)
+    s = om.score32_pairs(both, ii, jj + nq).reshape(nq, ndb)
+    ids = np.full((nq, topk), -1, np.int64)
+    sc = np.zeros((nq, topk), np.float32)
+    for q in range(nq):
+        o = np.lexsort((np.arange(ndb), -s[q].astype(np.float64)))[:topk]
+        ids[q, :o.size] = o
+        sc[q, :o.size] = s[q, o]
+    return ids, sc, (s >= np.float32(tau)).sum(axis=1)
+
+
+@pytest.fixture(scope="module")
+def setup(lib, ctx):
+    spec = synth.CONFIGS[1]
+    dbc = synth.generate(1, n_docs=3000)
+    qc = synth.generate_queries(spec, 150, seed=77, median=300, sigma=1.2, hi=6000, near_of=dbc, near_frac=0.4)
+    o, t = device_docs(dbc)
+    model = lib.mrc_build_vocab_idf(ctx, o, t, dbc.vocab, lib.ref_spec(64))
+    db = lib.mrc_db_create(ctx, 4000, 64)
+    first = lib.mrc_db_insert_docs(db, model, o, t)
+    assert first == 0 and lib.mrc_db_size(db) == (3000, 64)
+    sig_db = lib.mrc_sign(ctx, model, o, t)
+    qo, qt = device_docs(qc)
+    sig_q = lib.mrc_sign(ctx, model, qo, qt)
+    dbunit = lib.mrc_normalise(ctx, sig_db)["unit"].cpu().numpy()
+    qunit = lib.mrc_normalise(ctx, sig_q)["unit"].cpu().numpy()
+    return dict(dbc=dbc, qc=qc, model=model, db=db, qo=qo, qt=qt, dbunit=dbunit, qunit=qunit)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
+def test_query_equals_exact_chain(lib, ctx, setup, prec):
+    p = {"fp32": lib.PREC_FP32, "bf16": lib.PREC_BF16, "fp8": lib.PREC_FP8}[prec]
+    ids, sc, hits = lib.mrc_query(ctx, setup["db"], setup["model"], setup["qo"], setup["qt"], 16, TAU, p)
+    ids, sc, hits = ids.cpu().numpy(), sc.cpu().numpy(), hits.cpu().numpy()
+    wids, wsc, whits = chain_topk(setup["qunit"], setup["dbunit"], 16, TAU)
+    np.testing.assert_array_equal(ids, wids)
+    np.testing.assert_array_equal(sc.view(np.uint32), wsc.view(np.uint32))
+    np.testing.assert_array_equal(hits, whits)
+    flush(f"  {prec}: mean hits {hits.mean():.2f}, queries with a hit {int((hits > 0).sum())}")
+
+
+def test_query_vs_fp64_oracle(lib, ctx, setup):
+    dbc, qc = setup["dbc"], setup["qc"]
+    omodel = om.build_model(dbc.offsets, dbc.tokens, dbc.vocab, om.RefSpec(k=64))
+    sdb = om.normalise(om.sign(dbc.offsets, dbc.tokens, omodel)[0])
+    sq = om.normalise(om.sign(qc.offsets, qc.tokens, omodel)[0])
+    oids, osc, ohits = om.query_topk(sdb, sq, 16, TAU)
+    ids, sc, hits = lib.mrc_query(ctx, setup["db"], setup["model"], setup["qo"], setup["qt"], 16, TAU)
+    assert np.abs(sc.cpu().numpy() - osc).max() <= 1e-4
+    assert np.abs(hits.cpu().numpy() - ohits).max() <= 2      # only near-ties may move
+
+
+def test_query_edge_cases(lib, ctx, setup):
+    m = setup["model"]
+    small = lib.mrc_db_create(ctx, 10, 64)
+    dbc = setup["dbc"].subset(range(5))
+    o, t = device_docs(dbc)
+    lib.mrc_db_insert_docs(small, m, o, t)
+    qc = synth.from_docs([np.zeros(0, np.int32), dbc.doc(2)], dbc.vocab)
+    qo, qt = device_docs(qc)
+    for p in (lib.PREC_FP32, lib.PREC_BF16, lib.PREC_FP8):
+        ids, sc, hits = lib.mrc_query(ctx, small, m, qo, qt, 16, TAU, p)
+        ids = ids.cpu().numpy()
+        assert ids[0, :5].tolist() == [0, 1, 2, 3, 4] and np.all(ids[0, 5:] == -1)   # zero query: ties by id
+        assert ids[1, 0] == 2 and np.all(ids[1, 5:] == -1)
+        assert hits.cpu().numpy()[1] >= 1
+    with pytest.raises(lib.MrcError) as e:
+        lib.mrc_db_insert_docs(small, m, *device_docs(setup["dbc"].subset(range(6))))
+    assert e.value.status == lib.MRC_E_OVERFLOW
+
+
+def test_db_save_load_roundtrip(lib, ctx, setup, tmp_path):
+    p = tmp_path / "db.bin"
+    lib.mrc_db_save(setup["db"], p)
+    db2 = lib.mrc_db_load(ctx, p)
+    assert lib.mrc_db_size(db2) == (3000, 64)
+    for prec in (lib.PREC_FP32, lib.PREC_BF16):
+        a = lib.mrc_query(ctx, setup["db"], setup["model"], setup["qo"], setup["qt"], 16, TAU, prec)
+        b = lib.mrc_query(ctx, db2, setup["model"], setup["qo"], setup["qt"], 16, TAU, prec)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+    raw = bytearray(p.read_bytes())
+    raw[40] ^= 4
+    p.write_bytes(bytes(raw))
+    with pytest.raises(lib.MrcError):
+        lib.mrc_db_load(ctx, p)
