@@ -7,15 +7,22 @@ Workload: the full-scale plain-method corpus (20,000 synthetic documents over a
 131,072-term vocabulary, lognormal lengths with median 300, 5% exact and 10%
 near duplicates, k = 64 reference parts, tau = 0.9), resident in HBM before the
 timed region. One step runs the whole hot path on it: model build (term counts,
-df, idf, sorted list, parts), signing of every document, and the all-pairs
-comparison at the chosen precision with its FP32 rescoring.
+df, idf, frequency-sorted list, parts), signing of every document, and the
+all-pairs comparison at the chosen precision (with FP32 rescoring for BF16 /
+FP8). `value` = signature pairs compared per second over whole steps
+(N(N-1)/2 pairs per step).
 
-Prints one JSON line. `value` = signature pairs compared per second over whole
-steps (N(N-1)/2 pairs per step).
+Extras (same corpus, outside the timed steps): every precision form, the
+comparators (exact TF-IDF cosine, Simhash-64 + Hamming), recall / precision
+against exact cosine, error against the FP64 oracle, query latency against a
+database of the corpus, and the sign pass against HBM bandwidth.
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -30,11 +37,15 @@ if ROOT not in sys.path:
 PEAKS = {  # MI355X published peaks
     "hbm_GBps": 8000.0,
     "fp32_vector_TFLOPs": 157.3,
+    "fp32_matrix_TFLOPs": 157.3,
     "bf16_mfma_TFLOPs": 2500.0,
     "fp8_mfma_TFLOPs": 5000.0,
 }
-# Non-packed FP32 FMA rate: 256 CUs x 4 SIMDs x 16 lanes x 2 flop x 2.4 GHz.
-FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -48,8 +59,39 @@ def parse():
     return ap.parse_args()
 
 
+def source_digest(rel):
+    with open(os.path.join(ROOT, rel), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter runs, if the kernel's
+    source is unchanged since they were taken (else None)."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)[kernel]
+        if source_digest(t["source"]) != t["source_sha"]:
+            return None
+        return t["bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def timed(mrc, ctx, kernel, fn, reps):
+    """Average device time of `kernel` (HIP events on its launch stream) over reps calls."""
+    mrc.mrc_ctx_set_timing(ctx, True)
+    mrc.mrc_ctx_kernel_time(ctx, kernel, reset=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = fn()
+    wall = (time.perf_counter() - t0) / reps
+    ms, n = mrc.mrc_ctx_kernel_time(ctx, kernel, reset=True)
+    mrc.mrc_ctx_set_timing(ctx, False)
+    return (ms / n if n else None), wall * 1e3, out
+
+
 def cpu_baseline(c, k, tau):
-    """The FP64 oracle on the same workload (whole step: build, sign, compare)."""
+    """The FP64 oracle on the same workload (one whole step: build, sign, compare)."""
     from oracle import mrc as om
     try:
         from threadpoolctl import threadpool_info
@@ -59,20 +101,21 @@ def cpu_baseline(c, k, tau):
     t0 = time.perf_counter()
     m = om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=k))
     sig, _ = om.sign(c.offsets, c.tokens, m)
-    i, j, s = om.compare_pairs(om.normalise(sig), tau)
+    shat = om.normalise(sig)
+    i, j, s = om.compare_pairs(shat, tau)
     dt = time.perf_counter() - t0
     n = c.n_docs
     pairs = n * (n - 1) / 2
     return {"value": pairs / dt, "unit": "pairs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"full workload ({n} docs, one step: build+sign+compare, float64), {dt:.2f} s",
-            "seconds": dt, "flagged": int(i.size), "host_cpus": os.cpu_count()}, (i, j)
+            "sample": f"full workload: {n} docs, one step (build + sign + all-pairs compare), float64 NumPy, "
+                      f"{dt:.2f} s", "seconds": dt, "host_cpus": os.cpu_count()}, shat, (i, j)
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is described in the "
-                                   "design notes but not launched", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but not launched",
+                          "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
     from paper_1810_03099_amd import mrc
@@ -84,13 +127,13 @@ def main():
     k, tau = cs.k, cs.tau
     c = synth.generate(spec_idx)
     n = c.n_docs
+    log(f"corpus {cs.name}: {n} docs, {c.tokens.size} tokens")
     torch.cuda.set_device(0)
     off = torch.from_numpy(c.offsets).cuda()
     tok = torch.from_numpy(c.tokens).cuda()
     ctx = mrc.mrc_ctx_create(0)
     sig = torch.empty((n, k), dtype=torch.float32, device="cuda")
-    cap = 4 * 1024 * 1024
-
+    cap = 8 * 1024 * 1024
     state = {}
 
     def step():
@@ -102,8 +145,9 @@ def main():
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
+    log("warmup done")
     mrc.mrc_ctx_set_timing(ctx, True)
-    kernels = ["classify", "df", "rank_sort", "sign", "normalise", "compare_f32", "compare_lowp", "rescore"]
+    kernels = ["df", "rank_sort", "sign", "normalise", "compare_f32", "compare_lowp", "rescore"]
     for kname in kernels:
         mrc.mrc_ctx_kernel_time(ctx, kname, reset=True)
     torch.cuda.synchronize()
@@ -112,6 +156,7 @@ def main():
         step()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    log(f"timed {a.steps} steps: {dt * 1e3 / a.steps:.3f} ms/step")
     ktimes = {}
     for kname in kernels:
         ms, cnt = mrc.mrc_ctx_kernel_time(ctx, kname)
@@ -122,26 +167,20 @@ def main():
     ms_step = dt * 1e3 / a.steps
     pairs_per_step = n * (n - 1) / 2
     value = pairs_per_step / (dt / a.steps)
-
-    # dominant kernel roofline
+    flops = pairs_per_step * 2 * k
     if prec == mrc.PREC_FP32:
-        kname = "compare_f32"
-        flops = pairs_per_step * 2 * k
-        avg_s = ktimes[kname]["avg_ms"] / 1e3
-        achieved = flops / avg_s / 1e12
-        roof = {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": PEAKS["fp32_vector_TFLOPs"],
-                "unit": "TFLOP/s", "frac": achieved / PEAKS["fp32_vector_TFLOPs"], "traffic": None,
-                "algorithmic_flops_per_launch": flops,
-                "peak_nonpacked_fp32": FP32_NONPACKED_TFLOPS,
-                "frac_of_nonpacked": achieved / FP32_NONPACKED_TFLOPS}
+        kname, pk, bound = "compare_f32", PEAKS["fp32_matrix_TFLOPs"], "mfma"
+        src = "paper_1810_03099_amd/csrc/compare.hip"
     else:
         kname = "compare_lowp"
-        flops = pairs_per_step * 2 * k
-        avg_s = ktimes[kname]["avg_ms"] / 1e3
-        achieved = flops / avg_s / 1e12
         pk = PEAKS["bf16_mfma_TFLOPs"] if prec == mrc.PREC_BF16 else PEAKS["fp8_mfma_TFLOPs"]
-        roof = {"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": pk, "unit": "TFLOP/s",
-                "frac": achieved / pk, "traffic": None, "algorithmic_flops_per_launch": flops}
+        bound, src = "mfma", "paper_1810_03099_amd/csrc/compare.hip"
+    avg_s = ktimes[kname]["avg_ms"] / 1e3
+    achieved = flops / avg_s / 1e12
+    roof = {"kernel": kname, "bound": bound, "achieved": achieved, "peak": pk, "unit": "TFLOP/s",
+            "frac": achieved / pk, "traffic": measured_traffic(kname + "/" + a.precision),
+            "algorithmic_flops_per_launch": flops,
+            "note": "all-pairs signature contraction N(N-1)/2 x 2k flop per launch over the launch's HIP-event time"}
 
     sign_ms = ktimes.get("sign", {}).get("avg_ms")
     out = {
@@ -156,23 +195,131 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[a.precision],
-        "data": "synthetic (Zipf/topic/lognormal generator, seeded; stands in for NEWS20)",
-        "config": {"workload": f"{cs.name}: {n} docs, vocab {cs.vocab}, k={k}, tau={tau}, "
-                               f"reference = sorted list without its top 5%", "n_docs": n, "vocab": cs.vocab,
-                   "k": k, "tau": tau, "tokens": int(c.tokens.size), "precision": a.precision},
+        "data": "synthetic (seeded Zipf/topic/lognormal generator with planted duplicates; stands in for NEWS20)",
+        "config": {"workload": f"{cs.name}: {n} docs, vocab {cs.vocab}, k={k}, tau={tau}, reference = frequency-"
+                               f"sorted list without its top 5%", "n_docs": n, "vocab": cs.vocab, "k": k,
+                   "tau": tau, "tokens": int(c.tokens.size), "precision": a.precision},
         "docs_signed_per_s": n / (sign_ms / 1e3) if sign_ms else None,
         "flagged_pairs": int(state["stats"]["n_flagged"]),
         "kernel_avg_ms": ktimes,
         "roofline": roof,
     }
+    shat = None
     if not a.no_cpu_baseline:
-        cb, (oi, oj) = cpu_baseline(c, k, tau)
+        log("cpu baseline (oracle)")
+        cb, shat, (oi, oj) = cpu_baseline(c, k, tau)
         out["cpu_baseline"] = cb
         gi, gj, _, _ = mrc.pairs_to_numpy(state["pairs"])
         g = set(zip(gi.tolist(), gj.tolist()))
         o = set(zip(oi.tolist(), oj.tolist()))
-        out["decisions_vs_oracle"] = {"gpu_only": len(g - o), "oracle_only": len(o - g), "common": len(g & o)}
+        out["decisions_vs_fp64_oracle"] = {"gpu_only": len(g - o), "oracle_only": len(o - g), "common": len(g & o)}
+    if not a.no_extras:
+        out["extras"] = extras(mrc, ctx, c, off, tok, sig, state["model"], k, tau, cap, shat, sign_ms)
     print(json.dumps(out))
+
+
+def extras(mrc, ctx, c, off, tok, sig, model, k, tau, cap, shat, sign_ms):
+    import torch
+    from synth import corpus as synth
+    n = c.n_docs
+    pairs_total = n * (n - 1) / 2
+    ex = {}
+    # precision forms on the same signatures
+    forms = {}
+    pair_sets = {}
+    for name, p, kn in [("fp32", mrc.PREC_FP32, "compare_f32"), ("bf16", mrc.PREC_BF16, "compare_lowp"),
+                        ("fp8", mrc.PREC_FP8, "compare_lowp")]:
+        mrc.mrc_compare(ctx, sig, tau, p, 0.02, capacity=cap)
+        kms, wall, (pairs, st) = timed(mrc, ctx, kn, lambda: mrc.mrc_compare(ctx, sig, tau, p, 0.02, capacity=cap), 5)
+        rms = None
+        if p != mrc.PREC_FP32:
+            rms, _, _ = timed(mrc, ctx, "rescore", lambda: mrc.mrc_compare(ctx, sig, tau, p, 0.02, capacity=cap), 2)
+        gi, gj, gs, gf = mrc.pairs_to_numpy(pairs)
+        pair_sets[name] = set(zip(gi.tolist(), gj.tolist()))
+        f = {"kernel_ms": kms, "rescore_ms": rms, "call_ms": wall, "pairs_per_s_kernel": pairs_total / (kms / 1e3),
+             "pairs_per_s_call": pairs_total / (wall / 1e3), "flagged": int(gi.size),
+             "rescored": st["n_band"], "rescored_in_nominal_band": st["n_band_nominal"],
+             "flips_a_fixed_0.02_band_would_make": st["n_flip_outside_nominal"],
+             "max_abs_err_vs_fp32": st["max_abs_err"], "mean_abs_err_vs_fp32": st["mean_abs_err"]}
+        pk = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}[name]
+        f["mfma_frac"] = pairs_total * 2 * k / (kms / 1e3) / 1e12 / pk
+        if shat is not None and gi.size:
+            from oracle import mrc as om
+            s64 = om.pair_scores(shat, gi, gj)
+            err = np.abs(gs.astype(np.float64) - s64)
+            f["err_vs_fp64"] = {"max": float(err.max()), "mean": float(err.mean())}
+        forms[name] = f
+        log(f"form {name}: {kms:.4f} ms")
+    forms["decisions_identical_to_fp32"] = all(pair_sets[x] == pair_sets["fp32"] for x in ("bf16", "fp8"))
+    ex["forms"] = forms
+    # comparators
+    log("comparators")
+    mrc.mrc_exact_cosine(ctx, model, off, tok, tau, capacity=cap)
+    ems, ewall, ep = timed(mrc, ctx, "exact_cosine", lambda: mrc.mrc_exact_cosine(ctx, model, off, tok, tau,
+                                                                                  capacity=cap), 2)
+    ei, ej, _, _ = mrc.pairs_to_numpy(ep)
+    exact = set(zip(ei.tolist(), ej.tolist()))
+    mrc.mrc_simhash(ctx, model, off, tok)
+    sms, swall, sim = timed(mrc, ctx, "simhash", lambda: mrc.mrc_simhash(ctx, model, off, tok), 5)
+    hms, hwall, hp = timed(mrc, ctx, "hamming", lambda: mrc.mrc_hamming_pairs(ctx, sim, 3, capacity=cap), 5)
+    hi, hj, _, _ = mrc.pairs_to_numpy(hp)
+    simset = set(zip(hi.tolist(), hj.tolist()))
+
+    def rp(found):
+        tp = len(found & exact)
+        return {"recall": tp / len(exact) if exact else 1.0, "precision": tp / len(found) if found else 1.0,
+                "flagged": len(found)}
+
+    ex["comparators"] = {
+        "exact_cosine": {"call_ms": ewall, "kernel_ms": ems, "pairs_per_s": pairs_total / (ewall / 1e3),
+                         "flagged": len(exact)},
+        "simhash64": {"sign_ms": sms, "docs_per_s": n / (sms / 1e3), "hamming_ms": hms,
+                      "hamming_pairs_per_s": pairs_total / (hms / 1e3), "flagged_hamming_le_3": len(simset)},
+    }
+    ex["vs_exact_cosine_at_tau"] = {"mrc_fp32": rp(pair_sets["fp32"]), "simhash_hamming_le_3": rp(simset)}
+    # sign pass against HBM: algorithmic bytes = tokens in + offsets + signatures out
+    if sign_ms:
+        by = c.tokens.size * 4 + (n + 1) * 8 + n * k * 4
+        ex["sign_roofline"] = {"bound": "hbm", "algorithmic_bytes": int(by), "avg_ms": sign_ms,
+                               "achieved_GBps": by / (sign_ms / 1e3) / 1e9,
+                               "frac": by / (sign_ms / 1e3) / 1e9 / 8000.0}
+    # queries against a database of the corpus
+    log("queries")
+    db = mrc.mrc_db_create(ctx, n + 1024, k)
+    mrc.mrc_db_insert(db, sig)
+    qc = synth.generate_queries(synth.CONFIGS[1], 512, seed=11, median=300, sigma=1.2, hi=20000, near_of=c,
+                                near_frac=0.2)
+    qo = torch.from_numpy(qc.offsets).cuda()
+    qt = torch.from_numpy(qc.tokens).cuda()
+    singles = []
+    for i in range(200):
+        a, b = int(qc.offsets[i]), int(qc.offsets[i + 1])
+        o1 = torch.tensor([0, b - a], dtype=torch.int64, device="cuda")
+        t1 = qt[a:b].contiguous() if b > a else torch.zeros(1, dtype=torch.int32, device="cuda")
+        singles.append((o1, t1))
+    torch.cuda.synchronize()
+    q = {}
+    for name, p in [("fp32", mrc.PREC_FP32), ("bf16", mrc.PREC_BF16), ("fp8", mrc.PREC_FP8)]:
+        lat = []
+        for o1, t1 in singles:
+            t0 = time.perf_counter()
+            mrc.mrc_query(ctx, db, model, o1, t1, 16, tau, p)
+            torch.cuda.synchronize()
+            lat.append((time.perf_counter() - t0) * 1e3)
+        lat = np.array(lat[10:])
+        mrc.mrc_query(ctx, db, model, qo, qt, 16, tau, p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            mrc.mrc_query(ctx, db, model, qo, qt, 16, tau, p)
+        torch.cuda.synchronize()
+        bt = (time.perf_counter() - t0) / 3
+        q[name] = {"single_query_p50_ms": float(np.percentile(lat, 50)),
+                   "single_query_p99_ms": float(np.percentile(lat, 99)),
+                   "batch512_ms": bt * 1e3, "batch512_queries_per_s": 512 / bt}
+    q["database_rows"] = n
+    ex["query"] = q
+    return ex
 
 
 if __name__ == "__main__":

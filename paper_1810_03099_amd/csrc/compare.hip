@@ -5,9 +5,12 @@
 //    codes, float8 e4m3fn codes with a per-row scale max|u|/448, and per-row
 //    error norms |u - dequantised| used to bound low-precision scores.
 //  * k_compare_f32: the plain path. Every pair i < j gets the score
-//    acc = 0; acc = fmaf(u_ic, u_jc, acc), c = 0..k-1, on the vector ALUs,
-//    register-tiled 8x8 per thread over a 128x128 tile, upper-triangle tiles
-//    only; pairs with acc >= tau are appended to the output.
+//    acc = 0; acc = fmaf(u_ic, u_jc, acc), c = 0..k-1, computed on the FP32
+//    matrix cores (whose 16x16x4 step is that chain over its four k-values),
+//    persistent wavefronts over 64x64 upper-triangle tiles; pairs with
+//    acc >= tau are appended to the output.
+//  * k_compare_lowp: the same tiling over BF16 / FP8 codes, emitting the
+//    candidates that k_rescore then decides with the plain chain.
 //  * k_score_pairs / k_rescore: the same chain for listed pairs.
 #include <algorithm>
 
