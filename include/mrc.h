@@ -164,7 +164,8 @@ const char* mrc_last_error(void);
  * df > 0 (df descending, id ascending), the selection and its k parts.
  * vocab_size: term ids must lie in [0, vocab_size), vocab_size <= 2^24.
  * Errors: MRC_E_INVAL for a bad spec, a selection with fewer than k terms, an
- * out-of-range token or malformed offsets. */
+ * out-of-range token, malformed offsets or a document longer than 2^22
+ * tokens. */
 mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
                                const mrc_ref_spec* spec, mrc_model** out, void* hip_stream);
 mrc_status mrc_model_destroy(mrc_model* model);
@@ -190,10 +191,22 @@ mrc_status mrc_model_load(mrc_ctx* ctx, const char* path, mrc_model** out);
  * w_dt = tf * idf_t, 0 for an empty document. Terms with df = 0 in the model
  * corpus count in |w_d| (with their smoothed idf) but belong to no part.
  * sig_out: device float [n_docs][k] row-major. norm_out: device float [n_docs]
- * (|w_d|) or NULL. Norms of documents longer than 10^4 tokens accumulate in
- * float64. Errors: MRC_E_INVAL for a token outside [0, V) or bad offsets. */
+ * (|w_d|) or NULL. The part sums and |w_d|^2 are accumulated exactly (integer
+ * fixed point), so a document's signature does not depend on the batch it is
+ * signed in. Documents may hold at most 2^22 tokens. Errors: MRC_E_INVAL for a
+ * token outside [0, V), bad offsets or a longer document. */
 mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float* sig_out,
                     float* norm_out, void* hip_stream);
+
+/* Build the model of a corpus and sign that corpus (Sections 1 and 4: the
+ * signature database of a collection) in one call, reusing the per-document
+ * term counts of the build. Same result as mrc_build_vocab_idf followed by
+ * mrc_sign on the same documents, bit for bit. sig_out: device float
+ * [n_docs][k] (may be NULL only for an empty corpus); norm_out as mrc_sign.
+ * Errors: those of mrc_build_vocab_idf and mrc_sign. */
+mrc_status mrc_build_and_sign(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
+                              const mrc_ref_spec* spec, mrc_model** out, float* sig_out, float* norm_out,
+                              void* hip_stream);
 
 /* ------------------------------------------------------------------ comparison */
 

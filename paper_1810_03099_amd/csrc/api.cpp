@@ -11,7 +11,6 @@ using namespace mrc;
 
 namespace {
 
-constexpr uint64_t kErrOffsets = 1, kErrToken = 2, kErrSelection = 4, kErrTailCap = 8;
 
 mrc_status check_ctx(mrc_ctx* ctx, const char* fn) {
     if (!ctx) return fail(MRC_E_INVAL, std::string(fn) + ": ctx is NULL");
@@ -42,6 +41,8 @@ mrc_status sync_flags(mrc_ctx* ctx, hipStream_t s, int n_words, const char* fn) 
     MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
     const uint64_t err = (uint64_t)ctx->h_flags[0];
     if (err & kErrOffsets) return fail(MRC_E_INVAL, std::string(fn) + ": malformed offsets");
+    if (err & kErrDocLen)
+        return fail(MRC_E_INVAL, std::string(fn) + ": a document is longer than 2^22 tokens");
     if (err & kErrToken) return fail(MRC_E_INVAL, std::string(fn) + ": token id outside [0, vocab)");
     if (err & kErrSelection)
         return fail(MRC_E_INVAL, std::string(fn) + ": reference selection holds fewer terms than k");
@@ -50,18 +51,23 @@ mrc_status sync_flags(mrc_ctx* ctx, hipStream_t s, int n_words, const char* fn) 
     return MRC_OK;
 }
 
+// The model's tables live in one device block (offsets 256-byte aligned), so
+// a build costs one allocation and a destroy one free.
+size_t model_layout(size_t V, size_t k, size_t off[7]) {
+    const size_t sizes[7] = {V * 4, V * 4, V * 4, V * 4, V * sizeof(TermInfo), k * 8, k * 8};
+    size_t total = 0;
+    for (int i = 0; i < 7; ++i) {
+        off[i] = total;
+        total += (sizes[i] + 255) & ~size_t(255);
+    }
+    return total;
+}
+
 void free_model(mrc_model* m) {
     if (!m) return;
     mrc_ctx* c = m->ctx;
-    size_t V = (size_t)m->vocab, k = (size_t)m->k;
-    dev_free(c, m->d_df, V * 4);
-    dev_free(c, m->d_idf, V * 4);
-    dev_free(c, m->d_term_at, V * 4);
-    dev_free(c, m->d_rank_of, V * 4);
-    dev_free(c, m->d_tinfo, V * sizeof(TermInfo));
-    dev_free(c, m->d_rnorm, k * 8);
-    dev_free(c, m->d_rinv, k * 8);
-    dev_free(c, m->d_hash, V * 8);
+    dev_free(c, m->d_df, m->bytes);
+    dev_free(c, m->d_hash, (size_t)m->vocab * 8);
     delete m;
 }
 
@@ -70,19 +76,21 @@ mrc_status alloc_model(mrc_ctx* ctx, int32_t V, int32_t k, mrc_model** out) {
     m->ctx = ctx;
     m->vocab = V;
     m->k = k;
-    mrc_status st = MRC_OK;
-    const size_t Vs = (size_t)V;
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_df, Vs * 4);
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_idf, Vs * 4);
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_term_at, Vs * 4);
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_rank_of, Vs * 4);
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_tinfo, Vs * sizeof(TermInfo));
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_rnorm, (size_t)k * 8);
-    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&m->d_rinv, (size_t)k * 8);
+    size_t off[7];
+    m->bytes = model_layout((size_t)V, (size_t)k, off);
+    char* base = nullptr;
+    const mrc_status st = dev_alloc(ctx, (void**)&base, m->bytes);
     if (st != MRC_OK) {
-        free_model(m);
+        delete m;
         return st;
     }
+    m->d_df = (uint32_t*)(base + off[0]);
+    m->d_idf = (float*)(base + off[1]);
+    m->d_term_at = (int32_t*)(base + off[2]);
+    m->d_rank_of = (int32_t*)(base + off[3]);
+    m->d_tinfo = (TermInfo*)(base + off[4]);
+    m->d_rnorm = (double*)(base + off[5]);
+    m->d_rinv = (double*)(base + off[6]);
     *out = m;
     return MRC_OK;
 }
@@ -116,15 +124,18 @@ extern "C" {
 
 // ------------------------------------------------------------------ model
 
-mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
-                               const mrc_ref_spec* spec, mrc_model** out, void* hip_stream) {
-    MRC_TRY(check_ctx(ctx, "mrc_build_vocab_idf"));
-    MRC_TRY(check_docs(corpus, "mrc_build_vocab_idf"));
-    if (!out) return fail(MRC_E_INVAL, "mrc_build_vocab_idf: out is NULL");
+namespace {
+
+// Model build shared by mrc_build_vocab_idf and mrc_build_and_sign; with
+// sig_out set, the corpus is also signed from its count lists.
+mrc_status build_model(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size, const mrc_ref_spec* spec,
+                       mrc_model** out, float* sig_out, float* norm_out, hipStream_t s, const char* fn) {
+    MRC_TRY(check_ctx(ctx, fn));
+    MRC_TRY(check_docs(corpus, fn));
+    if (!out) return fail(MRC_E_INVAL, std::string(fn) + ": out is NULL");
     *out = nullptr;
     if (vocab_size < 1 || vocab_size > (1 << 24)) return fail(MRC_E_INVAL, "vocab_size must lie in [1, 2^24]");
     MRC_TRY(check_spec(spec, vocab_size));
-    hipStream_t s = (hipStream_t)hip_stream;
     mrc_model* m = nullptr;
     MRC_TRY(alloc_model(ctx, vocab_size, spec->k, &m));
     m->n_docs = corpus->n_docs;
@@ -134,15 +145,36 @@ mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t voc
         free_model(m);
         return st;
     };
-    mrc_status st = launch_df(ctx, corpus, vocab_size, m->d_df, s);
+    CountLists cl{};
+    mrc_status st = count_scratch(ctx, corpus, &cl);
+    if (st == MRC_OK) st = launch_df(ctx, corpus, vocab_size, m->d_df, cl, s);
     if (st == MRC_OK) st = launch_model_tables(ctx, m, s);
-    if (st == MRC_OK) st = sync_flags(ctx, s, 9, "mrc_build_vocab_idf");
+    if (st == MRC_OK && sig_out) st = launch_sign_counts(ctx, m, corpus, cl, sig_out, norm_out, s);
+    if (st == MRC_OK) st = sync_flags(ctx, s, 9, fn);
     if (st != MRC_OK) return bail(st);
     m->n_listed = ctx->h_flags[6];
     m->lo = ctx->h_flags[7];
     m->hi = ctx->h_flags[8];
     *out = m;
     return MRC_OK;
+}
+
+}  // namespace
+
+mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
+                               const mrc_ref_spec* spec, mrc_model** out, void* hip_stream) {
+    return build_model(ctx, corpus, vocab_size, spec, out, nullptr, nullptr, (hipStream_t)hip_stream,
+                       "mrc_build_vocab_idf");
+}
+
+mrc_status mrc_build_and_sign(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size, const mrc_ref_spec* spec,
+                              mrc_model** out, float* sig_out, float* norm_out, void* hip_stream) {
+    if (corpus && corpus->n_docs > 0 && !sig_out) return fail(MRC_E_INVAL, "mrc_build_and_sign: sig_out is NULL");
+    float* sig = sig_out;
+    float dummy = 0.f;
+    if (!sig) sig = &dummy;  // empty corpus: nothing is written
+    return build_model(ctx, corpus, vocab_size, spec, out, sig, norm_out, (hipStream_t)hip_stream,
+                       "mrc_build_and_sign");
 }
 
 mrc_status mrc_model_destroy(mrc_model* model) {
@@ -339,7 +371,7 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
         const int64_t n_pad = ceil_div(n > 0 ? n : 1, 64) * 64, kp = 16 * (int64_t)mfma_chunks(k);
         void* umfma = nullptr;
         MRC_TRY(scratch(ctx, "cmp_unit_mfma", (size_t)(n_pad * kp) * sizeof(float), &umfma));
-        MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 16 * sizeof(int64_t), s));
+        MRC_TRY(clear_words(ctx, ctx->d_flags, 16, s));
         MRC_TRY(launch_normalise(ctx, sig, n, k, nullptr, nullptr, nullptr, nullptr, nullptr, s, (float*)umfma));
         PairSink sink{pairs_out, capacity, counter};
         MRC_TRY(launch_compare_f32(ctx, (const float*)umfma, n, k, opts->tau, sink, s));
@@ -367,7 +399,7 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
     for (int attempt = 0; attempt < 2; ++attempt) {
         void* cand = nullptr;
         MRC_TRY(scratch(ctx, "lp_cand", (size_t)cand_cap * sizeof(mrc_pair), &cand));
-        MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 32 * sizeof(int64_t), s));
+        MRC_TRY(clear_words(ctx, ctx->d_flags, 32, s));
         NormLayout o{(float*)unit, k, prec == MRC_PREC_BF16 ? (uint16_t*)q : nullptr, ldq,
                      prec == MRC_PREC_FP8 ? (uint8_t*)q : nullptr, ldq, (float*)scale, (float*)err, n_pad,
                      nullptr, 0, n_pad};
@@ -445,7 +477,7 @@ mrc_status mrc_hamming_pairs(mrc_ctx* ctx, const uint64_t* sim, int64_t n, int32
         (capacity > 0 && !pairs_out))
         return fail(MRC_E_INVAL, "mrc_hamming_pairs: bad argument");
     hipStream_t s = (hipStream_t)hip_stream;
-    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 8 * sizeof(int64_t), s));
+    MRC_TRY(clear_words(ctx, ctx->d_flags, 8, s));
     PairSink sink{pairs_out, capacity, (unsigned long long*)(ctx->d_flags + 4)};
     MRC_TRY(launch_hamming(ctx, sim, n, max_dist, sink, s));
     MRC_TRY(sync_flags(ctx, s, 8, "mrc_hamming_pairs"));
@@ -461,7 +493,7 @@ mrc_status mrc_exact_cosine(mrc_ctx* ctx, const mrc_model* model, const mrc_docs
     if (!model || !n_found || capacity < 0 || (capacity > 0 && !pairs_out) || !(tau == tau))
         return fail(MRC_E_INVAL, "mrc_exact_cosine: bad argument");
     hipStream_t s = (hipStream_t)hip_stream;
-    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 8 * sizeof(int64_t), s));
+    MRC_TRY(clear_words(ctx, ctx->d_flags, 8, s));
     PairSink sink{pairs_out, capacity, (unsigned long long*)(ctx->d_flags + 4)};
     MRC_TRY(launch_exact_cosine(ctx, model, docs, tau, sink, s));
     MRC_TRY(sync_flags(ctx, s, 8, "mrc_exact_cosine"));

@@ -79,7 +79,7 @@ struct mrc_model {
     double* d_rnorm = nullptr;       // [k]
     double* d_rinv = nullptr;        // [k]  1 / |r_j|
     uint64_t* d_hash = nullptr;      // [V]  MD5 term hashes (built on first use)
-    size_t bytes = 0;
+    size_t bytes = 0;                // the one device block holding d_df .. d_rinv (at d_df)
 };
 
 struct mrc_db {
@@ -130,13 +130,35 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // ---------------------------------------------------------------- stage launchers
 // Each returns MRC_OK or an error; all work is enqueued on `s`.
 
-// Clear the error word and check offsets on the device (kErrOffsets = bit 0);
-// the document kernels return at once when it is set.
-mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s);
+// Zero n 64-bit words at p with one small kernel (no fill-kernel split for
+// unaligned ranges).
+mrc_status clear_words(mrc_ctx* ctx, int64_t* p, int n, hipStream_t s);
 
-// df over a corpus: one increment per distinct (document, term). Also checks
-// offsets and token ids (error bits in ctx->d_flags[0]).
-mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s);
+// Clear the error word and check offsets on the device (kErrOffsets = bit 0);
+// the document kernels return at once when it is set. With `lists` (2n int32)
+// it also lists the medium documents in lists[0..) and the long ones in
+// lists[n..), their counts in ctx->d_flags[1] and [2].
+mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s, int32_t* lists = nullptr);
+
+// Distinct terms of each document of a corpus with their counts, at the
+// document's token offset: term[off[d] + e], tf[off[d] + e] for e < nnz[d].
+struct CountLists {
+    int32_t* term;
+    int32_t* tf;
+    int32_t* nnz;
+};
+// Context scratch sized for `docs`.
+mrc_status count_scratch(mrc_ctx* ctx, const mrc_docs* docs, CountLists* c);
+
+// df over a corpus: the count lists, then one count per distinct (document,
+// term). Also checks offsets and token ids (error bits in ctx->d_flags[0]).
+mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, const CountLists& c,
+                     hipStream_t s);
+
+// Signatures of the corpus whose count lists `c` holds (bit-identical to
+// launch_sign on the same documents).
+mrc_status launch_sign_counts(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const CountLists& c,
+                              float* sig_out, float* norm_out, hipStream_t s);
 
 // Unit TF-IDF vectors of a batch for the exact-cosine comparator: ranks < H in
 // a dense [n_pad][ldh] matrix (matrix-core layout), the rest listed per
@@ -294,7 +316,11 @@ int mfma_chunks(int k);
 constexpr int kShortMax = 512;    // one wavefront per document, LDS hash table
 constexpr int kMediumMax = 4096;  // one 256-thread workgroup per document, LDS hash table
 constexpr int kLongBlocks = 64;   // workgroups of the long-document pass (each owns a [V] table)
-constexpr int kFp64NormMin = 10000;  // norms of longer documents accumulate in float64
+constexpr int64_t kMaxDocLen = 1 << 22;  // longest document (exact 64/128-bit sums below this)
+
+// Error bits of ctx->d_flags[0], set by kernels and decoded after the call.
+constexpr unsigned long long kErrOffsets = 1, kErrToken = 2, kErrSelection = 4, kErrTailCap = 8,
+                             kErrQueryCap = 16, kErrDocLen = 32;
 
 }  // namespace mrc
 

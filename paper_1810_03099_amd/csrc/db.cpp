@@ -143,7 +143,8 @@ mrc_status mrc_db_insert_docs(mrc_db* db, const mrc_model* model, const mrc_docs
     MRC_TRY(launch_sign(ctx, model, docs, (float*)sig, nullptr, s));
     MRC_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, 8, hipMemcpyDeviceToHost, s));
     MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (ctx->h_flags[0]) return fail(MRC_E_INVAL, "mrc_db_insert_docs: malformed offsets or token ids");
+    if (ctx->h_flags[0])
+        return fail(MRC_E_INVAL, "mrc_db_insert_docs: malformed offsets, token ids or document lengths");
     return mrc_db_insert(db, (const float*)sig, docs->n_docs, first_id, hip_stream);
 }
 
@@ -246,7 +247,8 @@ mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, con
     MRC_TRY(run_query(ctx, db, rows, model, q, topk, tau, precision, topk_out, n_hits, s));
     MRC_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, 8, hipMemcpyDeviceToHost, s));
     MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
-    if (ctx->h_flags[0] & 3) return fail(MRC_E_INVAL, "mrc_query: malformed offsets or token ids");
+    if (ctx->h_flags[0] & (kErrOffsets | kErrToken | kErrDocLen))
+        return fail(MRC_E_INVAL, "mrc_query: malformed offsets, token ids or document lengths");
     return MRC_OK;
 }
 

@@ -1,20 +1,32 @@
-// Per-document passes over the token CSR: length classification, document
-// frequency (model build) and MRC signing (Section 4: cosine of the TF-IDF
-// vector of a document against each of the k reference parts).
+// Per-document passes over the token CSR (Section 4: the TF-IDF vector of a
+// document and its cosine against each of the k reference parts).
 //
-// Every pass turns a document's token stream into term counts with a hash
-// table: in LDS for documents up to kMediumMax tokens (one wavefront per
-// short document, one 256-thread workgroup per medium document), and in a
-// per-workgroup [V] count array in global memory for longer documents.
+// A document's tokens become term counts in a hash table: in LDS for
+// documents up to kMediumMax tokens (one wavefront per short document, one
+// 256-thread workgroup per medium document), and in a per-workgroup [V] count
+// array in global memory for longer documents. The passes are
+//  * COUNT (model build): the distinct terms of each document and their
+//    counts, written at the document's token offset; document frequencies are
+//    then a histogram of those lists (k_df_hist / k_df_sum, LDS counters per
+//    vocabulary slice, no global atomics);
+//  * SIGN: the signature straight from the table;
+//  * CSR: unit TF-IDF weights for the exact-cosine comparator.
+// k_sign_counts signs from the COUNT lists, so a corpus that built the model
+// is signed without hashing it again.
 //
 // Signing needs, per document d and part j,
-//   num_j = sum over occurrences p with part(t_p) = j of c_p,  c_p = idf_t * rho_t,
-//   |w_d|^2 = sum over occurrences p of tf(t_p) * idf(t_p)^2,
-// and sig_dj = num_j / (|w_d| |r_j|). num_j is accumulated in exact 64-bit
-// fixed point (c_p * 2^32 is an integer for the weights that occur), so it is
-// exact and independent of order; the norm sums in a fixed per-document order
-// (float32, float64 for documents longer than 10^4 tokens). A document's result
-// therefore depends only on its own tokens, never on the batch around it.
+//   num_j = sum over terms t of part j of tf_t * c_t,   c_t = idf_t * rho_t,
+//   |w_d|^2 = sum over terms t of (tf_t * idf_t)^2,
+// and sig_dj = num_j / (|w_d| |r_j|). Both sums are formed exactly in integer
+// fixed point: c * 2^32 is an integer for the weights that occur (c >= 1), and
+// for idf in [1, 32), idf = m * 2^(E-23) with integer m < 2^24, so
+// (tf * idf)^2 * 2^46 = (tf * m)^2 * 2^(2E) is an integer; a 128-bit sum of
+// these is exact for documents up to kMaxDocLen tokens. The results are thus
+// independent of the order of summation: every pass, and any batch a document
+// is part of, gives the same bits. |w_d| is the square root of that exact sum,
+// rounded once to float64.
+#include <algorithm>
+
 #include "common.h"
 
 using namespace mrc;
@@ -23,12 +35,54 @@ namespace {
 
 constexpr int kBlock = 256;
 constexpr int kEmpty = -1;
-constexpr int kDfReplicas = 32;
+constexpr int kHistSlice = 65536;  // vocabulary ids per LDS histogram slice (16-bit counters)
+constexpr int kHistMaxSlices = 8;  // above this, df is counted with global atomics instead
 
-enum : unsigned long long {
-    kErrOffsets = 1ull,
-    kErrToken = 2ull,
-};
+typedef unsigned __int128 u128;
+
+// --------------------------------------------------------------- exact sums
+
+// tf * idf^2 * 2^46 (the contribution of one occurrence of a term with count tf)
+__device__ __forceinline__ u128 occ_sq_fixed(uint32_t tf, float idf) {
+    const uint32_t b = __float_as_uint(idf);
+    const int E = (int)(b >> 23) - 127;  // 0 <= E <= 4 for idf in [1, 32)
+    const uint64_t m = (b & 0x7FFFFFu) | 0x800000u;
+    return ((u128)(m * m) * tf) << (2 * E);
+}
+
+// (tf * idf)^2 * 2^46 (the contribution of a distinct term with count tf)
+__device__ __forceinline__ u128 term_sq_fixed(uint32_t tf, float idf) {
+    const uint32_t b = __float_as_uint(idf);
+    const int E = (int)(b >> 23) - 127;
+    const uint64_t m = (b & 0x7FFFFFu) | 0x800000u;
+    const uint64_t a = (uint64_t)tf * m;
+    return ((u128)a * a) << (2 * E);
+}
+
+// Correctly rounded u128 -> double: the leading 64 bits with a sticky bit for
+// the rest (below the rounding position), converted once.
+__device__ __forceinline__ double u128_to_double(u128 v) {
+    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
+    if (hi == 0) return (double)lo;
+    const int lz = __clzll((long long)hi);
+    const uint64_t top = lz ? (hi << lz) | (lo >> (64 - lz)) : hi;
+    const uint64_t rest = lz ? (lo << lz) : lo;
+    return ldexp((double)(top | (rest != 0 ? 1ull : 0ull)), 64 - lz);
+}
+
+__device__ __forceinline__ double norm_from_fixed(u128 s) { return sqrt(u128_to_double(s) * 0x1p-46); }
+
+__device__ __forceinline__ u128 wave_sum_u128(u128 v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint64_t lo = __shfl_xor((unsigned long long)(uint64_t)v, off, 64);
+        const uint64_t hi = __shfl_xor((unsigned long long)(uint64_t)(v >> 64), off, 64);
+        v += ((u128)hi << 64) | lo;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------------ helpers
 
 __device__ __forceinline__ int hash_slot(int t, int log2_slots) {
     return (int)(((unsigned)t * 0x9E3779B1u) >> (32 - log2_slots));
@@ -45,17 +99,17 @@ __device__ __forceinline__ void team_sync() {
     }
 }
 
-// Fixed-order sum over a team (one wavefront, or the 4 wavefronts of a block).
-template <int TEAM, typename T>
-__device__ __forceinline__ T team_sum(T v, T* red) {
-    v = mrc_dev::wave_sum(v);
+// Sum over a team (one wavefront, or the 4 wavefronts of a block); exact.
+template <int TEAM>
+__device__ __forceinline__ u128 team_sum(u128 v, u128* red) {
+    v = wave_sum_u128(v);
     if constexpr (TEAM == 64) {
         return v;
     } else {
         const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) red[w] = v;
         __syncthreads();
-        T r = red[0];
+        u128 r = red[0];
 #pragma unroll
         for (int i = 1; i < TEAM / 64; ++i) r += red[i];
         __syncthreads();
@@ -63,14 +117,20 @@ __device__ __forceinline__ T team_sum(T v, T* red) {
     }
 }
 
-struct SignArgs {
+struct PassArgs {
+    // SIGN / CSR
     const TermInfo* tinfo;
     const double* rinv;
     int k;
-    int ref_idf;       // 1: rho_t = idf_t, so c_p = idf^2
+    int ref_idf;       // 1: rho_t = idf_t, so c_t = idf^2
     float* sig;
     float* norm;
-    // MODE_CSR: unit TF-IDF weights w = tf * idf / |w_d| of each distinct term.
+    // COUNT: distinct terms and counts of document d at [off[d], off[d] + nnz[d]);
+    // the document's remaining slots up to off[d + 1] hold term -1
+    int32_t* cnt_term;
+    int32_t* cnt_tf;
+    int32_t* cnt_nnz;
+    // CSR: unit TF-IDF weights w = tf * idf / |w_d| of each distinct term.
     // Ranks below H go to the dense head matrix (matrix-core layout, ld ldh);
     // the others are listed at the document's token offset (ent_*), counted
     // per rank in pcount, and their number stored in nnz_tail.
@@ -84,57 +144,112 @@ struct SignArgs {
     uint32_t* pcount;
 };
 
-enum { MODE_DF = 0, MODE_SIGN = 1, MODE_CSR = 2 };
+enum { MODE_COUNT = 0, MODE_SIGN = 1, MODE_CSR = 2 };
 
-// Emit one distinct term of document d (MODE_CSR).
-__device__ __forceinline__ void csr_emit(const SignArgs& sa, int64_t d, int64_t o, int t, unsigned tf, double nrm,
-                                         int* tcount) {
-    const float w = (float)((double)tf * (double)sa.tinfo[t].idf / nrm);
-    const int r = sa.rank_of[t];
-    if (r < sa.H) {
-        sa.wh[d * sa.ldh + mrc_dev::mfma_col(r)] = w;
+__device__ __forceinline__ float ref_coef(const PassArgs& a, float idf) { return a.ref_idf ? idf * idf : idf; }
+
+// Emit one distinct term of document d (MODE_COUNT / MODE_CSR). `pos` is the
+// entry's index in the document's list (MODE_COUNT).
+template <int MODE>
+__device__ __forceinline__ void emit_term(const PassArgs& a, int64_t d, int64_t o, int t, unsigned tf, double nrm,
+                                          int pos, int* tcount) {
+    if constexpr (MODE == MODE_COUNT) {
+        a.cnt_term[o + pos] = t;
+        a.cnt_tf[o + pos] = (int32_t)tf;
     } else {
-        const int e = atomicAdd(tcount, 1);
-        sa.ent_rank[o + e] = r;
-        sa.ent_w[o + e] = w;
-        atomicAdd(&sa.pcount[r - sa.H], 1u);
+        const float w = (float)((double)tf * (double)a.tinfo[t].idf / nrm);
+        const int r = a.rank_of[t];
+        if (r < a.H) {
+            a.wh[d * a.ldh + mrc_dev::mfma_col(r)] = w;
+        } else {
+            const int e = atomicAdd(tcount, 1);
+            a.ent_rank[o + e] = r;
+            a.ent_w[o + e] = w;
+            atomicAdd(&a.pcount[r - a.H], 1u);
+        }
     }
 }
 
+__device__ __forceinline__ void write_signature(const PassArgs& a, int64_t d, const unsigned long long* bins,
+                                                double nrm, int tid, int team) {
+    float* out = a.sig + d * a.k;
+    for (int j = tid; j < a.k; j += team) {
+        const double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * a.rinv[j] / nrm : 0.0;
+        out[j] = (float)v;
+    }
+    if (tid == 0 && a.norm) a.norm[d] = (float)nrm;
+}
+
 // Offsets check before any token is read: offsets[0] = 0, non-decreasing,
-// offsets[n] <= n_tokens. Sets kErrOffsets; the document kernels then return
-// at once.
-__global__ void k_validate_offsets(const int64_t* __restrict__ off, int64_t n, int64_t n_tokens,
-                                   unsigned long long* __restrict__ err) {
+// offsets[n] <= n_tokens, no document longer than kMaxDocLen. Sets error bits;
+// the document kernels then return at once. With `lists` set, it also lists
+// the medium documents (kShortMax < L <= kMediumMax) in lists[0..) and the
+// long ones in lists[n..), with their counts in err[1] and err[2] (one atomic
+// per wavefront and class), so the medium and long kernels visit only theirs.
+__global__ __launch_bounds__(256) void k_validate_offsets(const int64_t* __restrict__ off, int64_t n,
+                                                          int64_t n_tokens, unsigned long long* __restrict__ err,
+                                                          int32_t* __restrict__ lists) {
     const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (d > n) return;
-    bool bad = false;
-    if (d == 0) bad = off[0] != 0;
-    else bad = off[d] < off[d - 1];
-    if (d == n) bad = bad || off[n] > n_tokens || off[n] < 0;
+    bool bad = false, too_long = false, med = false, lng = false;
+    if (d <= n) {
+        const int64_t o = off[d];
+        if (d == 0) bad = o != 0;
+        else bad = o < off[d - 1];
+        if (d == n) {
+            bad = bad || o > n_tokens || o < 0;
+        } else {
+            const int64_t L = off[d + 1] - o;
+            med = L > kShortMax && L <= kMediumMax;
+            lng = L > kMediumMax;
+            too_long = L > kMaxDocLen;
+        }
+    }
     if (bad) atomicOr(err, kErrOffsets);
+    if (too_long) atomicOr(err, kErrDocLen);
+    if (lists == nullptr) return;
+    const int lane = __lane_id();
+    const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const bool f = c == 0 ? med : lng;
+        const unsigned long long m = __ballot(f);
+        if (m == 0) continue;
+        const int leader = __ffsll((long long)m) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(err + 1 + c, (unsigned long long)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (f) lists[(int64_t)c * n + (int64_t)base + __popcll(m & below)] = (int32_t)d;
+    }
+}
+
+__global__ void k_clear_words(int64_t* __restrict__ p, int n) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+__device__ __forceinline__ bool pass_disabled(const unsigned long long* err) {
+    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & (kErrOffsets | kErrDocLen);
 }
 
 // LDS layout of one team: bins u64[kpad] | keys i32[SLOTS] | cnt i32[SLOTS] |
-// used u16[SLOTS/2] | nused i32 | red (double[4])
+// used u16[SLOTS/2] (a document has at most SLOTS/2 tokens) | nused i32
+// (+pad) | red (u128[4])
 __host__ __device__ constexpr size_t team_lds_bytes(int kpad, int slots) {
-    return (size_t)kpad * 8 + (size_t)slots * 8 + (size_t)slots + 16 + 32;
+    return (size_t)kpad * 8 + (size_t)slots * 9 + 16 + 64;
 }
 
-// Documents d with lo_len < L_d <= hi_len are this kernel's; every kernel scans
-// all offsets and skips the others (no lists, no atomics). df increments go to
-// one of kDfReplicas copies of the [V] counters (chosen by document), so that
-// frequent terms do not serialise on one address; the copies are summed later.
+// Short (list == nullptr: every document with L <= hi_len) or medium (the
+// documents listed by k_validate_offsets, count in err[1]) documents.
 template <int MODE, int TEAM, int LOG2_SLOTS, int MAXPER>
 __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ off, int64_t n_docs,
                                                     int lo_len, int hi_len,
                                                     const int32_t* __restrict__ tok,
-                                                    int32_t V, uint32_t* __restrict__ df,
-                                                    SignArgs sa, unsigned long long* __restrict__ err) {
+                                                    int32_t V, PassArgs a, unsigned long long* __restrict__ err,
+                                                    const int32_t* __restrict__ list) {
     constexpr int SLOTS = 1 << LOG2_SLOTS;
     constexpr int TEAMS = kBlock / TEAM;
     extern __shared__ __align__(16) unsigned char smem[];
-    const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
+    const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
     const size_t tbytes = team_lds_bytes(kpad, SLOTS);
     const int team = threadIdx.x / TEAM;
     const int tid = threadIdx.x % TEAM;
@@ -144,9 +259,9 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     int* cnt = keys + SLOTS;
     unsigned short* used = (unsigned short*)(cnt + SLOTS);
     int* nused = (int*)(used + SLOTS / 2);
-    double* red = (double*)(base + tbytes - 32);
+    u128* red = (u128*)(base + tbytes - 64);
 
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrOffsets) return;
+    if (pass_disabled(err)) return;
     for (int s = tid; s < SLOTS; s += TEAM) {
         keys[s] = kEmpty;
         cnt[s] = 0;
@@ -155,23 +270,36 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     if (tid == 0) *nused = 0;
     team_sync<TEAM>();
 
-    for (int64_t d = (int64_t)blockIdx.x * TEAMS + team; d < n_docs; d += (int64_t)gridDim.x * TEAMS) {
+    const int64_t n_items = list ? (int64_t)__hip_atomic_load(err + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : n_docs;
+    for (int64_t item = (int64_t)blockIdx.x * TEAMS + team; item < n_items; item += (int64_t)gridDim.x * TEAMS) {
+        const int64_t d = list ? (int64_t)list[item] : item;
         const int64_t o = off[d];
         const int64_t L64 = off[d + 1] - o;
         if (L64 <= lo_len || L64 > hi_len) {
             if (!(lo_len == 0 && L64 == 0)) continue;
         }
         const int L = (int)L64;
-        uint32_t* dfr = df ? df + (size_t)(d % kDfReplicas) * (size_t)V : nullptr;
+        // all of this thread's tokens (and their term data) are loaded before
+        // the table is touched, so the loads overlap
+        int t_r[MAXPER];
+#pragma unroll
+        for (int r = 0; r < MAXPER; ++r) {
+            const int p = tid + r * TEAM;
+            t_r[r] = p < L ? tok[o + p] : kEmpty;
+        }
+        TermInfo ti_r[MAXPER];
+        if constexpr (MODE != MODE_COUNT) {
+#pragma unroll
+            for (int r = 0; r < MAXPER; ++r)
+                ti_r[r] = (unsigned)t_r[r] < (unsigned)V ? a.tinfo[t_r[r]] : TermInfo{1.f, -1};
+        }
         int slot_r[MAXPER];
-        float idf_r[MAXPER];
 #pragma unroll
         for (int r = 0; r < MAXPER; ++r) {
             slot_r[r] = -1;
-            idf_r[r] = 0.f;
-            const int p = tid + r * TEAM;
-            if (p < L) {
-                const int t = tok[o + p];
+            if (tid + r * TEAM < L) {
+                const int t = t_r[r];
                 if ((unsigned)t >= (unsigned)V) {
                     atomicOr(err, kErrToken);
                     continue;
@@ -179,7 +307,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
                 int h = hash_slot(t, LOG2_SLOTS);
                 bool won = false;
                 while (true) {
-                    int prev = atomicCAS(&keys[h], kEmpty, t);
+                    const int prev = atomicCAS(&keys[h], kEmpty, t);
                     if (prev == kEmpty) {
                         won = true;
                         break;
@@ -187,55 +315,45 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
                     if (prev == t) break;
                     h = (h + 1) & (SLOTS - 1);
                 }
-                int old = atomicAdd(&cnt[h], 1);
+                atomicAdd(&cnt[h], 1);
                 if (won) used[atomicAdd(nused, 1)] = (unsigned short)h;
-                if constexpr (MODE == MODE_DF) {
-                    if (old == 0) atomicAdd(&dfr[t], 1u);
-                } else {
-                    (void)old;
-                    TermInfo ti = sa.tinfo[t];
-                    slot_r[r] = h;
-                    idf_r[r] = ti.idf;
-                    if (MODE == MODE_SIGN && ti.part >= 0) {
-                        float c = sa.ref_idf ? ti.idf * ti.idf : ti.idf;
-                        atomicAdd(&bins[ti.part], mrc_dev::fixed32(c));
-                    }
+                slot_r[r] = h;
+                if constexpr (MODE == MODE_SIGN) {
+                    if (ti_r[r].part >= 0) atomicAdd(&bins[ti_r[r].part], mrc_dev::fixed32(ref_coef(a, ti_r[r].idf)));
                 }
             }
         }
         team_sync<TEAM>();
         double nrm = 0.0;
-        if constexpr (MODE != MODE_DF) {
-            float nacc = 0.f;
+        if constexpr (MODE != MODE_COUNT) {
+            u128 nacc = 0;
 #pragma unroll
-            for (int r = 0; r < MAXPER; ++r) {
-                if (slot_r[r] >= 0) nacc += (float)cnt[slot_r[r]] * (idf_r[r] * idf_r[r]);
-            }
-            float n2 = team_sum<TEAM, float>(nacc, (float*)red);
-            nrm = (double)sqrtf(n2);
+            for (int r = 0; r < MAXPER; ++r)
+                if (slot_r[r] >= 0) nacc += occ_sq_fixed((uint32_t)cnt[slot_r[r]], ti_r[r].idf);
+            nrm = norm_from_fixed(team_sum<TEAM>(nacc, red));
         }
-        if constexpr (MODE == MODE_SIGN) {
-            float* out = sa.sig + (int64_t)d * sa.k;
-            for (int j = tid; j < sa.k; j += TEAM) {
-                double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
-                out[j] = (float)v;
-            }
-            if (tid == 0 && sa.norm) sa.norm[d] = (float)nrm;
-        }
-        team_sync<TEAM>();
+        if constexpr (MODE == MODE_SIGN) write_signature(a, d, bins, nrm, tid, TEAM);
         const int nu = *nused;
-        if constexpr (MODE == MODE_CSR) {
+        if constexpr (MODE == MODE_COUNT) {
+            for (int u = tid; u < nu; u += TEAM) {
+                const int sl = used[u];
+                emit_term<MODE_COUNT>(a, d, o, keys[sl], (unsigned)cnt[sl], 0.0, u, nullptr);
+            }
+            for (int u = nu + tid; u < L; u += TEAM) a.cnt_term[o + u] = kEmpty;  // unused slots
+            if (tid == 0) a.cnt_nnz[d] = nu;
+        } else if constexpr (MODE == MODE_CSR) {
             int* tcount = (int*)red;
+            team_sync<TEAM>();
             if (tid == 0) *tcount = 0;
             team_sync<TEAM>();
             for (int u = tid; u < nu; u += TEAM) {
                 const int sl = used[u];
-                csr_emit(sa, d, o, keys[sl], (unsigned)cnt[sl], nrm, tcount);
+                emit_term<MODE_CSR>(a, d, o, keys[sl], (unsigned)cnt[sl], nrm, u, tcount);
             }
             team_sync<TEAM>();
-            if (tid == 0) sa.nnz_tail[d] = *tcount;
-            team_sync<TEAM>();
+            if (tid == 0) a.nnz_tail[d] = *tcount;
         }
+        team_sync<TEAM>();
         for (int u = tid; u < nu; u += TEAM) {
             const int s = used[u];
             keys[s] = kEmpty;
@@ -248,92 +366,80 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     }
 }
 
-// Long documents: a [V] uint32 count table per workgroup in global memory
-// (all zero between documents).
+// Long documents (listed by k_validate_offsets, count in err[2]): a [V]
+// uint32 count table per workgroup in global memory (all zero between
+// documents).
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off, int64_t n_docs,
-                                                       int lo_len,
-                                                       const int32_t* __restrict__ tok,
-                                                       int32_t V, uint32_t* __restrict__ df,
-                                                       SignArgs sa, uint32_t* __restrict__ tables,
-                                                       unsigned long long* __restrict__ err) {
+__global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off, int32_t V,
+                                                       const int32_t* __restrict__ tok, PassArgs a,
+                                                       uint32_t* __restrict__ tables,
+                                                       unsigned long long* __restrict__ err,
+                                                       const int32_t* __restrict__ list) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long* bins = (unsigned long long*)smem;
-    const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
-    double* red = (double*)(smem + (size_t)kpad * 8);
+    const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
+    u128* red = (u128*)(smem + (size_t)kpad * 8);
+    int* tcount = (int*)(red + 4);
     uint32_t* cnt = tables + (size_t)blockIdx.x * (size_t)V;
     const int tid = threadIdx.x;
-    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & kErrOffsets) return;
+    if (pass_disabled(err)) return;
     for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
     __syncthreads();
-    for (int64_t d = blockIdx.x; d < n_docs; d += gridDim.x) {
+    const int64_t n_items = (int64_t)__hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t d = list[item];
         const int64_t o = off[d];
         const int64_t L = off[d + 1] - o;
-        if (L <= lo_len) continue;
-        uint32_t* dfr = df ? df + (size_t)(d % kDfReplicas) * (size_t)V : nullptr;
         for (int64_t p = tid; p < L; p += kBlock) {
             const int t = tok[o + p];
             if ((unsigned)t >= (unsigned)V) {
                 atomicOr(err, kErrToken);
                 continue;
             }
-            unsigned old = atomicAdd(&cnt[t], 1u);
-            if constexpr (MODE == MODE_DF) {
-                if (old == 0) atomicAdd(&dfr[t], 1u);
-            } else if constexpr (MODE == MODE_SIGN) {
-                (void)old;
-                TermInfo ti = sa.tinfo[t];
-                if (ti.part >= 0) {
-                    float c = sa.ref_idf ? ti.idf * ti.idf : ti.idf;
-                    atomicAdd(&bins[ti.part], mrc_dev::fixed32(c));
-                }
+            atomicAdd(&cnt[t], 1u);
+            if constexpr (MODE == MODE_SIGN) {
+                const TermInfo ti = a.tinfo[t];
+                if (ti.part >= 0) atomicAdd(&bins[ti.part], mrc_dev::fixed32(ref_coef(a, ti.idf)));
             }
         }
         __threadfence();
         __syncthreads();
-        if constexpr (MODE != MODE_DF) {
-            double nrm;
-            if (L > kFp64NormMin) {
-                double acc = 0.0;
-                for (int64_t p = tid; p < L; p += kBlock) {
-                    const int t = tok[o + p];
-                    if ((unsigned)t >= (unsigned)V) continue;
-                    unsigned tf = __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    double idf = (double)sa.tinfo[t].idf;
-                    acc += (double)tf * idf * idf;
-                }
-                nrm = sqrt(team_sum<kBlock, double>(acc, red));
-            } else {
-                float acc = 0.f;
-                for (int64_t p = tid; p < L; p += kBlock) {
-                    const int t = tok[o + p];
-                    if ((unsigned)t >= (unsigned)V) continue;
-                    unsigned tf = __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    float idf = sa.tinfo[t].idf;
-                    acc += (float)tf * (idf * idf);
-                }
-                nrm = (double)sqrtf(team_sum<kBlock, float>(acc, (float*)red));
+        double nrm = 0.0;
+        if constexpr (MODE != MODE_COUNT) {
+            u128 acc = 0;
+            for (int64_t p = tid; p < L; p += kBlock) {
+                const int t = tok[o + p];
+                if ((unsigned)t >= (unsigned)V) continue;
+                const unsigned tf = __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                acc += occ_sq_fixed(tf, a.tinfo[t].idf);
             }
-            if constexpr (MODE == MODE_SIGN) {
-                float* out = sa.sig + (int64_t)d * sa.k;
-                for (int j = tid; j < sa.k; j += kBlock) {
-                    double v = nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * sa.rinv[j] / nrm : 0.0;
-                    out[j] = (float)v;
+            nrm = norm_from_fixed(team_sum<kBlock>(acc, red));
+        }
+        if constexpr (MODE == MODE_SIGN) {
+            write_signature(a, d, bins, nrm, tid, kBlock);
+        } else {
+            // each distinct term once: the occurrence that swaps its count out emits it
+            if (tid == 0) *tcount = 0;
+            __syncthreads();
+            for (int64_t p = tid; p < L; p += kBlock) {
+                const int t = tok[o + p];
+                if ((unsigned)t >= (unsigned)V) continue;
+                const unsigned tf = atomicExch(&cnt[t], 0u);
+                if (tf > 0) {
+                    if constexpr (MODE == MODE_COUNT) {
+                        emit_term<MODE_COUNT>(a, d, o, t, tf, 0.0, atomicAdd(tcount, 1), nullptr);
+                    } else {
+                        emit_term<MODE_CSR>(a, d, o, t, tf, nrm, 0, tcount);
+                    }
                 }
-                if (tid == 0 && sa.norm) sa.norm[d] = (float)nrm;
+            }
+            __syncthreads();
+            if constexpr (MODE == MODE_COUNT) {
+                const int nu = *tcount;
+                for (int64_t u = nu + tid; u < L; u += kBlock) a.cnt_term[o + u] = kEmpty;  // unused slots
+                if (tid == 0) a.cnt_nnz[d] = nu;
             } else {
-                // each distinct term once: the first occurrence to swap its count out emits it
-                int* tcount = (int*)(red + 2);
-                if (tid == 0) *tcount = 0;
-                __syncthreads();
-                for (int64_t p = tid; p < L; p += kBlock) {
-                    const int t = tok[o + p];
-                    if ((unsigned)t >= (unsigned)V) continue;
-                    const unsigned tf = atomicExch(&cnt[t], 0u);
-                    if (tf > 0) csr_emit(sa, d, o, t, tf, nrm, tcount);
-                }
-                __syncthreads();
-                if (tid == 0) sa.nnz_tail[d] = *tcount;
+                if (tid == 0) a.nnz_tail[d] = *tcount;
             }
         }
         __syncthreads();
@@ -348,10 +454,143 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
     }
 }
 
+// ------------------------------------------------------------ df from counts
+
+// One workgroup per (vocabulary slice, document range): the distinct terms
+// listed in the range's token slots (slots holding -1 are unused) that fall
+// inside the slice are counted in LDS, two 16-bit counters per word (a term
+// is listed at most once per document and a range holds at most 65535
+// documents), and the slice's counts are written to partial[range][...].
+constexpr int kHistThreads = 1024;
+__global__ __launch_bounds__(kHistThreads) void k_df_hist(const int64_t* __restrict__ off, int64_t n,
+                                                          const int32_t* __restrict__ term, int groups,
+                                                          uint32_t* __restrict__ partial, int64_t words,
+                                                          const unsigned long long* __restrict__ err) {
+    __shared__ uint32_t h[kHistSlice / 2];
+    if (pass_disabled(err)) return;
+    const int slice = blockIdx.x / groups, g = blockIdx.x % groups;
+    const int t0 = slice * kHistSlice;
+    for (int i = threadIdx.x; i < kHistSlice / 2; i += kHistThreads) h[i] = 0u;
+    __syncthreads();
+    const int64_t e0 = off[n * g / groups], e1 = off[n * (g + 1) / groups];
+    constexpr int U = 8;
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)U * kHistThreads) {
+        int32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t x = e + (int64_t)u * kHistThreads;
+            v[u] = x < e1 ? term[x] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const unsigned t = (unsigned)(v[u] - t0);
+            if (v[u] >= 0 && t < (unsigned)kHistSlice) atomicAdd(&h[t >> 1], 1u << ((t & 1u) * 16u));
+        }
+    }
+    __syncthreads();
+    uint32_t* dst = partial + (size_t)g * (size_t)words + (size_t)(t0 / 2);
+    for (int i = threadIdx.x; i < kHistSlice / 2; i += kHistThreads) dst[i] = h[i];
+}
+
+// df = the sum of the partial counts: 64 words per wavefront (coalesced), the
+// 4 wavefronts of a block over interleaved quarters of the ranges.
+__global__ __launch_bounds__(256) void k_df_sum(const uint32_t* __restrict__ partial, int groups, int64_t words,
+                                                int32_t V, uint32_t* __restrict__ df) {
+    __shared__ uint32_t red[2][4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t w = (int64_t)blockIdx.x * 64 + lane;
+    uint32_t lo = 0, hi = 0;
+    if (w < words) {
+        for (int g = wv; g < groups; g += 4) {
+            const uint32_t x = partial[(size_t)g * (size_t)words + (size_t)w];
+            lo += x & 0xFFFFu;
+            hi += x >> 16;
+        }
+    }
+    red[0][wv][lane] = lo;
+    red[1][wv][lane] = hi;
+    __syncthreads();
+    if (wv == 0 && w < words) {
+        lo = red[0][0][lane] + red[0][1][lane] + red[0][2][lane] + red[0][3][lane];
+        hi = red[1][0][lane] + red[1][1][lane] + red[1][2][lane] + red[1][3][lane];
+        if (2 * w < V) df[2 * w] = lo;
+        if (2 * w + 1 < V) df[2 * w + 1] = hi;
+    }
+}
+
+// Large vocabularies: one atomic per distinct (document, term).
+__global__ __launch_bounds__(256) void k_df_atomic(const int64_t* __restrict__ off, int64_t n,
+                                                   const int32_t* __restrict__ term,
+                                                   const int32_t* __restrict__ nnz, uint32_t* __restrict__ df,
+                                                   const unsigned long long* __restrict__ err) {
+    if (pass_disabled(err)) return;
+    const int lane = threadIdx.x & 63;
+    for (int64_t d = ((int64_t)blockIdx.x * 256 + threadIdx.x) / 64; d < n; d += (int64_t)gridDim.x * 4) {
+        const int64_t o = off[d];
+        const int m = nnz[d];
+        for (int e = lane; e < m; e += 64) atomicAdd(&df[term[o + e]], 1u);
+    }
+}
+
+// ------------------------------------------------------- sign from counts
+
+// One wavefront per document over its distinct-term list (same exact sums as
+// the hash passes, so the same signature bits).
+__global__ __launch_bounds__(256) void k_sign_counts(const int64_t* __restrict__ off, int64_t n,
+                                                     const int32_t* __restrict__ term,
+                                                     const int32_t* __restrict__ tfv,
+                                                     const int32_t* __restrict__ nnz, PassArgs a,
+                                                     const unsigned long long* __restrict__ err) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int kpad = (a.k + 1) & ~1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    unsigned long long* bins = (unsigned long long*)smem + (size_t)wave * kpad;
+    if (pass_disabled(err)) return;
+    for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
+    for (int64_t d = (int64_t)blockIdx.x * 4 + wave; d < n; d += (int64_t)gridDim.x * 4) {
+        const int64_t o = off[d];
+        const int m = nnz[d];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        u128 nacc = 0;
+        for (int e0 = 0; e0 < m; e0 += 256) {
+            int t_r[4], f_r[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int e = e0 + r * 64 + lane;
+                t_r[r] = e < m ? term[o + e] : -1;
+                f_r[r] = e < m ? tfv[o + e] : 0;
+            }
+            TermInfo ti_r[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) ti_r[r] = t_r[r] >= 0 ? a.tinfo[t_r[r]] : TermInfo{1.f, -1};
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (t_r[r] < 0) continue;
+                nacc += term_sq_fixed((uint32_t)f_r[r], ti_r[r].idf);
+                if (ti_r[r].part >= 0)
+                    atomicAdd(&bins[ti_r[r].part],
+                              (unsigned long long)f_r[r] * mrc_dev::fixed32(ref_coef(a, ti_r[r].idf)));
+            }
+        }
+        const double nrm = norm_from_fixed(wave_sum_u128(nacc));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        write_signature(a, d, bins, nrm, lane, 64);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
+    }
+}
+
+// ------------------------------------------------------------------- driver
+
 constexpr int kShortTeam = 64, kShortLog2 = 10, kShortPer = kShortMax / 64;      // 1024 slots
 constexpr int kMedTeam = 256, kMedLog2 = 13, kMedPer = kMediumMax / 256;         // 8192 slots
 static_assert((1 << kShortLog2) >= 2 * kShortMax, "short table load factor");
 static_assert((1 << kMedLog2) >= 2 * kMediumMax, "medium table load factor");
+static_assert((1 << kMedLog2) <= 65536, "slot indices are stored as uint16");
 
 int grid_for(int64_t n_items_upper, int teams_per_block, int cap) {
     int64_t g = ceil_div(n_items_upper, teams_per_block);
@@ -360,60 +599,43 @@ int grid_for(int64_t n_items_upper, int teams_per_block, int cap) {
     return (int)g;
 }
 
-__global__ void k_df_reduce(const uint32_t* __restrict__ rep, int32_t V, uint32_t* __restrict__ df) {
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= V) return;
-    uint32_t s = 0;
-#pragma unroll 8
-    for (int r = 0; r < kDfReplicas; ++r) s += rep[(size_t)r * V + t];
-    df[t] = s;
-}
-
 template <int MODE>
-mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* df, const SignArgs& sa,
-                       hipStream_t s, const char* name) {
+mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const PassArgs& a, hipStream_t s,
+                       const char* name) {
     const int64_t n = docs->n_docs;
     unsigned long long* err = (unsigned long long*)ctx->d_flags;
-    MRC_TRY(launch_validate_offsets(ctx, docs, s));
+    void* lists = nullptr;
+    if (n > 0) MRC_TRY(scratch(ctx, "doc_lists", (size_t)2 * (size_t)n * sizeof(int32_t), &lists));
+    MRC_TRY(launch_validate_offsets(ctx, docs, s, (int32_t*)lists));
     if (n == 0) return MRC_OK;
-    const int kpad = MODE == MODE_SIGN ? ((sa.k + 1) & ~1) : 0;
-    const size_t rep_bytes = (size_t)kDfReplicas * (size_t)V * sizeof(uint32_t);
-    void* rep = nullptr;
-    if (MODE == MODE_DF) {
-        MRC_TRY(scratch(ctx, "df_replicas", rep_bytes, &rep));
-        MRC_HIP_TRY(ctx, hipMemsetAsync(rep, 0, rep_bytes, s));
-    }
-    uint32_t* dfk = (uint32_t*)rep;
+    const int32_t* med_list = (const int32_t*)lists;
+    const int32_t* long_list = med_list + n;
+    const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
     ScopedTimer tm(ctx, name, s);
     {
-        size_t lds = team_lds_bytes(kpad, 1 << kShortLog2) * (kBlock / kShortTeam);
-        int grid = grid_for(n, kBlock / kShortTeam, 256 * 8);
+        const size_t lds = team_lds_bytes(kpad, 1 << kShortLog2) * (kBlock / kShortTeam);
+        const int grid = grid_for(n, kBlock / kShortTeam, 256 * 8);
         hipLaunchKernelGGL((k_doc_lds<MODE, kShortTeam, kShortLog2, kShortPer>), dim3(grid), dim3(kBlock),
-                           lds, s, docs->offsets, n, 0, kShortMax, docs->tokens, V, dfk, sa, err);
+                           lds, s, docs->offsets, n, 0, kShortMax, docs->tokens, V, a, err, nullptr);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
-        size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
-        int grid = grid_for(n, 1, 256 * 2);
+        const size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
+        const int grid = grid_for(n, 1, 256 * 2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid), dim3(kBlock), lds, s,
-                           docs->offsets, n, kShortMax, kMediumMax, docs->tokens, V, dfk, sa, err);
+                           docs->offsets, n, kShortMax, kMediumMax, docs->tokens, V, a, err, med_list);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
         const size_t table_bytes = (size_t)kLongBlocks * (size_t)V * sizeof(uint32_t);
         auto it = ctx->scratch.find("long_tables");
-        bool fresh = it == ctx->scratch.end() || it->second.second < table_bytes;
+        const bool fresh = it == ctx->scratch.end() || it->second.second < table_bytes;
         void* tables = nullptr;
         MRC_TRY(scratch(ctx, "long_tables", table_bytes, &tables));
         if (fresh) MRC_HIP_TRY(ctx, hipMemsetAsync(tables, 0, ctx->scratch["long_tables"].second, s));
-        size_t lds = (size_t)kpad * 8 + 32;
-        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets, n,
-                           kMediumMax, docs->tokens, V, dfk, sa, (uint32_t*)tables, err);
-        MRC_HIP_TRY(ctx, hipGetLastError());
-    }
-    if (MODE == MODE_DF) {
-        hipLaunchKernelGGL(k_df_reduce, dim3((unsigned)ceil_div(V, 256)), dim3(256), 0, s, (const uint32_t*)rep,
-                           V, df);
+        const size_t lds = (size_t)kpad * 8 + 4 * sizeof(u128) + 16;
+        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets, V,
+                           docs->tokens, a, (uint32_t*)tables, err, long_list);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     return MRC_OK;
@@ -423,45 +645,113 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* 
 
 namespace mrc {
 
-mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s) {
-    MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, sizeof(int64_t), s));
-    const int64_t n = docs->n_docs;
-    if (n == 0) return MRC_OK;
-    hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, docs->offsets, n,
-                       docs->n_tokens, (unsigned long long*)ctx->d_flags);
+mrc_status clear_words(mrc_ctx* ctx, int64_t* p, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_words, dim3((unsigned)ceil_div(n, 64)), dim3(64), 0, s, p, n);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }
 
-mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, hipStream_t s) {
-    SignArgs sa{};
-    return run_docpass<MODE_DF>(ctx, docs, vocab, d_df, sa, s, "df");
+mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s, int32_t* lists) {
+    MRC_TRY(clear_words(ctx, ctx->d_flags, 3, s));
+    const int64_t n = docs->n_docs;
+    if (n == 0) return MRC_OK;
+    hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, docs->offsets, n,
+                       docs->n_tokens, (unsigned long long*)ctx->d_flags, lists);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+mrc_status count_scratch(mrc_ctx* ctx, const mrc_docs* docs, CountLists* c) {
+    const size_t T = (size_t)std::max<int64_t>(docs->n_tokens, 1);
+    void *pt = nullptr, *pf = nullptr, *pn = nullptr;
+    MRC_TRY(scratch(ctx, "count_term", T * sizeof(int32_t), &pt));
+    MRC_TRY(scratch(ctx, "count_tf", T * sizeof(int32_t), &pf));
+    MRC_TRY(scratch(ctx, "count_nnz", (size_t)std::max<int64_t>(docs->n_docs, 1) * sizeof(int32_t), &pn));
+    c->term = (int32_t*)pt;
+    c->tf = (int32_t*)pf;
+    c->nnz = (int32_t*)pn;
+    return MRC_OK;
+}
+
+mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* d_df, const CountLists& c,
+                     hipStream_t s) {
+    const int64_t n = docs->n_docs;
+    PassArgs a{};
+    a.cnt_term = c.term;
+    a.cnt_tf = c.tf;
+    a.cnt_nnz = c.nnz;
+    MRC_TRY(run_docpass<MODE_COUNT>(ctx, docs, V, a, s, "df_count"));
+    if (n == 0) {
+        MRC_HIP_TRY(ctx, hipMemsetAsync(d_df, 0, (size_t)V * 4, s));
+        return MRC_OK;
+    }
+    const unsigned long long* err = (const unsigned long long*)ctx->d_flags;
+    ScopedTimer tm(ctx, "df_hist", s);
+    const int slices = (int)ceil_div(V, kHistSlice);
+    if (slices > kHistMaxSlices) {
+        MRC_HIP_TRY(ctx, hipMemsetAsync(d_df, 0, (size_t)V * 4, s));
+        hipLaunchKernelGGL(k_df_atomic, dim3(grid_for(n, 4, 256 * 8)), dim3(256), 0, s, docs->offsets, n, c.term,
+                           c.nnz, d_df, err);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+        return MRC_OK;
+    }
+    // document ranges of at most 65535 documents; about 256 workgroups in all
+    const int64_t groups = std::max<int64_t>(ceil_div(n, 65535), std::min<int64_t>(ceil_div(256, slices), n));
+    const int64_t words = (int64_t)slices * kHistSlice / 2;
+    void* partial = nullptr;
+    MRC_TRY(scratch(ctx, "df_partial", (size_t)groups * (size_t)words * sizeof(uint32_t), &partial));
+    hipLaunchKernelGGL(k_df_hist, dim3((unsigned)(slices * groups)), dim3(kHistThreads), 0, s, docs->offsets, n,
+                       c.term, (int)groups, (uint32_t*)partial, words, err);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    hipLaunchKernelGGL(k_df_sum, dim3((unsigned)ceil_div(words, 64)), dim3(256), 0, s, (const uint32_t*)partial,
+                       (int)groups, words, V, d_df);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+mrc_status launch_sign_counts(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const CountLists& c,
+                              float* sig_out, float* norm_out, hipStream_t s) {
+    const int64_t n = docs->n_docs;
+    if (n == 0) return MRC_OK;
+    PassArgs a{};
+    a.tinfo = m->d_tinfo;
+    a.rinv = m->d_rinv;
+    a.k = m->k;
+    a.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
+    a.sig = sig_out;
+    a.norm = norm_out;
+    const size_t lds = (size_t)4 * (size_t)((m->k + 1) & ~1) * 8;
+    ScopedTimer tm(ctx, "sign_counts", s);
+    hipLaunchKernelGGL(k_sign_counts, dim3(grid_for(n, 4, 256 * 16)), dim3(256), lds, s, docs->offsets, n, c.term,
+                       c.tf, c.nnz, a, (const unsigned long long*)ctx->d_flags);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
 }
 
 mrc_status launch_csr(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const CsrOut& c, hipStream_t s) {
-    SignArgs sa{};
-    sa.tinfo = m->d_tinfo;
-    sa.rank_of = m->d_rank_of;
-    sa.H = c.H;
-    sa.ldh = c.ldh;
-    sa.wh = c.wh;
-    sa.ent_rank = c.ent_rank;
-    sa.ent_w = c.ent_w;
-    sa.nnz_tail = c.nnz_tail;
-    sa.pcount = c.pcount;
-    return run_docpass<MODE_CSR>(ctx, docs, m->vocab, nullptr, sa, s, "csr");
+    PassArgs a{};
+    a.tinfo = m->d_tinfo;
+    a.rank_of = m->d_rank_of;
+    a.H = c.H;
+    a.ldh = c.ldh;
+    a.wh = c.wh;
+    a.ent_rank = c.ent_rank;
+    a.ent_w = c.ent_w;
+    a.nnz_tail = c.nnz_tail;
+    a.pcount = c.pcount;
+    return run_docpass<MODE_CSR>(ctx, docs, m->vocab, a, s, "csr");
 }
 
 mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, float* sig_out,
                        float* norm_out, hipStream_t s) {
-    SignArgs sa{};
-    sa.tinfo = m->d_tinfo;
-    sa.rinv = m->d_rinv;
-    sa.k = m->k;
-    sa.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
-    sa.sig = sig_out;
-    sa.norm = norm_out;
-    return run_docpass<MODE_SIGN>(ctx, docs, m->vocab, nullptr, sa, s, "sign");
+    PassArgs a{};
+    a.tinfo = m->d_tinfo;
+    a.rinv = m->d_rinv;
+    a.k = m->k;
+    a.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
+    a.sig = sig_out;
+    a.norm = norm_out;
+    return run_docpass<MODE_SIGN>(ctx, docs, m->vocab, a, s, "sign");
 }
 
 }  // namespace mrc

@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_sort_tail(const int64_t* __restrict__ o
         const int m = nnz_tail[d];
         if (m <= 1) continue;
         if (m > kSortCap) {
-            if (threadIdx.x == 0) atomicOr(err, 8ull);
+            if (threadIdx.x == 0) atomicOr(err, kErrTailCap);
             continue;
         }
         const int64_t o = off[d];

@@ -302,7 +302,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
     const int q = blockIdx.x;
     const int nc = ccount[q];
     if (nc > cap) {
-        if (threadIdx.x == 0) atomicOr(err, 16ull);
+        if (threadIdx.x == 0) atomicOr(err, kErrQueryCap);
         return;
     }
     if (threadIdx.x == 0) shits = 0;
@@ -517,7 +517,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         MRC_TRY(scratch(ctx, "q_cand", (size_t)nq * cap * 8, &cand));
         MRC_TRY(scratch(ctx, "q_ccount", (size_t)nq * 4, &cc));
         MRC_HIP_TRY(ctx, hipMemsetAsync(cc, 0, (size_t)nq * 4, s));
-        MRC_HIP_TRY(ctx, hipMemsetAsync(ctx->d_flags, 0, 8, s));
+        MRC_TRY(clear_words(ctx, ctx->d_flags, 1, s));
         a.thr = (const float*)thr;
         a.cand = (int64_t*)cand;
         a.ccount = (int32_t*)cc;

@@ -84,7 +84,7 @@ __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off
                     h = hash[t];
                     valid = true;
                 } else {
-                    atomicOr(err, 2ull);
+                    atomicOr(err, kErrToken);
                 }
             }
             const unsigned long long vm = __ballot(valid);

@@ -33,7 +33,7 @@ REQ_QUERY, REQ_INSERT = 0, 1
 # names of the exported C functions (checked against include/mrc.h by the tests)
 EXPORTS = (
     "mrc_ctx_create", "mrc_ctx_destroy", "mrc_ctx_memory", "mrc_ctx_set_timing", "mrc_ctx_kernel_time",
-    "mrc_last_error", "mrc_build_vocab_idf", "mrc_model_destroy", "mrc_model_info", "mrc_model_get",
+    "mrc_last_error", "mrc_build_vocab_idf", "mrc_build_and_sign", "mrc_model_destroy", "mrc_model_info", "mrc_model_get",
     "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_compare", "mrc_normalise", "mrc_score_pairs",
     "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
     "mrc_db_destroy", "mrc_db_insert", "mrc_db_insert_docs", "mrc_db_size", "mrc_db_save", "mrc_db_load",
@@ -104,6 +104,7 @@ _SIGS = {
     "mrc_ctx_set_timing": [_P, C.c_int32],
     "mrc_ctx_kernel_time": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "mrc_build_vocab_idf": [_P, C.POINTER(MrcDocs), C.c_int32, C.POINTER(MrcRefSpec), C.POINTER(_P), _P],
+    "mrc_build_and_sign": [_P, C.POINTER(MrcDocs), C.c_int32, C.POINTER(MrcRefSpec), C.POINTER(_P), _P, _P, _P],
     "mrc_model_destroy": [_P],
     "mrc_model_info": [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                        C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
@@ -268,6 +269,22 @@ def mrc_build_vocab_idf(ctx, offsets, tokens, vocab_size, spec, stream=None):
     _check(lib().mrc_build_vocab_idf(ctx, C.byref(d), int(vocab_size), C.byref(spec), C.byref(p),
                                      _stream(stream)), "mrc_build_vocab_idf")
     return Model(p, ctx)
+
+
+def mrc_build_and_sign(ctx, offsets, tokens, vocab_size, spec, sig_out=None, norm_out=None, stream=None,
+                       with_norm=False):
+    """Model of the corpus and the corpus' signatures in one call. Returns (model, sig[, norm])."""
+    d, _keep = _docs(offsets, tokens)
+    if sig_out is None:
+        sig_out = torch.empty((d.n_docs, spec.k), dtype=torch.float32, device=offsets.device)
+    if norm_out is None and with_norm:
+        norm_out = torch.empty((d.n_docs,), dtype=torch.float32, device=offsets.device)
+    p = C.c_void_p()
+    _check(lib().mrc_build_and_sign(ctx, C.byref(d), int(vocab_size), C.byref(spec), C.byref(p),
+                                    _dptr(sig_out, torch.float32, "sig_out"), _dptr(norm_out, torch.float32, "norm_out"),
+                                    _stream(stream)), "mrc_build_and_sign")
+    m = Model(p, ctx)
+    return (m, sig_out, norm_out) if with_norm else (m, sig_out)
 
 
 def mrc_model_info(model):

@@ -83,8 +83,8 @@ def test_reference_modes(lib, ctx, mode, kw):
 
 def test_edge_documents(lib, ctx):
     """Empty documents, one-token documents, the largest id, documents in every
-    length class (LDS wavefront / LDS workgroup / global table) and past 10^4
-    tokens (float64 norm), 50,000 repeats of one id."""
+    length class (LDS wavefront / LDS workgroup / global table), 50,000
+    repeats of one id."""
     rng = np.random.default_rng(4)
     V = 4096
     docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
@@ -99,6 +99,75 @@ def test_edge_documents(lib, ctx):
     assert np.abs(sig - osig).max() <= SIG_TOL
     np.testing.assert_allclose(norm, onorm, rtol=2e-6)
     assert np.all(sig[0] == 0) and norm[0] == 0
+
+
+def _edge_corpus():
+    rng = np.random.default_rng(4)
+    V = 4096
+    docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
+    for L in (1, 63, 64, 65, 511, 512, 513, 4095, 4096, 4097, 9999, 10001, 30000):
+        docs.append(rng.zipf(1.3, L).astype(np.int64) % V)
+    docs.append(np.full(50_000, 7, np.int32))
+    docs += [rng.integers(0, V, int(rng.integers(0, 300))) for _ in range(200)]
+    return synth.from_docs(docs, V)
+
+
+@pytest.mark.parametrize("which", ["small", "full3000", "edge"])
+def test_build_and_sign_equals_build_then_sign(lib, ctx, which):
+    """The fused call signs the model corpus from the build's count lists; it
+    must give the same model and the same signature and norm bits."""
+    if which == "edge":
+        c, k, mode = _edge_corpus(), 8, om.SEL_ALL
+    else:
+        c = synth.generate(0) if which == "small" else synth.generate(1, n_docs=3000)
+        k, mode = (16, om.SEL_DROP_TOP) if which == "small" else (64, om.SEL_DROP_TOP)
+    _, gspec = _spec_pair(lib, k, mode)
+    o, t = device_docs(c)
+    flush(f"  fused build+sign {which} n={c.n_docs}")
+    gm, sig, norm = lib.mrc_build_and_sign(ctx, o, t, c.vocab, gspec, with_norm=True)
+    gm2 = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    sig2, norm2 = lib.mrc_sign(ctx, gm2, o, t, with_norm=True)
+    a, b = lib.mrc_model_get(gm), lib.mrc_model_get(gm2)
+    for key in ("df", "idf", "term_at", "rank_of", "part_of", "rnorm"):
+        np.testing.assert_array_equal(a[key], b[key])
+    np.testing.assert_array_equal(sig.cpu().numpy(), sig2.cpu().numpy())
+    np.testing.assert_array_equal(norm.cpu().numpy(), norm2.cpu().numpy())
+    omodel = om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=k, mode=mode))
+    osig, _ = om.sign(c.offsets, c.tokens, omodel)
+    assert np.abs(sig.cpu().numpy() - osig).max() <= SIG_TOL
+
+
+def test_norm_is_exact_sum_rounded_once(lib, ctx):
+    """|w_d| is the square root of the exact sum of (tf * idf32)^2, rounded to
+    float64 once, square-rooted in float64, then rounded to float32; checked
+    against exact rational arithmetic on the GPU model's own float32 idf."""
+    import math
+    from fractions import Fraction
+    c = _edge_corpus()
+    _, gspec = _spec_pair(lib, 8, om.SEL_ALL)
+    o, t = device_docs(c)
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    _, norm = lib.mrc_sign(ctx, gm, o, t, with_norm=True)
+    norm = norm.cpu().numpy()
+    idf = lib.mrc_model_get(gm)["idf"]
+    for d in range(c.n_docs):
+        ids, tf = np.unique(c.doc(d), return_counts=True)
+        exact = sum(Fraction(int(f)) ** 2 * Fraction(float(idf[i])) ** 2 for i, f in zip(ids, tf))
+        want = np.float32(math.sqrt(float(exact))) if exact else np.float32(0)
+        assert norm[d] == want, (d, norm[d], want)
+
+
+def test_large_vocabulary_df(lib, ctx):
+    """A vocabulary past the LDS histogram slices (df by atomics) and one just
+    inside them: df bit-exact, signatures within tolerance."""
+    rng = np.random.default_rng(9)
+    for V in (8 * 65536, 8 * 65536 + 1000):
+        docs = [rng.integers(0, V, int(rng.integers(1, 700))) for _ in range(600)]
+        docs.append(np.array([V - 1], np.int32))
+        c = synth.from_docs(docs, V)
+        gm, omodel, sig, norm, osig, onorm = _run(lib, ctx, c, 32, om.SEL_ALL)
+        _check_model(lib, gm, omodel, V)
+        assert np.abs(sig - osig).max() <= SIG_TOL
 
 
 def test_sign_is_deterministic_and_batch_independent(lib, ctx):
@@ -148,6 +217,14 @@ def test_invalid_inputs_raise(lib, ctx):
         lib.mrc_build_vocab_idf(ctx, boff, t, c.vocab, gspec)
     with pytest.raises(lib.MrcError):                     # more parts than selected terms
         lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(16, mode=lib.SEL_RAREST, m=10))
+    # a document longer than 2^22 tokens
+    long_o = torch.tensor([0, 5, 5 + (1 << 22) + 1], dtype=torch.int64, device="cuda")
+    long_t = torch.zeros((1 << 22) + 6, dtype=torch.int32, device="cuda")
+    with pytest.raises(lib.MrcError) as e:
+        lib.mrc_sign(ctx, gm, long_o, long_t)
+    assert "2^22" in str(e.value)
+    with pytest.raises(lib.MrcError):
+        lib.mrc_build_and_sign(ctx, long_o, long_t, c.vocab, gspec)
     # the context stays usable after input errors
     sig = lib.mrc_sign(ctx, gm, o, t)
     assert torch.isfinite(sig).all()
