@@ -56,7 +56,23 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy MIB MiB device-to-device 5 times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
+
+
+def copy_probe(mib):
+    import torch
+    x = torch.ones(mib * 1024 * 1024 // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / 5
+    print(json.dumps({"copy_probe_bytes_each_way": x.numel() * 4, "copies": 5, "ms_each": dt * 1e3,
+                      "GBps_read_plus_write": 2 * x.numel() * 4 / dt / 1e9}))
 
 
 def source_digest(rel):
@@ -113,6 +129,9 @@ def cpu_baseline(c, k, tau):
 
 def main():
     a = parse()
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but not launched",
                           "n_gpus": a.gpus}))

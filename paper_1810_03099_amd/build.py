@@ -34,9 +34,14 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
+# Per-source extra flags: the all-pairs kernels keep their matrix-core
+# accumulators in VGPRs (their epilogues read every accumulator).
+EXTRA = {"compare.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, *EXTRA.get(os.path.basename(src), []), "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     err = "\n".join(l for l in r.stderr.splitlines() if "packed-fp32-ops" not in l)
     if r.returncode != 0:

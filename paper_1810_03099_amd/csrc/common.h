@@ -210,6 +210,13 @@ mrc_status launch_rescore2(mrc_ctx* ctx, int precision, const mrc_pair* cand, co
                            int64_t cand_cap, const float* unit, int32_t k, const float* err, float tau, float nominal,
                            PairSink out, unsigned long long* stats, hipStream_t s);
 // Normalise with explicit layouts (see compare.hip).
+// Outputs of the normalisation kernel. umfma holds the unit signatures for the
+// FP32 matrix cores: with frag == 0 row-major (ld_mfma floats per row, 4x4
+// sub-blocks of each 16-column block transposed, see mfma_col); with
+// frag != 0 fragment-major: fragment (16-row block rb, 16-column chunk c) is
+// 64 lanes x 4 floats at ((rb * ld_mfma / 16 + c) * 64 + lane) * 4, lane
+// l = li + 16 g holding components 16c + 4m + g (m = 0..3) of row 16rb + li,
+// so each operand load of the all-pairs kernel reads 1 KB contiguously.
 struct NormLayout {
     float* unit;      int ld_unit;
     uint16_t* bf16;   int ld_bf16;
@@ -218,7 +225,14 @@ struct NormLayout {
     float* err;       int64_t ld_err;
     float* umfma;     int ld_mfma;
     int64_t n_pad;
+    int frag = 0;
 };
+
+// Offset of component c of row r in the fragment-major FP32 layout with nc
+// 16-column chunks.
+__host__ __device__ __forceinline__ int64_t frag_offset(int64_t r, int c, int nc) {
+    return (((r >> 4) * nc + (c >> 4)) * 64 + (r & 15) + 16 * (c & 3)) * 4 + ((c >> 2) & 3);
+}
 mrc_status launch_normalise_rows(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const NormLayout& o,
                                  hipStream_t s);
 mrc_status launch_score_pairs(mrc_ctx* ctx, const float* unit, int32_t k, const int32_t* ii,
@@ -265,34 +279,41 @@ struct TileOrder {
     const int64_t* band_start;  // device [n_bands + 1]: first tile index of each band
     static constexpr int kBand = 8;
 
-    // Tile handled by (workgroup p, slot w); false when there is none.
-    __device__ __forceinline__ bool tile_of(int64_t p, int w, int* bi, int* bj) const {
-        const int64_t xcd = p % 8, j = p / 8;
-        const int64_t lb = xcd * per_xcd + j;          // logical workgroup
-        if (lb >= blocks) return false;
-        const int64_t t = lb * per_block + w;
-        if (t >= n_tiles) return false;
-        tile_at(t, bi, bj);
-        return true;
-    }
+    // Position of one wavefront in the band order: its current band and the
+    // band's first and one-past-last tile indices (all wavefront-uniform).
+    struct Cursor {
+        int band;
+        int64_t start, next;
+    };
 
-    // Coordinates of tile t of the band order. Call with a wavefront-uniform t:
-    // everything here is then scalar.
-    __device__ __forceinline__ void tile_at(int64_t t, int* bi, int* bj) const {
+    // Cursor at tile t (binary search over the band starts; once per wavefront).
+    __device__ __forceinline__ Cursor seek(int64_t t) const {
         int lo = 0, hi = n_bands - 1;                   // band: last start <= t
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
             if (band_start[mid] <= t) lo = mid; else hi = mid - 1;
         }
-        const int r0 = lo * kBand;
+        return Cursor{lo, band_start[lo], band_start[lo + 1]};
+    }
+
+    // Coordinates of tile t >= the cursor's tile (the cursor moves forward).
+    // Call with a wavefront-uniform t: everything here is then scalar, and
+    // memory is only read when t enters a later band.
+    __device__ __forceinline__ void tile(Cursor& c, int64_t t, int* bi, int* bj) const {
+        while (t >= c.next) {
+            ++c.band;
+            c.start = c.next;
+            c.next = band_start[c.band + 1];
+        }
+        const int r0 = c.band * kBand;
         const int h = min(kBand, nb - r0);
-        int q = (int)(t - band_start[lo]);              // < kBand * nb
+        int q = (int)(t - c.start);                     // < kBand * nb
         const int tri = h * (h + 1) / 2;
         if (q < tri) {                                  // columns r0 .. r0+h-1: J - r0 + 1 tiles each
-            int c = 0;
-            while ((c + 1) * (c + 2) / 2 <= q) ++c;
-            *bj = r0 + c;
-            *bi = r0 + (q - c * (c + 1) / 2);
+            int col = 0;
+            while ((col + 1) * (col + 2) / 2 <= q) ++col;
+            *bj = r0 + col;
+            *bi = r0 + (q - col * (col + 1) / 2);
         } else {
             q -= tri;
             const int col = q / h;
@@ -303,6 +324,10 @@ struct TileOrder {
 };
 
 mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s);
+// FP8 candidate kernels (fp8.hip), called by launch_compare_lowp.
+mrc_status launch_compare_fp8(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, const float* scale, int64_t n, int nk,
+                              const float* d_lo_thr, const TileOrder& ord, int64_t grid, PairSink cand,
+                              hipStream_t s);
 // Workgroups of a persistent launch: as many as are resident at once on the
 // device (occupancy x CUs), rounded down to a multiple of the 8 XCDs and at most
 // `cap`.

@@ -14,6 +14,7 @@
 //  * k_score_pairs / k_rescore: the same chain for listed pairs.
 #include <algorithm>
 
+#include "allpairs.h"
 #include "common.h"
 
 using namespace mrc;
@@ -72,7 +73,9 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
         if (o.unit) for (int c = lane; c < o.ld_unit; c += 64) o.unit[row * o.ld_unit + c] = 0.f;
         if (o.bf16) for (int c = lane; c < o.ld_bf16; c += 64) o.bf16[row * o.ld_bf16 + c] = 0;
         if (o.fp8) for (int c = lane; c < o.ld_fp8; c += 64) o.fp8[row * o.ld_fp8 + c] = 0;
-        if (o.umfma) for (int c = lane; c < o.ld_mfma; c += 64) o.umfma[row * o.ld_mfma + c] = 0.f;
+        if (o.umfma)
+            for (int c = lane; c < o.ld_mfma; c += 64)
+                o.umfma[o.frag ? frag_offset(row, c, o.ld_mfma / 16) : row * o.ld_mfma + c] = 0.f;
         if (lane == 0) {
             if (o.scale) o.scale[row] = 0.f;
             if (o.err) o.err[row] = o.err[o.ld_err + row] = 0.f;
@@ -82,7 +85,9 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
     if (o.unit) for (int c = k + lane; c < o.ld_unit; c += 64) o.unit[row * o.ld_unit + c] = 0.f;
     if (o.bf16) for (int c = k + lane; c < o.ld_bf16; c += 64) o.bf16[row * o.ld_bf16 + c] = 0;
     if (o.fp8) for (int c = k + lane; c < o.ld_fp8; c += 64) o.fp8[row * o.ld_fp8 + c] = 0;
-    if (o.umfma) for (int c = k + lane; c < o.ld_mfma; c += 64) o.umfma[row * o.ld_mfma + mfma_col(c)] = 0.f;
+    if (o.umfma)
+        for (int c = k + lane; c < o.ld_mfma; c += 64)
+            o.umfma[o.frag ? frag_offset(row, c, o.ld_mfma / 16) : row * o.ld_mfma + mfma_col(c)] = 0.f;
     const float* x = sig + row * k;
     float v[kMaxPerLane];
     float s2 = 0.f;
@@ -101,7 +106,8 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
         amax = fmaxf(amax, fabsf(v[r]));
         const int c = lane + 64 * r;
         if (c < k && o.unit) o.unit[row * o.ld_unit + c] = v[r];
-        if (c < k && o.umfma) o.umfma[row * o.ld_mfma + mfma_col(c)] = v[r];
+        if (c < k && o.umfma)
+            o.umfma[o.frag ? frag_offset(row, c, o.ld_mfma / 16) : row * o.ld_mfma + mfma_col(c)] = v[r];
     }
     amax = mrc_dev::wave_max(amax);
     const float sc = amax / 448.0f;
@@ -134,132 +140,69 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
 
 // ---------------------------------------------------------------- FP32 plain path
 
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void tile_coords(int64_t t, int nb, int* bi, int* bj) {
-    // Upper-triangle tiles (bi <= bj) in row-major order: row bi holds nb - bi tiles.
-    // Invert t = bi*nb - bi*(bi-1)/2 + (bj - bi) with a float64 estimate and a fix-up.
-    double a = 2.0 * nb + 1.0;
-    int r = (int)((a - sqrt(a * a - 8.0 * (double)t)) * 0.5);
-    if (r < 0) r = 0;
-    if (r > nb - 1) r = nb - 1;
-    auto start = [nb](int64_t row) { return row * nb - row * (row - 1) / 2; };
-    while (r > 0 && start(r) > t) --r;
-    while (r + 1 < nb && start(r + 1) <= t) ++r;
-    *bi = r;
-    *bj = r + (int)(t - start(r));
-}
-
-// One wavefront per 64x64 tile of the upper triangle. v_mfma_f32_16x16x4_f32
-// computes acc = fmaf(a3, b3, fmaf(a2, b2, fmaf(a1, b1, fmaf(a0, b0, acc))))
-// over its 4 k-values in lane-group order, so with the transposed 16-blocks of
-// `u` (kp columns, rows padded to 64) each output is exactly the plain chain
-// acc = fmaf(u_ic, u_jc, acc) over c = 0..k-1 ascending (zero columns past k
-// leave it unchanged).
-constexpr int kWT = 64;
-
-// Per-wavefront LDS staging of flagged pairs: a wavefront appends pairs to its
-// own buffer and reserves global output space with one atomic per flush.
-constexpr int kStage = 512;
-
-struct PairStage {
-    mrc_pair* buf;  // LDS, kStage entries of this wavefront
-    int n;          // staged entries (wavefront-uniform)
-
-    __device__ __forceinline__ void flush(const PairSink& sink) {
-        if (n == 0) return;
-        const int lane = __lane_id();
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(sink.counter, (unsigned long long)n);
-        base = __shfl(base, 0, 64);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        for (int e = lane; e < n; e += 64) {
-            const int64_t dst = (int64_t)base + e;
-            if (dst < sink.capacity) sink.pairs[dst] = buf[e];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        n = 0;
-    }
-
-    // Append the pairs of one output slot across the wavefront (flag per lane).
-    // The pair indices are only formed on this (rare) path.
-    template <class IJ>
-    __device__ __forceinline__ void add(const PairSink& sink, bool flag, IJ ij, float s, int flags) {
-        const unsigned long long m = __ballot(flag);
-        if (m == 0) return;
-        const int cnt = __popcll(m);
-        if (n + cnt > kStage) flush(sink);
-        if (flag) {
-            const int lane = __lane_id();
-            const int r = __popcll(m & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
-            int i, j;
-            ij(&i, &j);
-            buf[n + r] = mrc_pair{i, j, s, flags};
-        }
-        n += cnt;
-    }
-};
-
 // Persistent wavefronts: workgroup p runs on XCD p % 8 and its wavefronts walk
 // that XCD's contiguous share of the band-ordered tiles. Each tile is 64x64;
 // the 16-column chunks are fully unrolled (NC even) and the first chunk of
-// the next tile is loaded before the epilogue of the current one.
+// the next tile is loaded during the last chunk of the current one; the next
+// tile's coordinates are found before the current tile's products.
 template <int NC>
-__global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u, int n, int kp, float tau,
-                                                     TileOrder ord, PairSink sink) {
+__global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u, int n, float tau, TileOrder ord,
+                                                     PairSink sink) {
     static_assert(NC % 2 == 0, "even chunk count");
-    __shared__ mrc_pair stage_buf[4][kStage];
+    __shared__ TileLds lds;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
-    PairStage st{stage_buf[wave], 0};
+    PairStage st{lds.stage[wave], 0};
+    float* scr = lds.scr[wave];
     const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
     const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
     const int64_t stride = per_xcd_blocks * 4;
     int64_t t = t_lo + bx * 4 + wave;
     if (t >= t_hi) return;
+    TileOrder::Cursor cur = ord.seek(t);
     int bi, bj;
-    ord.tile_at(t, &bi, &bj);
-    const float* pa = u + (int64_t)(bi * kWT + li) * kp + 4 * lg;
-    const float* pb = u + (int64_t)(bj * kWT + li) * kp + 4 * lg;
+    ord.tile(cur, t, &bi, &bj);
+    // fragment (16-row block x of the tile, chunk c) of a 64-row panel p
+    auto frag = [&](const float* p, int x, int c) { return *(const f32x4*)(p + ((int64_t)x * NC + c) * 256); };
+    auto panel = [&](int blk) { return u + ((int64_t)blk * 4 * NC * 64 + lane) * 4; };
+    const float* pa = panel(bi);
+    const float* pb = panel(bj);
     f32x4 a[2][4], b[2][4];
 #pragma unroll
     for (int x = 0; x < 4; ++x) {
-        a[0][x] = *(const f32x4*)(pa + (int64_t)16 * x * kp);
-        b[0][x] = *(const f32x4*)(pb + (int64_t)16 * x * kp);
+        a[0][x] = frag(pa, x, 0);
+        b[0][x] = frag(pb, x, 0);
     }
     while (true) {
+        const int64_t tn = t + stride;
+        const bool more = tn < t_hi;
+        int ni = 0, nj = 0;
+        if (more) ord.tile(cur, tn, &ni, &nj);
         f32x4 acc[4][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
         const int row0 = bi * kWT, col0 = bj * kWT;
-        const int64_t tn = t + stride;
-        const bool more = tn < t_hi;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const int cur = c & 1, nxt = cur ^ 1;
+            const int cur_b = c & 1, nxt = cur_b ^ 1;
             if (c + 1 < NC) {
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
-                    a[nxt][x] = *(const f32x4*)(pa + (int64_t)16 * x * kp + 16 * (c + 1));
-                    b[nxt][x] = *(const f32x4*)(pb + (int64_t)16 * x * kp + 16 * (c + 1));
+                    a[nxt][x] = frag(pa, x, c + 1);
+                    b[nxt][x] = frag(pb, x, c + 1);
                 }
             } else if (more) {
                 // first chunk of the next tile (NC even: it goes to buffer 0)
-                int ni, nj;
-                ord.tile_at(tn, &ni, &nj);
-                pa = u + (int64_t)(ni * kWT + li) * kp + 4 * lg;
-                pb = u + (int64_t)(nj * kWT + li) * kp + 4 * lg;
+                pa = panel(ni);
+                pb = panel(nj);
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
-                    a[nxt][x] = *(const f32x4*)(pa + (int64_t)16 * x * kp);
-                    b[nxt][x] = *(const f32x4*)(pb + (int64_t)16 * x * kp);
+                    a[nxt][x] = frag(pa, x, 0);
+                    b[nxt][x] = frag(pb, x, 0);
                 }
-                bi = ni;
-                bj = nj;
             }
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -268,174 +211,20 @@ __global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u
                 for (int x = 0; x < 4; ++x)
 #pragma unroll
                     for (int y = 0; y < 4; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur][x][m], b[cur][y][m], acc[x][y], 0, 0, 0);
+                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur_b][x][m], b[cur_b][y][m], acc[x][y], 0,
+                                                                         0, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
-        // epilogue: lane holds rows row0 + 16x + 4lg + r, column col0 + 16y + li
         const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
         const int ib = row0 + 4 * lg, jb = col0 + li;
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float v = acc[x][y][r];
-                    bool f = v >= tau;
-                    if (!interior) {
-                        const int i = ib + 16 * x + r, j = jb + 16 * y;
-                        f = f && i < j && j < n;
-                    }
-                    st.add(sink, f, [&](int* i, int* j) { *i = ib + 16 * x + r; *j = jb + 16 * y; }, v, 0);
-                }
+        tile_half<0>(acc, tau, interior, ib, jb, n, scr, st, sink);
+        tile_half<1>(acc, tau, interior, ib, jb, n, scr, st, sink);
         if (!more) break;
         t = tn;
+        bi = ni;
+        bj = nj;
     }
     st.flush(sink);
-}
-
-// ---------------------------------------------------------------- BF16 / FP8 forms
-
-typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
-typedef int i32x8 __attribute__((ext_vector_type(8)));
-typedef int i32x4 __attribute__((ext_vector_type(4)));
-
-// Element width (bytes) and k per MFMA step of each low-precision form.
-template <int PREC> struct LowpTraits;
-template <> struct LowpTraits<MRC_PREC_BF16> { static constexpr int kStep = 32, kBytes = 2, kLaneBytes = 16; };
-template <> struct LowpTraits<MRC_PREC_FP8> { static constexpr int kStep = 128, kBytes = 1, kLaneBytes = 32; };
-
-// Operand fragment of one 16-row block for one MFMA step: lane (row li, group
-// lg) holds kLaneBytes consecutive bytes of its row at k = c0 + lg * (kStep/4).
-template <int PREC> struct Frag;
-template <> struct Frag<MRC_PREC_BF16> {
-    i32x4 v;
-    __device__ __forceinline__ void load(const uint8_t* p) { v = *(const i32x4*)p; }
-};
-template <> struct Frag<MRC_PREC_FP8> {
-    i32x4 lo, hi;
-    __device__ __forceinline__ void load(const uint8_t* p) {
-        lo = *(const i32x4*)p;
-        hi = *(const i32x4*)(p + 16);
-    }
-};
-
-__device__ __forceinline__ f32x4 mma(const Frag<MRC_PREC_BF16>& a, const Frag<MRC_PREC_BF16>& b, f32x4 c) {
-    bf16x8 av, bv;
-    __builtin_memcpy(&av, &a.v, 16);
-    __builtin_memcpy(&bv, &b.v, 16);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ f32x4 mma(const Frag<MRC_PREC_FP8>& a, const Frag<MRC_PREC_FP8>& b, f32x4 c) {
-    const i32x8 av = {a.lo[0], a.lo[1], a.lo[2], a.lo[3], a.hi[0], a.hi[1], a.hi[2], a.hi[3]};
-    const i32x8 bv = {b.lo[0], b.lo[1], b.lo[2], b.lo[3], b.hi[0], b.hi[1], b.hi[2], b.hi[3]};
-    // formats 0/0: both operands float8 e4m3; E8M0 block scales 127 = 2^0
-    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
-}
-
-// Candidate search of the low-precision forms: same persistent band-ordered
-// 64x64 wavefront tiles as the FP32 path. A pair becomes a candidate when its
-// low-precision score is >= lo_thr = tau - (the largest rescoring band over all
-// rows); the rescoring kernel then decides each candidate exactly.
-// q: [n_pad][ldq] bytes of codes (zero padded), scale: [n_pad] (FP8 only).
-template <int PREC, int NK>
-__global__ __launch_bounds__(256) void k_compare_lowp(const uint8_t* __restrict__ q, int ldq_bytes,
-                                                      const float* __restrict__ scale, int n,
-                                                      const float* __restrict__ lo_thr_ptr, TileOrder ord,
-                                                      PairSink cand) {
-    using T = LowpTraits<PREC>;
-    static_assert(NK % 2 == 0, "even step count");
-    __shared__ mrc_pair stage_buf[4][kStage];
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int li = lane & 15, lg = lane >> 4;
-    PairStage st{stage_buf[wave], 0};
-    const float lo_thr = *lo_thr_ptr;
-    const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
-    const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
-    const int64_t stride = per_xcd_blocks * 4;
-    int64_t t = t_lo + bx * 4 + wave;
-    if (t >= t_hi) return;
-    int bi, bj;
-    ord.tile_at(t, &bi, &bj);
-    constexpr int kStepBytes = T::kStep * T::kBytes;
-    const uint8_t* pa = q + (int64_t)(bi * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-    const uint8_t* pb = q + (int64_t)(bj * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-    Frag<PREC> a[2][4], b[2][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        a[0][x].load(pa + (int64_t)16 * x * ldq_bytes);
-        b[0][x].load(pb + (int64_t)16 * x * ldq_bytes);
-    }
-    while (true) {
-        f32x4 acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const int row0 = bi * kWT, col0 = bj * kWT;
-        const int64_t tn = t + stride;
-        const bool more = tn < t_hi;
-#pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            const int cur = c & 1, nxt = cur ^ 1;
-            if (c + 1 < NK) {
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[nxt][x].load(pa + (int64_t)16 * x * ldq_bytes + kStepBytes * (c + 1));
-                    b[nxt][x].load(pb + (int64_t)16 * x * ldq_bytes + kStepBytes * (c + 1));
-                }
-            } else if (more) {
-                int ni, nj;
-                ord.tile_at(tn, &ni, &nj);
-                pa = q + (int64_t)(ni * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-                pb = q + (int64_t)(nj * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[nxt][x].load(pa + (int64_t)16 * x * ldq_bytes);
-                    b[nxt][x].load(pb + (int64_t)16 * x * ldq_bytes);
-                }
-                bi = ni;
-                bj = nj;
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = mma(a[cur][x], b[cur][y], acc[x][y]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
-        const int ib = row0 + 4 * lg, jb = col0 + li;
-        float rs[4][4], cs[4];
-        if constexpr (PREC == MRC_PREC_FP8) {
-#pragma unroll
-            for (int y = 0; y < 4; ++y) cs[y] = scale[jb + 16 * y];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) rs[x][r] = scale[ib + 16 * x + r];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    float v = acc[x][y][r];
-                    if constexpr (PREC == MRC_PREC_FP8) v = v * rs[x][r] * cs[y];
-                    bool f = v >= lo_thr;
-                    if (!interior) {
-                        const int i = ib + 16 * x + r, j = jb + 16 * y;
-                        f = f && i < j && j < n;
-                    }
-                    st.add(cand, f, [&](int* i, int* j) { *i = ib + 16 * x + r; *j = jb + 16 * y; }, v, 0);
-                }
-        if (!more) break;
-        t = tn;
-    }
-    st.flush(cand);
 }
 
 // lo_thr = tau - max(nominal, band(e_max, e_max)) with e_max the largest row error.
@@ -557,7 +346,7 @@ mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k
                             uint16_t* bf16, uint8_t* fp8, float* scale, float* err, hipStream_t s,
                             float* umfma) {
     if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
-    NormOut o{unit, k, bf16, k, fp8, k, scale, err, n, umfma, 16 * mfma_chunks(k), n};
+    NormOut o{unit, k, bf16, k, fp8, k, scale, err, n, umfma, 16 * mfma_chunks(k), n, 1};
     if (umfma) o.n_pad = ceil_div(n, 64) * 64;
     return launch_normalise_rows(ctx, sig, n, k, o, s);
 }
@@ -586,14 +375,13 @@ mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32
     int64_t grid = 0;
     MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
     const int nc = mfma_chunks(k);
-    const int kp = 16 * nc;
     ScopedTimer tm(ctx, "compare_f32", s);
     switch (nc) {
 #define MRC_NC(c)                                                                                        \
     case c: {                                                                                            \
         const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_f32<c>, 256, grid);            \
-        hipLaunchKernelGGL(k_compare_f32<c>, dim3((unsigned)pgrid), dim3(256), 0, s, umfma, (int)n, kp, tau, \
-                           ord, sink);                                                                   \
+        hipLaunchKernelGGL(k_compare_f32<c>, dim3((unsigned)pgrid), dim3(256), 0, s, umfma, (int)n, tau, ord,   \
+                           sink);                                                                        \
     } break;
         MRC_NC(2) MRC_NC(4) MRC_NC(6) MRC_NC(8) MRC_NC(12) MRC_NC(16) MRC_NC(24) MRC_NC(32)
         MRC_NC(48) MRC_NC(64)
@@ -620,28 +408,9 @@ mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q
     MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
     const int nk = lowp_steps(precision, k);
     ScopedTimer tm(ctx, "compare_lowp", s);
-#define MRC_LP(P, c)                                                                                    \
-    case c: {                                                                                           \
-        const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_lowp<P, c>, 256, grid);       \
-        hipLaunchKernelGGL((k_compare_lowp<P, c>), dim3((unsigned)pgrid), dim3(256), 0, s, q, ldq_bytes, scale, \
-                           (int)n, d_lo_thr, ord, cand);                                                \
-    } break;
-    if (precision == MRC_PREC_BF16) {
-        switch (nk) {
-            MRC_LP(MRC_PREC_BF16, 2) MRC_LP(MRC_PREC_BF16, 4) MRC_LP(MRC_PREC_BF16, 6) MRC_LP(MRC_PREC_BF16, 8)
-            MRC_LP(MRC_PREC_BF16, 10) MRC_LP(MRC_PREC_BF16, 12) MRC_LP(MRC_PREC_BF16, 16)
-            MRC_LP(MRC_PREC_BF16, 20) MRC_LP(MRC_PREC_BF16, 24) MRC_LP(MRC_PREC_BF16, 32)
-            default: return fail(MRC_E_INVAL, "unsupported k for the BF16 form");
-        }
-    } else {
-        switch (nk) {
-            MRC_LP(MRC_PREC_FP8, 2) MRC_LP(MRC_PREC_FP8, 4) MRC_LP(MRC_PREC_FP8, 6) MRC_LP(MRC_PREC_FP8, 8)
-            default: return fail(MRC_E_INVAL, "unsupported k for the FP8 form");
-        }
-    }
-#undef MRC_LP
-    MRC_HIP_TRY(ctx, hipGetLastError());
-    return MRC_OK;
+    if (precision == MRC_PREC_BF16)
+        return launch_lowp_kernel<MRC_PREC_BF16>(ctx, q, ldq_bytes, scale, n, nk, d_lo_thr, ord, grid, cand, s);
+    return launch_compare_fp8(ctx, q, ldq_bytes, scale, n, nk, d_lo_thr, ord, grid, cand, s);
 }
 
 // Accumulation slack of a low-precision score relative to |a_i||a_j|. BF16
