@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
+    ap.add_argument("--workload", default="plain_full", choices=["plain_full", "precision"],
+                    help="plain_full: 20k docs, k=64 (default); precision: 200k docs, k=256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -106,7 +108,7 @@ def timed(mrc, ctx, kernel, fn, reps):
     return (ms / n if n else None), wall * 1e3, out
 
 
-def cpu_baseline(c, k, tau):
+def cpu_baseline(c, k, tau, sample_note="full workload"):
     """The FP64 oracle on the same workload (one whole step: build, sign, compare)."""
     from oracle import mrc as om
     try:
@@ -123,7 +125,7 @@ def cpu_baseline(c, k, tau):
     n = c.n_docs
     pairs = n * (n - 1) / 2
     return {"value": pairs / dt, "unit": "pairs/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"full workload: {n} docs, one step (build + sign + all-pairs compare), float64 NumPy, "
+            "sample": f"{sample_note}: {n} docs, one step (build + sign + all-pairs compare), float64 NumPy, "
                       f"{dt:.2f} s", "seconds": dt, "host_cpus": os.cpu_count()}, shat, (i, j)
 
 
@@ -141,7 +143,7 @@ def main():
     from synth import corpus as synth
 
     prec = {"fp32": mrc.PREC_FP32, "bf16": mrc.PREC_BF16, "fp8": mrc.PREC_FP8}[a.precision]
-    spec_idx = 1
+    spec_idx = 1 if a.workload == "plain_full" else 2
     cs = synth.CONFIGS[spec_idx]
     k, tau = cs.k, cs.tau
     c = synth.generate(spec_idx)
@@ -152,7 +154,7 @@ def main():
     tok = torch.from_numpy(c.tokens).cuda()
     ctx = mrc.mrc_ctx_create(0)
     sig = torch.empty((n, k), dtype=torch.float32, device="cuda")
-    cap = 8 * 1024 * 1024
+    cap = 8 * 1024 * 1024 if a.workload == "plain_full" else 16 * 1024 * 1024
     state = {}
 
     def step():
@@ -230,6 +232,16 @@ def main():
         "roofline": roof,
     }
     shat = None
+    if a.workload == "precision":
+        if not a.no_cpu_baseline:
+            # bounded sample: the oracle's whole step on 5,000 documents, scaled by pairs
+            log("cpu baseline (oracle, 5,000-document subsample)")
+            cb, _, _ = cpu_baseline(c.subset(np.arange(5000)), k, tau, "5,000-document subsample of the workload")
+            out["cpu_baseline"] = cb
+        if not a.no_extras:
+            out["extras"] = precision_extras(mrc, ctx, c, sig, k, tau, cap)
+        print(json.dumps(out))
+        return
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle)")
         cb, shat, (oi, oj) = cpu_baseline(c, k, tau)
@@ -242,6 +254,55 @@ def main():
         out["extras"] = extras(mrc, ctx, c, off, tok, sig, state["model"], k, tau, cap, shat, sign_ms,
                                ktimes.get("sign_counts", {}).get("avg_ms"))
     print(json.dumps(out))
+
+
+def precision_extras(mrc, ctx, c, sig, k, tau, cap):
+    """All three forms on the whole corpus (times, decisions), and their scores
+    against the float64 oracle on a 5,000-document subsample."""
+    import torch
+    from oracle import mrc as om
+    n = c.n_docs
+    pairs_total = n * (n - 1) / 2
+    forms, sets = {}, {}
+    for name, p, kn in [("fp32", mrc.PREC_FP32, "compare_f32"), ("bf16", mrc.PREC_BF16, "compare_lowp"),
+                        ("fp8", mrc.PREC_FP8, "compare_lowp")]:
+        mrc.mrc_compare(ctx, sig, tau, p, 0.02, capacity=cap)
+        kms, wall, (pairs, st) = timed(mrc, ctx, kn, lambda: mrc.mrc_compare(ctx, sig, tau, p, 0.02, capacity=cap), 3)
+        rms = None
+        if p != mrc.PREC_FP32:
+            rms, _, _ = timed(mrc, ctx, "rescore", lambda: mrc.mrc_compare(ctx, sig, tau, p, 0.02, capacity=cap), 2)
+        gi, gj, _, _ = mrc.pairs_to_numpy(pairs)
+        sets[name] = set(zip(gi.tolist(), gj.tolist()))
+        pk = {"fp32": 157.3, "bf16": 2500.0, "fp8": 5000.0}[name]
+        forms[name] = {"kernel_ms": kms, "rescore_ms": rms, "call_ms": wall,
+                       "pairs_per_s_call": pairs_total / (wall / 1e3), "pairs_per_s_kernel": pairs_total / (kms / 1e3),
+                       "mfma_frac": pairs_total * 2 * k / (kms / 1e3) / 1e12 / pk, "flagged": int(gi.size),
+                       "rescored": st["n_band"], "rescored_in_nominal_band": st["n_band_nominal"],
+                       "flips_a_fixed_0.02_band_would_make": st["n_flip_outside_nominal"]}
+        log(f"precision form {name}: kernel {kms:.3f} ms, call {wall:.3f} ms")
+    forms["decisions_identical_to_fp32"] = all(sets[x] == sets["fp32"] for x in ("bf16", "fp8"))
+    # error vs float64 on a 5,000-document subsample: the oracle's model of the
+    # whole corpus, its signatures of the subsample, all subsample pairs
+    log("oracle model of the whole corpus (float64)")
+    m = om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=k))
+    sub = c.subset(np.arange(5000))
+    osig, _ = om.sign(sub.offsets, sub.tokens, m)
+    shat = om.normalise(osig)
+    ref = shat @ shat.T
+    iu = np.triu_indices(5000, 1)
+    ref = ref[iu]
+    ssub = sig[:5000].contiguous()
+    err = {}
+    for name, p in [("fp32", mrc.PREC_FP32), ("bf16", mrc.PREC_BF16), ("fp8", mrc.PREC_FP8)]:
+        pairs, _ = mrc.mrc_compare(ctx, ssub, -2.0, p, 0.02, capacity=5000 * 4999 // 2 + 16)
+        gi, gj, gs, _ = mrc.pairs_to_numpy(pairs)
+        got = np.zeros((5000, 5000))
+        got[gi, gj] = gs
+        e = np.abs(got[iu] - ref)
+        err[name] = {"max": float(e.max()), "mean": float(e.mean()), "pairs": int(e.size)}
+    torch.cuda.synchronize()
+    return {"forms": forms, "err_vs_fp64_5000_subsample": err,
+            "note": "subsample scores are the form's own scores (no rescoring applies at tau = -2)"}
 
 
 def extras(mrc, ctx, c, off, tok, sig, model, k, tau, cap, shat, sign_ms, counts_ms):

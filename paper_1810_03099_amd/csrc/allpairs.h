@@ -120,6 +120,26 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
     __builtin_amdgcn_wave_barrier();
 }
 
+// Whole epilogue of one 64x64 wavefront tile (lane layout as in tile_half). A
+// tile whose largest score is below thr in every lane (the common case away
+// from duplicates) ends after a max tree.
+__device__ __forceinline__ void tile_epilogue(const f32x4 (&acc)[4][4], float thr, bool interior, int ib, int jb,
+                                              int n, float* __restrict__ scr, PairStage& st, const PairSink& sink) {
+    float mx[16];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            mx[x * 4 + y] = fmaxf(fmaxf(acc[x][y][0], acc[x][y][1]), fmaxf(acc[x][y][2], acc[x][y][3]));
+#pragma unroll
+    for (int w = 8; w >= 1; w >>= 1)
+#pragma unroll
+        for (int i = 0; i < w; ++i) mx[i] = fmaxf(mx[i], mx[i + w]);
+    if (__ballot(mx[0] >= thr) == 0) return;
+    tile_half<0>(acc, thr, interior, ib, jb, n, scr, st, sink);
+    tile_half<1>(acc, thr, interior, ib, jb, n, scr, st, sink);
+}
+
 // LDS of the all-pairs kernels (4 wavefronts): pair stages and score parking.
 struct TileLds {
     mrc_pair stage[4][kStage];
@@ -253,8 +273,7 @@ __global__ __launch_bounds__(256) void k_compare_lowp(const uint8_t* __restrict_
                     for (int y = 0; y < 4; ++y) acc[x][y][r] = acc[x][y][r] * rs * cs[y];
                 }
         }
-        tile_half<0>(acc, lo_thr, interior, ib, jb, n, scr, st, cand);
-        tile_half<1>(acc, lo_thr, interior, ib, jb, n, scr, st, cand);
+        tile_epilogue(acc, lo_thr, interior, ib, jb, n, scr, st, cand);
         if (!more) break;
         t = tn;
         bi = ni;

@@ -217,8 +217,7 @@ __global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u
         }
         const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
         const int ib = row0 + 4 * lg, jb = col0 + li;
-        tile_half<0>(acc, tau, interior, ib, jb, n, scr, st, sink);
-        tile_half<1>(acc, tau, interior, ib, jb, n, scr, st, sink);
+        tile_epilogue(acc, tau, interior, ib, jb, n, scr, st, sink);
         if (!more) break;
         t = tn;
         bi = ni;
