@@ -387,7 +387,8 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
     const int prec = opts->precision;
     const int step = prec == MRC_PREC_BF16 ? 32 : 128, ebytes = prec == MRC_PREC_BF16 ? 2 : 1;
     const int ldq = lowp_steps(prec, k) * step;
-    const int64_t n_pad = ceil_div(n > 0 ? n : 1, 64) * 64;
+    // BF16 blocks are 256 rows, FP8 blocks 64
+    const int64_t n_pad = ceil_div(n > 0 ? n : 1, prec == MRC_PREC_BF16 ? 256 : 64) * (prec == MRC_PREC_BF16 ? 256 : 64);
     void *unit = nullptr, *q = nullptr, *scale = nullptr, *err = nullptr;
     MRC_TRY(scratch(ctx, "lp_unit", (size_t)(n > 0 ? n : 1) * k * sizeof(float), &unit));
     MRC_TRY(scratch(ctx, "lp_codes", (size_t)n_pad * ldq * ebytes, &q));

@@ -324,6 +324,10 @@ struct TileOrder {
 };
 
 mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s);
+// BF16 candidate kernels (bf16.hip, LDS-tiled 256x256 blocks), called by
+// launch_compare_lowp; the codes need ceil(n / 256) * 256 rows.
+mrc_status launch_compare_bf16(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, int64_t n, int nk,
+                               const float* d_lo_thr, PairSink cand, hipStream_t s);
 // FP8 candidate kernels (fp8.hip), called by launch_compare_lowp.
 mrc_status launch_compare_fp8(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, const float* scale, int64_t n, int nk,
                               const float* d_lo_thr, const TileOrder& ord, int64_t grid, PairSink cand,

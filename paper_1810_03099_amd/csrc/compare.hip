@@ -407,8 +407,7 @@ mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q
     MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
     const int nk = lowp_steps(precision, k);
     ScopedTimer tm(ctx, "compare_lowp", s);
-    if (precision == MRC_PREC_BF16)
-        return launch_lowp_kernel<MRC_PREC_BF16>(ctx, q, ldq_bytes, scale, n, nk, d_lo_thr, ord, grid, cand, s);
+    if (precision == MRC_PREC_BF16) return launch_compare_bf16(ctx, q, ldq_bytes, n, nk, d_lo_thr, cand, s);
     return launch_compare_fp8(ctx, q, ldq_bytes, scale, n, nk, d_lo_thr, ord, grid, cand, s);
 }
 
