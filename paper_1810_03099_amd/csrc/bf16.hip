@@ -5,12 +5,11 @@
 // upper triangle of Q Q^T (Q: bfloat16 codes of the unit signatures, rows
 // padded to a multiple of 256 with zeros); wavefront (wr, wc) owns the 128x128
 // quarter at rows 128wr, columns 128wc, as 4x4 blocks of 32x32x16 matrix-core
-// products accumulating in FP32. Operands pass through LDS in chunks of 32
-// components (64-byte rows whose four 16-byte parts are XOR-swizzled by
-// (row / 4) % 4, so that both the coalesced chunk stores and the 16-byte
-// fragment reads of 16 consecutive rows hit distinct banks), double-buffered,
-// with the next chunk loaded into registers while the current one is
-// multiplied. Every score is
+// products accumulating in FP32. Operands pass through LDS in chunks of 64
+// components, loaded straight from global memory into LDS (no register
+// staging) one chunk ahead into the other of two buffers; each 128-byte row
+// holds its eight 16-byte parts XOR-swizzled by (row / 2) % 8, so the 16-byte
+// fragment reads of 16 consecutive rows hit distinct banks. Every score is
 // compared with the candidate threshold; blocks without any score at or above
 // it end after a max tree.
 //
@@ -27,53 +26,27 @@ namespace {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) void lds_void;
 
 constexpr int kBM = 256;          // workgroup tile (rows = columns)
-constexpr int kKC = 32;           // components per LDS chunk
-constexpr int kLdsRow = 32;       // LDS row stride in bfloat16 (64 bytes, parts swizzled)
-constexpr int kBufElems = kBM * kLdsRow;
+constexpr int kKC = 64;           // components per LDS chunk
+constexpr int kRowB = kKC * 2;    // LDS bytes per row of a chunk (8 parts of 16 bytes, swizzled)
+constexpr int kBufB = kBM * kRowB;
+
+constexpr int kStageB = 256;      // staged pairs per wavefront
 
 struct Bf16Lds {
-    uint16_t a[2][kBufElems];
-    uint16_t b[2][kBufElems];
-    mrc_pair stage[4][kStage];
-    float scr[4][16 * 64];
+    uint8_t buf[2][2][kBufB];     // [buffer][A, B][256 rows x 128 bytes]
+    mrc_pair stage[4][kStageB];
+    float scr[4][16 * 64];        // parked scores of one 32x32 block per wavefront
 };
-
-// Chunk kc (32 components) of the 256-row panels at rows ra / rb: this
-// thread's 4 + 4 segments of 16 bytes (segment s = t + 256 e: row s / 4,
-// part s % 4).
-struct ChunkRegs {
-    u32x4 a[4], b[4];
-};
-
-__device__ __forceinline__ void load_chunk(ChunkRegs& g, const uint8_t* __restrict__ q, int ldq_bytes, int64_t ra,
-                                           int64_t rb, int kc) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int s = threadIdx.x + 256 * e, row = s >> 2, part = s & 3;
-        const int64_t off = (int64_t)kc * kKC * 2 + part * 16;
-        g.a[e] = *(const u32x4*)(q + (ra + row) * ldq_bytes + off);
-        g.b[e] = *(const u32x4*)(q + (rb + row) * ldq_bytes + off);
-    }
-}
-
-__device__ __forceinline__ void store_chunk(const ChunkRegs& g, uint16_t* __restrict__ la, uint16_t* __restrict__ lb) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int s = threadIdx.x + 256 * e, row = s >> 2, part = s & 3;
-        const int pos = row * kLdsRow + ((part ^ ((row >> 2) & 3)) * 8);
-        *(u32x4*)(la + pos) = g.a[e];
-        *(u32x4*)(lb + pos) = g.b[e];
-    }
-}
 
 // Stage the flagged entries of one result slot across the wavefront.
 __device__ __forceinline__ void stage_add(PairStage& st, const PairSink& sink, bool flag, int i, int j, float s) {
     const unsigned long long m = __ballot(flag);
     if (m == 0) return;
     const int cnt = __popcll(m);
-    if (st.n + cnt > kStage) st.flush(sink);
+    if (st.n + cnt > kStageB) st.flush(sink);
     if (flag) {
         const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         st.buf[st.n + r] = mrc_pair{i, j, s, 0};
@@ -81,17 +54,35 @@ __device__ __forceinline__ void stage_add(PairStage& st, const PairSink& sink, b
     st.n += cnt;
 }
 
-template <int NKC>
+// Chunk kc of the 256-row panels at rows ra (A) and rb (B) straight into LDS
+// (each load instruction fills 1 KB: 8 rows; lane l writes stored part l % 8
+// of row l / 8, which holds part (l % 8) ^ ((row / 2) % 8) of the chunk).
+// Wavefront w fills rows 64w .. 64w + 63 of both panels.
+__device__ __forceinline__ void load_chunk_lds(uint8_t* __restrict__ la, uint8_t* __restrict__ lb,
+                                               const uint8_t* __restrict__ q, int ldq_bytes, int64_t ra, int64_t rb,
+                                               int kc, int wave, int lane) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int row = wave * 64 + i * 8 + (lane >> 3);
+        const int part = (lane & 7) ^ ((row >> 1) & 7);
+        const int64_t off = (int64_t)kc * kRowB + part * 16;
+        __builtin_amdgcn_global_load_lds((const void*)(q + (ra + row) * ldq_bytes + off),
+                                         (lds_void*)(la + (wave * 64 + i * 8) * kRowB), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const void*)(q + (rb + row) * ldq_bytes + off),
+                                         (lds_void*)(lb + (wave * 64 + i * 8) * kRowB), 16, 0, 0);
+    }
+}
+
+template <int NK>
 __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restrict__ q, int ldq_bytes, int n,
                                                          const float* __restrict__ lo_thr_ptr, TileOrder ord,
                                                          PairSink cand) {
-    static_assert(NKC % 2 == 0, "even chunk count");
+    constexpr int NKC = NK / 2;   // 64-component chunks (NK steps of 32)
     __shared__ Bf16Lds lds;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int wr = wave >> 1, wc = wave & 1;
     PairStage st{lds.stage[wave], 0};
-    float* scr = lds.scr[wave];
     const float thr = *lo_thr_ptr;
     const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
     const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
@@ -100,15 +91,14 @@ __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restri
     TileOrder::Cursor cur = ord.seek(t);
     int bi, bj;
     ord.tile(cur, t, &bi, &bj);
-    ChunkRegs g;
-    load_chunk(g, q, ldq_bytes, (int64_t)bi * kBM, (int64_t)bj * kBM, 0);
-    store_chunk(g, lds.a[0], lds.b[0]);
+    int cb = 0;  // LDS buffer of the current chunk
+    load_chunk_lds(lds.buf[0][0], lds.buf[0][1], q, ldq_bytes, (int64_t)bi * kBM, (int64_t)bj * kBM, 0, wave, lane);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     // fragment reads: row (l % 32) of each 32-row block, part 2s + l / 32 of
-    // step s, at its swizzled position (blocks start at multiples of 32 rows,
-    // so the swizzle depends on l % 32 only)
-    const int frow = lane & 31, swz = (frow >> 2) & 3;
-    const int fpart0 = ((0 + (lane >> 5)) ^ swz) * 8, fpart1 = ((2 + (lane >> 5)) ^ swz) * 8;
+    // step s at its stored position (blocks start at multiples of 32 rows, so
+    // the swizzle depends on l % 32 only)
+    const int frow = lane & 31, swz = (frow >> 1) & 7, fhi = lane >> 5;
     while (true) {
         const int64_t tn = t + per_xcd_blocks;
         const bool more = tn < t_hi;
@@ -120,31 +110,41 @@ __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restri
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[x][y] = f32x16{};
         for (int kc = 0; kc < NKC; ++kc) {
-            const int cb = kc & 1;
             // next chunk of this block pair, or the first chunk of the next one
-            if (kc + 1 < NKC) load_chunk(g, q, ldq_bytes, (int64_t)bi * kBM, (int64_t)bj * kBM, kc + 1);
-            else if (more) load_chunk(g, q, ldq_bytes, (int64_t)ni * kBM, (int64_t)nj * kBM, 0);
-            const uint16_t* la = lds.a[cb] + (wr * 128 + frow) * kLdsRow;
-            const uint16_t* lb = lds.b[cb] + (wc * 128 + frow) * kLdsRow;
-#pragma unroll
-            for (int s = 0; s < kKC / 16; ++s) {
-                const int fp = s == 0 ? fpart0 : fpart1;
-                bf16x8 fa[4], fb[4];
+            if (kc + 1 < NKC)
+                load_chunk_lds(lds.buf[cb ^ 1][0], lds.buf[cb ^ 1][1], q, ldq_bytes, (int64_t)bi * kBM,
+                               (int64_t)bj * kBM, kc + 1, wave, lane);
+            else if (more)
+                load_chunk_lds(lds.buf[cb ^ 1][0], lds.buf[cb ^ 1][1], q, ldq_bytes, (int64_t)ni * kBM,
+                               (int64_t)nj * kBM, 0, wave, lane);
+            const uint8_t* la = lds.buf[cb][0] + (wr * 128 + frow) * kRowB;
+            const uint8_t* lb = lds.buf[cb][1] + (wc * 128 + frow) * kRowB;
+            bf16x8 fa[2][4], fb[2][4];
+            auto read_step = [&](int s, bf16x8 (&ra)[4], bf16x8 (&rb)[4]) {
+                const int off = (((2 * s + fhi) ^ swz) * 16);
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
-                    const u32x4 va = *(const u32x4*)(la + x * 32 * kLdsRow + fp);
-                    const u32x4 vb = *(const u32x4*)(lb + x * 32 * kLdsRow + fp);
-                    __builtin_memcpy(&fa[x], &va, 16);
-                    __builtin_memcpy(&fb[x], &vb, 16);
+                    const u32x4 va = *(const u32x4*)(la + x * 32 * kRowB + off);
+                    const u32x4 vb = *(const u32x4*)(lb + x * 32 * kRowB + off);
+                    __builtin_memcpy(&ra[x], &va, 16);
+                    __builtin_memcpy(&rb[x], &vb, 16);
                 }
+            };
+            read_step(0, fa[0], fb[0]);
+#pragma unroll
+            for (int s = 0; s < kKC / 16; ++s) {
+                if (s + 1 < kKC / 16) read_step(s + 1, fa[(s + 1) & 1], fb[(s + 1) & 1]);
 #pragma unroll
                 for (int x = 0; x < 4; ++x)
 #pragma unroll
                     for (int y = 0; y < 4; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[x], fb[y], acc[x][y], 0, 0, 0);
+                        acc[x][y] =
+                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s & 1][x], fb[s & 1][y], acc[x][y], 0, 0, 0);
             }
-            if (kc + 1 < NKC || more) store_chunk(g, lds.a[cb ^ 1], lds.b[cb ^ 1]);
+            // the next chunk is in LDS for every wavefront
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
+            cb ^= 1;
         }
         // ---- candidates of this wavefront's 128x128 quarter
         const int row0 = bi * kBM + wr * 128, col0 = bj * kBM + wc * 128;
@@ -153,26 +153,27 @@ __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restri
         for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int y = 0; y < 4; ++y) {
-                float m[8];
-#pragma unroll
-                for (int i = 0; i < 8; ++i) m[i] = fmaxf(acc[x][y][i], acc[x][y][i + 8]);
-#pragma unroll
-                for (int w = 4; w >= 1; w >>= 1)
-#pragma unroll
-                    for (int i = 0; i < w; ++i) m[i] = fmaxf(m[i], m[i + w]);
-                mx[x * 4 + y] = m[0];
+                // three-input maxima: 16 values in 8 instructions
+                float m0 = fmaxf(fmaxf(acc[x][y][0], acc[x][y][1]), acc[x][y][2]);
+                float m1 = fmaxf(fmaxf(acc[x][y][3], acc[x][y][4]), acc[x][y][5]);
+                float m2 = fmaxf(fmaxf(acc[x][y][6], acc[x][y][7]), acc[x][y][8]);
+                float m3 = fmaxf(fmaxf(acc[x][y][9], acc[x][y][10]), acc[x][y][11]);
+                float m4 = fmaxf(fmaxf(acc[x][y][12], acc[x][y][13]), acc[x][y][14]);
+                m0 = fmaxf(fmaxf(m0, m1), acc[x][y][15]);
+                m2 = fmaxf(fmaxf(m2, m3), m4);
+                mx[x * 4 + y] = fmaxf(m0, m2);
                 __builtin_amdgcn_sched_barrier(0);
             }
         float mall = mx[0];
 #pragma unroll
         for (int i = 1; i < 16; ++i) mall = fmaxf(mall, mx[i]);
         if (__ballot(mall >= thr) != 0) {
+            float* scr = lds.scr[wave];
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
                 for (int y = 0; y < 4; ++y) {
                     if (__ballot(mx[x * 4 + y] >= thr) == 0) continue;
-                    // park the block's 16 scores, then walk them
 #pragma unroll
                     for (int i = 0; i < 16; ++i) scr[i * 64 + lane] = acc[x][y][i];
                     __builtin_amdgcn_sched_barrier(0);
