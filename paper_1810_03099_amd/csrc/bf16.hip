@@ -6,10 +6,13 @@
 // padded to a multiple of 256 with zeros); wavefront (wr, wc) owns the 128x128
 // quarter at rows 128wr, columns 128wc, as 4x4 blocks of 32x32x16 matrix-core
 // products accumulating in FP32. Operands pass through LDS in chunks of 64
-// components, loaded straight from global memory into LDS (no register
-// staging) one chunk ahead into the other of two buffers; each 128-byte row
-// holds its eight 16-byte parts XOR-swizzled by (row / 2) % 8, so the 16-byte
-// fragment reads of 16 consecutive rows hit distinct banks. Every score is
+// components, loaded by buffer loads straight into LDS (no register staging)
+// one chunk ahead into the other of two buffers, the loads interleaved with
+// the first step's products; each 128-byte row holds its eight 16-byte parts
+// XOR-swizzled by (row / 2) % 8, so the 16-byte fragment reads of 16
+// consecutive rows hit distinct banks. The fragment reads of step s + 1 are
+// issued before the products of step s (scheduling fences keep the compiler
+// from sinking them), so LDS latency hides behind 16 products. Every score is
 // compared with the candidate threshold; blocks without any score at or above
 // it end after a max tree.
 //
@@ -19,6 +22,8 @@
 // column l % 32.
 #include "allpairs.h"
 #include "common.h"
+
+#include <type_traits>
 
 using namespace mrc;
 
@@ -36,7 +41,8 @@ constexpr int kBufB = kBM * kRowB;
 constexpr int kStageB = 256;      // staged pairs per wavefront
 
 struct Bf16Lds {
-    uint8_t buf[2][2][kBufB];     // [buffer][A, B][256 rows x 128 bytes]
+    uint8_t a[2][kBufB];          // [buffer][256 rows x 128 bytes] of the row panel
+    uint8_t b[2][kBufB];          // the same for the column panel
     mrc_pair stage[4][kStageB];
     float scr[4][16 * 64];        // parked scores of one 32x32 block per wavefront
 };
@@ -54,24 +60,8 @@ __device__ __forceinline__ void stage_add(PairStage& st, const PairSink& sink, b
     st.n += cnt;
 }
 
-// Chunk kc of the 256-row panels at rows ra (A) and rb (B) straight into LDS
-// (each load instruction fills 1 KB: 8 rows; lane l writes stored part l % 8
-// of row l / 8, which holds part (l % 8) ^ ((row / 2) % 8) of the chunk).
-// Wavefront w fills rows 64w .. 64w + 63 of both panels.
-__device__ __forceinline__ void load_chunk_lds(uint8_t* __restrict__ la, uint8_t* __restrict__ lb,
-                                               const uint8_t* __restrict__ q, int ldq_bytes, int64_t ra, int64_t rb,
-                                               int kc, int wave, int lane) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int row = wave * 64 + i * 8 + (lane >> 3);
-        const int part = (lane & 7) ^ ((row >> 1) & 7);
-        const int64_t off = (int64_t)kc * kRowB + part * 16;
-        __builtin_amdgcn_global_load_lds((const void*)(q + (ra + row) * ldq_bytes + off),
-                                         (lds_void*)(la + (wave * 64 + i * 8) * kRowB), 16, 0, 0);
-        __builtin_amdgcn_global_load_lds((const void*)(q + (rb + row) * ldq_bytes + off),
-                                         (lds_void*)(lb + (wave * 64 + i * 8) * kRowB), 16, 0, 0);
-    }
-}
+template <int V>
+using ic = std::integral_constant<int, V>;
 
 template <int NK>
 __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restrict__ q, int ldq_bytes, int n,
@@ -91,61 +81,121 @@ __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restri
     TileOrder::Cursor cur = ord.seek(t);
     int bi, bj;
     ord.tile(cur, t, &bi, &bj);
-    int cb = 0;  // LDS buffer of the current chunk
-    load_chunk_lds(lds.buf[0][0], lds.buf[0][1], q, ldq_bytes, (int64_t)bi * kBM, (int64_t)bj * kBM, 0, wave, lane);
+
+    // Operand loads: load i (0..7) of a chunk fills rows 64 wave + 8 i .. +8 of
+    // both panels; lane l writes stored part l % 8 of row l / 8 there, i.e.
+    // chunk part (l % 8) ^ ((row / 2) % 8), where (row / 2) % 8 = l / 16 + 4 (i % 2).
+    // Per lane only two global byte offsets occur (even / odd i); the rest of the
+    // address is wavefront-uniform.
+    uint32_t voff[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+        voff[h] = (uint32_t)((wave * 64 + (lane >> 3)) * ldq_bytes + (((lane & 7) ^ ((lane >> 4) + 4 * h)) * 16));
+    const int panel_bytes = kBM * ldq_bytes;
+    auto rsrc = [&](int blk) {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(q + (int64_t)blk * panel_bytes), (short)0, panel_bytes,
+                                                 0x00020000);
+    };
+    auto issue_chunk = [&](auto bc, __amdgpu_buffer_rsrc_t ra, __amdgpu_buffer_rsrc_t rb, int kc) __attribute__((always_inline)) {
+        constexpr int b = decltype(bc)::value;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int so = kc * kRowB + i * 8 * ldq_bytes;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (lds_void*)(lds.a[b] + (wave * 64 + i * 8) * kRowB), 16,
+                                                     voff[i & 1], so, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, (lds_void*)(lds.b[b] + (wave * 64 + i * 8) * kRowB), 16,
+                                                     voff[i & 1], so, 0, 0);
+        }
+    };
+    // Fragment reads: row l % 32 of each 32-row block, part 2s + l / 32 of step
+    // s at its stored position (blocks start at multiples of 32 rows, so the
+    // swizzle depends on l % 32 only).
+    const int frow = lane & 31, swz = (frow >> 1) & 7, fhi = lane >> 5;
+    const uint8_t* pa[4];
+    const uint8_t* pb[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        const int po = ((2 * s) ^ fhi ^ swz) * 16;
+        pa[s] = &lds.a[0][0] + (wr * 128 + frow) * kRowB + po;
+        pb[s] = &lds.b[0][0] + (wc * 128 + frow) * kRowB + po;
+    }
+    bf16x8 fa[2][4], fb[2][4];
+    auto read_step = [&](auto bc, int s, bf16x8 (&ra)[4], bf16x8 (&rb)[4]) __attribute__((always_inline)) {
+        constexpr int b = decltype(bc)::value;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            const u32x4 va = *(const u32x4*)(pa[s] + b * kBufB + x * 32 * kRowB);
+            const u32x4 vb = *(const u32x4*)(pb[s] + b * kBufB + x * 32 * kRowB);
+            __builtin_memcpy(&ra[x], &va, 16);
+            __builtin_memcpy(&rb[x], &vb, 16);
+        }
+    };
+
+    __amdgpu_buffer_rsrc_t qa = rsrc(bi), qb = rsrc(bj);
+    issue_chunk(ic<0>{}, qa, qb, 0);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    // fragment reads: row (l % 32) of each 32-row block, part 2s + l / 32 of
-    // step s at its stored position (blocks start at multiples of 32 rows, so
-    // the swizzle depends on l % 32 only)
-    const int frow = lane & 31, swz = (frow >> 1) & 7, fhi = lane >> 5;
-    while (true) {
+    read_step(ic<0>{}, 0, fa[0], fb[0]);
+
+    f32x16 acc[4][4];
+    // One 64-component chunk in buffer b. The loads of the following chunk (of
+    // this block pair, or the first of the next pair) go to the other buffer,
+    // one after each product of the first step; the reads of step s + 1 are
+    // issued before the products of step s, and the reads of the following
+    // chunk's first step (of this block pair) before the last products, after
+    // the barrier that makes that chunk visible.
+    auto chunk = [&](auto bc, int kc, bool more, __amdgpu_buffer_rsrc_t nqa, __amdgpu_buffer_rsrc_t nqb) __attribute__((always_inline)) {
+        constexpr int b = decltype(bc)::value;
+        const bool next_here = kc + 1 < NKC;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if (s < 3) {
+                read_step(bc, s + 1, fa[(s + 1) & 1], fb[(s + 1) & 1]);
+            } else {
+                // the following chunk is in LDS for every wavefront, and no
+                // wavefront reads buffer b any more
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                if (next_here) read_step(ic<b ^ 1>{}, 0, fa[0], fb[0]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (s == 0) {
+                if (next_here) issue_chunk(ic<b ^ 1>{}, qa, qb, kc + 1);
+                else if (more) issue_chunk(ic<b ^ 1>{}, nqa, nqb, 0);
+            }
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int y = 0; y < 4; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s & 1][x], fb[s & 1][y], acc[x][y], 0, 0, 0);
+            if (s == 0) {  // product, load, product, load, ...
+#pragma unroll
+                for (int g = 0; g < 16; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    };
+    auto tile = [&](auto pc) __attribute__((always_inline)) -> bool {
+        constexpr int P = decltype(pc)::value;   // buffer of the first chunk
         const int64_t tn = t + per_xcd_blocks;
         const bool more = tn < t_hi;
         int ni = bi, nj = bj;
         if (more) ord.tile(cur, tn, &ni, &nj);
-        f32x16 acc[4][4];
+        const __amdgpu_buffer_rsrc_t nqa = rsrc(ni), nqb = rsrc(nj);
 #pragma unroll
         for (int x = 0; x < 4; ++x)
 #pragma unroll
             for (int y = 0; y < 4; ++y) acc[x][y] = f32x16{};
-        for (int kc = 0; kc < NKC; ++kc) {
-            // next chunk of this block pair, or the first chunk of the next one
-            if (kc + 1 < NKC)
-                load_chunk_lds(lds.buf[cb ^ 1][0], lds.buf[cb ^ 1][1], q, ldq_bytes, (int64_t)bi * kBM,
-                               (int64_t)bj * kBM, kc + 1, wave, lane);
-            else if (more)
-                load_chunk_lds(lds.buf[cb ^ 1][0], lds.buf[cb ^ 1][1], q, ldq_bytes, (int64_t)ni * kBM,
-                               (int64_t)nj * kBM, 0, wave, lane);
-            const uint8_t* la = lds.buf[cb][0] + (wr * 128 + frow) * kRowB;
-            const uint8_t* lb = lds.buf[cb][1] + (wc * 128 + frow) * kRowB;
-            bf16x8 fa[2][4], fb[2][4];
-            auto read_step = [&](int s, bf16x8 (&ra)[4], bf16x8 (&rb)[4]) {
-                const int off = (((2 * s + fhi) ^ swz) * 16);
+        int kc = 0;
 #pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    const u32x4 va = *(const u32x4*)(la + x * 32 * kRowB + off);
-                    const u32x4 vb = *(const u32x4*)(lb + x * 32 * kRowB + off);
-                    __builtin_memcpy(&ra[x], &va, 16);
-                    __builtin_memcpy(&rb[x], &vb, 16);
-                }
-            };
-            read_step(0, fa[0], fb[0]);
-#pragma unroll
-            for (int s = 0; s < kKC / 16; ++s) {
-                if (s + 1 < kKC / 16) read_step(s + 1, fa[(s + 1) & 1], fb[(s + 1) & 1]);
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y)
-                        acc[x][y] =
-                            __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[s & 1][x], fb[s & 1][y], acc[x][y], 0, 0, 0);
-            }
-            // the next chunk is in LDS for every wavefront
-            __builtin_amdgcn_s_waitcnt(0);
-            __syncthreads();
-            cb ^= 1;
+        for (; kc + 2 <= NKC; kc += 2) {
+            chunk(ic<P>{}, kc, more, nqa, nqb);
+            chunk(ic<P ^ 1>{}, kc + 1, more, nqa, nqb);
         }
+        if (NKC & 1) chunk(ic<P>{}, kc, more, nqa, nqb);
         // ---- candidates of this wavefront's 128x128 quarter
         const int row0 = bi * kBM + wr * 128, col0 = bj * kBM + wc * 128;
         float mx[16];
@@ -190,10 +240,20 @@ __global__ __launch_bounds__(256, 1) void k_compare_bf16(const uint8_t* __restri
                     __builtin_amdgcn_wave_barrier();
                 }
         }
-        if (!more) break;
+        if (!more) return false;
+        // first step of the next block pair (its first chunk is in LDS)
+        read_step(ic<(P + NKC) & 1>{}, 0, fa[0], fb[0]);
         t = tn;
         bi = ni;
         bj = nj;
+        qa = nqa;
+        qb = nqb;
+        return true;
+    };
+    while (true) {
+        if (!tile(ic<0>{})) break;
+        if constexpr ((NKC & 1) != 0)
+            if (!tile(ic<1>{})) break;
     }
     st.flush(cand);
 }
