@@ -318,12 +318,18 @@ def fp8_e4m3fn_codes(x32):
 
 
 def fp8_quantise_rows(shat32):
-    """Per-row FP8 form: scale_i = max_c |s_ic| / 448 (float32 division),
-    q_ic = RNE_e4m3fn(s_ic / scale_i) (float32 division), zero rows get scale 0
-    and zero codes. Returns (codes uint8 [N][k], scale float32 [N])."""
+    """Per-row FP8 form: scale_i = the smallest power of two >= max_c |s_ic| / 448
+    (the quotient taken in float32), q_ic = RNE_e4m3fn(s_ic / scale_i) (float32
+    division, exact for a power of two), zero rows get scale 0 and zero codes.
+    A power-of-two scale is what the matrix cores can apply as an E8M0 operand
+    scale; the paper defines no FP8 form (this is the candidate filter's code).
+    Returns (codes uint8 [N][k], scale float32 [N])."""
     x = np.asarray(shat32, dtype=np.float32)
     mx = np.abs(x).max(axis=1) if x.shape[1] else np.zeros(x.shape[0], np.float32)
-    scale = (mx / np.float32(448.0)).astype(np.float32)
+    q = (mx / np.float32(448.0)).astype(np.float32)
+    m, e = np.frexp(q.astype(np.float64))                 # q = m 2^e, m in [0.5, 1)
+    scale = np.where(m == 0.5, q.astype(np.float64), np.ldexp(1.0, e)).astype(np.float32)
+    scale = np.where(q > 0, scale, np.float32(0.0)).astype(np.float32)
     safe = np.where(scale > 0, scale, np.float32(1.0)).astype(np.float32)
     y = (x / safe[:, None]).astype(np.float32)
     codes = fp8_e4m3fn_codes(y)

@@ -1,8 +1,7 @@
 // Device code shared by the all-pairs kernels (FP32 plain path and the BF16 /
-// FP8 candidate search): the 64x64 wavefront tiles over the band order, the
-// compact flag epilogue with per-wavefront pair staging, and the
-// low-precision candidate kernel (instantiated per precision in the files
-// that launch it).
+// FP8 candidate search): the 64x64 wavefront tiles of the FP32 path over the
+// band order, its compact flag epilogue, the per-wavefront pair staging, and
+// the operand vector types of the low-precision matrix-core steps.
 #pragma once
 
 #include "common.h"
@@ -151,163 +150,5 @@ struct TileLds {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
-
-// Element width (bytes) and k per MFMA step of each low-precision form.
-template <int PREC> struct LowpTraits;
-template <> struct LowpTraits<MRC_PREC_BF16> { static constexpr int kStep = 32, kBytes = 2, kLaneBytes = 16; };
-template <> struct LowpTraits<MRC_PREC_FP8> { static constexpr int kStep = 128, kBytes = 1, kLaneBytes = 32; };
-
-// Operand fragment of one 16-row block for one MFMA step: lane (row li, group
-// lg) holds kLaneBytes consecutive bytes of its row at k = c0 + lg * (kStep/4).
-template <int PREC> struct Frag;
-template <> struct Frag<MRC_PREC_BF16> {
-    i32x4 v;
-    __device__ __forceinline__ void load(const uint8_t* p) { v = *(const i32x4*)p; }
-};
-template <> struct Frag<MRC_PREC_FP8> {
-    i32x4 lo, hi;
-    __device__ __forceinline__ void load(const uint8_t* p) {
-        lo = *(const i32x4*)p;
-        hi = *(const i32x4*)(p + 16);
-    }
-};
-
-__device__ __forceinline__ f32x4 mma(const Frag<MRC_PREC_BF16>& a, const Frag<MRC_PREC_BF16>& b, f32x4 c) {
-    bf16x8 av, bv;
-    __builtin_memcpy(&av, &a.v, 16);
-    __builtin_memcpy(&bv, &b.v, 16);
-    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
-}
-
-__device__ __forceinline__ f32x4 mma(const Frag<MRC_PREC_FP8>& a, const Frag<MRC_PREC_FP8>& b, f32x4 c) {
-    const i32x8 av = {a.lo[0], a.lo[1], a.lo[2], a.lo[3], a.hi[0], a.hi[1], a.hi[2], a.hi[3]};
-    const i32x8 bv = {b.lo[0], b.lo[1], b.lo[2], b.lo[3], b.hi[0], b.hi[1], b.hi[2], b.hi[3]};
-    // formats 0/0: both operands float8 e4m3; E8M0 block scales 127 = 2^0
-    return __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
-}
-
-// Candidate search of the low-precision forms: same persistent band-ordered
-// 64x64 wavefront tiles as the FP32 path. A pair becomes a candidate when its
-// low-precision score is >= lo_thr = tau - (the largest rescoring band over all
-// rows); the rescoring kernel then decides each candidate exactly.
-// q: [n_pad][ldq] bytes of codes (zero padded), scale: [n_pad] (FP8 only).
-template <int PREC, int NK>
-__global__ __launch_bounds__(256) void k_compare_lowp(const uint8_t* __restrict__ q, int ldq_bytes,
-                                                      const float* __restrict__ scale, int n,
-                                                      const float* __restrict__ lo_thr_ptr, TileOrder ord,
-                                                      PairSink cand) {
-    using T = LowpTraits<PREC>;
-    static_assert(NK % 2 == 0, "even step count");
-    __shared__ TileLds lds;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int li = lane & 15, lg = lane >> 4;
-    PairStage st{lds.stage[wave], 0};
-    float* scr = lds.scr[wave];
-    const float lo_thr = *lo_thr_ptr;
-    const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
-    const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
-    const int64_t stride = per_xcd_blocks * 4;
-    int64_t t = t_lo + bx * 4 + wave;
-    if (t >= t_hi) return;
-    TileOrder::Cursor cur = ord.seek(t);
-    int bi, bj;
-    ord.tile(cur, t, &bi, &bj);
-    constexpr int kStepBytes = T::kStep * T::kBytes;
-    const uint8_t* pa = q + (int64_t)(bi * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-    const uint8_t* pb = q + (int64_t)(bj * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-    Frag<PREC> a[2][4], b[2][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        a[0][x].load(pa + (int64_t)16 * x * ldq_bytes);
-        b[0][x].load(pb + (int64_t)16 * x * ldq_bytes);
-    }
-    while (true) {
-        const int64_t tn = t + stride;
-        const bool more = tn < t_hi;
-        int ni = 0, nj = 0;
-        if (more) ord.tile(cur, tn, &ni, &nj);
-        f32x4 acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const int row0 = bi * kWT, col0 = bj * kWT;
-#pragma unroll
-        for (int c = 0; c < NK; ++c) {
-            const int cur_b = c & 1, nxt = cur_b ^ 1;
-            if (c + 1 < NK) {
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[nxt][x].load(pa + (int64_t)16 * x * ldq_bytes + kStepBytes * (c + 1));
-                    b[nxt][x].load(pb + (int64_t)16 * x * ldq_bytes + kStepBytes * (c + 1));
-                }
-            } else if (more) {
-                pa = q + (int64_t)(ni * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-                pb = q + (int64_t)(nj * kWT + li) * ldq_bytes + lg * T::kLaneBytes;
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[nxt][x].load(pa + (int64_t)16 * x * ldq_bytes);
-                    b[nxt][x].load(pb + (int64_t)16 * x * ldq_bytes);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int y = 0; y < 4; ++y) acc[x][y] = mma(a[cur_b][x], b[cur_b][y], acc[x][y]);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
-        const int ib = row0 + 4 * lg, jb = col0 + li;
-        if constexpr (PREC == MRC_PREC_FP8) {
-            float cs[4];
-#pragma unroll
-            for (int y = 0; y < 4; ++y) cs[y] = scale[jb + 16 * y];
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const float rs = scale[ib + 16 * x + r];
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y][r] = acc[x][y][r] * rs * cs[y];
-                }
-        }
-        tile_epilogue(acc, lo_thr, interior, ib, jb, n, scr, st, cand);
-        if (!more) break;
-        t = tn;
-        bi = ni;
-        bj = nj;
-    }
-    st.flush(cand);
-}
-
-
-// Launch of the candidate kernel of one precision over the band-ordered tiles.
-template <int PREC>
-mrc_status launch_lowp_kernel(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, const float* scale, int64_t n, int nk,
-                              const float* d_lo_thr, const TileOrder& ord, int64_t grid, PairSink cand,
-                              hipStream_t s) {
-#define MRC_LP(c)                                                                                        \
-    case c: {                                                                                            \
-        const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_lowp<PREC, c>, 256, grid);     \
-        hipLaunchKernelGGL((k_compare_lowp<PREC, c>), dim3((unsigned)pgrid), dim3(256), 0, s, q, ldq_bytes, \
-                           scale, (int)n, d_lo_thr, ord, cand);                                          \
-    } break;
-    if constexpr (PREC == MRC_PREC_BF16) {
-        switch (nk) {
-            MRC_LP(2) MRC_LP(4) MRC_LP(6) MRC_LP(8) MRC_LP(10) MRC_LP(12) MRC_LP(16) MRC_LP(20) MRC_LP(24) MRC_LP(32)
-            default: return fail(MRC_E_INVAL, "unsupported k for the BF16 form");
-        }
-    } else {
-        switch (nk) {
-            MRC_LP(2) MRC_LP(4) MRC_LP(6) MRC_LP(8)
-            default: return fail(MRC_E_INVAL, "unsupported k for the FP8 form");
-        }
-    }
-#undef MRC_LP
-    MRC_HIP_TRY(ctx, hipGetLastError());
-    return MRC_OK;
-}
 
 }  // namespace

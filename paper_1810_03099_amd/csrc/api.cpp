@@ -385,10 +385,11 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
     }
     // BF16 / FP8: candidates on the matrix cores, then exact decisions by rescoring.
     const int prec = opts->precision;
-    const int step = prec == MRC_PREC_BF16 ? 32 : 128, ebytes = prec == MRC_PREC_BF16 ? 2 : 1;
-    const int ldq = lowp_steps(prec, k) * step;
-    // BF16 blocks are 256 rows, FP8 blocks 64
-    const int64_t n_pad = ceil_div(n > 0 ? n : 1, prec == MRC_PREC_BF16 ? 256 : 64) * (prec == MRC_PREC_BF16 ? 256 : 64);
+    const int ebytes = prec == MRC_PREC_BF16 ? 2 : 1;
+    const int chunks = lowp_lds_chunks(prec, k);
+    if (chunks < 0) return fail(MRC_E_INVAL, "mrc_compare: k too large for the low-precision form");
+    const int ldq = chunks * 128 / ebytes;  // components per row (whole 128-byte chunks)
+    const int64_t n_pad = ceil_div(n > 0 ? n : 1, 256) * 256;  // 256-row blocks
     void *unit = nullptr, *q = nullptr, *scale = nullptr, *err = nullptr;
     MRC_TRY(scratch(ctx, "lp_unit", (size_t)(n > 0 ? n : 1) * k * sizeof(float), &unit));
     MRC_TRY(scratch(ctx, "lp_codes", (size_t)n_pad * ldq * ebytes, &q));

@@ -197,8 +197,8 @@ struct PairSink {
 mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
                               PairSink sink, hipStream_t s);
 
-// Low-precision forms. Codes are [n_pad][ldq] (bytes per row ldq_bytes), rows
-// padded to 64 and columns to an even number of MFMA steps (lowp_steps).
+// Even number of 16x16 matrix-core steps (32 BF16 or 128 FP8 components)
+// covering k: the column padding of the query kernels' code layouts.
 int lowp_steps(int precision, int k);
 mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q, int ldq_bytes,
                                const float* scale, int64_t n, int32_t k, const float* d_lo_thr,
@@ -324,14 +324,15 @@ struct TileOrder {
 };
 
 mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s);
-// BF16 candidate kernels (bf16.hip, LDS-tiled 256x256 blocks), called by
-// launch_compare_lowp; the codes need ceil(n / 256) * 256 rows.
-mrc_status launch_compare_bf16(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, int64_t n, int nk,
-                               const float* d_lo_thr, PairSink cand, hipStream_t s);
-// FP8 candidate kernels (fp8.hip), called by launch_compare_lowp.
-mrc_status launch_compare_fp8(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, const float* scale, int64_t n, int nk,
-                              const float* d_lo_thr, const TileOrder& ord, int64_t grid, PairSink cand,
-                              hipStream_t s);
+// Low-precision candidate kernels (lds_allpairs.hip, LDS-tiled 256x256 blocks),
+// called by launch_compare_lowp. The codes need ceil(n / 256) * 256 rows of
+// ldq_bytes = 128 * lowp_lds_chunks(precision, k) bytes, zero padded; the FP8
+// row scales are powers of two.
+int lowp_lds_chunks(int precision, int k);  // -1: k too large for the form
+mrc_status launch_compare_bf16(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, int64_t n, const float* d_lo_thr,
+                               PairSink cand, hipStream_t s);
+mrc_status launch_compare_fp8(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, const float* scale, int64_t n,
+                              const float* d_lo_thr, PairSink cand, hipStream_t s);
 // Workgroups of a persistent launch: as many as are resident at once on the
 // device (occupancy x CUs), rounded down to a multiple of the 8 XCDs and at most
 // `cap`.

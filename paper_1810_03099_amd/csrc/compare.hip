@@ -2,15 +2,18 @@
 // Eq. 2 calls multi reference cosine).
 //
 //  * k_normalise: unit signatures u = sig / |sig| (float32), their bfloat16
-//    codes, float8 e4m3fn codes with a per-row scale max|u|/448, and per-row
-//    error norms |u - dequantised| used to bound low-precision scores.
+//    codes, float8 e4m3fn codes with a per-row power-of-two scale (the
+//    smallest one >= max|u|/448, so that the matrix cores can apply it as an
+//    E8M0 operand scale), and per-row error norms |u - dequantised| used to
+//    bound low-precision scores.
 //  * k_compare_f32: the plain path. Every pair i < j gets the score
 //    acc = 0; acc = fmaf(u_ic, u_jc, acc), c = 0..k-1, computed on the FP32
 //    matrix cores (whose 16x16x4 step is that chain over its four k-values),
 //    persistent wavefronts over 64x64 upper-triangle tiles; pairs with
 //    acc >= tau are appended to the output.
-//  * k_compare_lowp: the same tiling over BF16 / FP8 codes, emitting the
-//    candidates that k_rescore then decides with the plain chain.
+//  * launch_compare_lowp: the candidate search over the BF16 / FP8 codes
+//    (LDS-tiled kernels of lds_allpairs.hip), emitting the candidates that
+//    k_rescore then decides with the plain chain.
 //  * k_score_pairs / k_rescore: the same chain for listed pairs.
 #include <algorithm>
 
@@ -110,7 +113,10 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
             o.umfma[o.frag ? frag_offset(row, c, o.ld_mfma / 16) : row * o.ld_mfma + mfma_col(c)] = v[r];
     }
     amax = mrc_dev::wave_max(amax);
-    const float sc = amax / 448.0f;
+    // smallest power of two >= amax / 448 (amax / 448 is a normal float: a
+    // unit vector of k <= 1024 components has amax >= 2^-5)
+    float sc = amax / 448.0f;
+    if (__float_as_uint(sc) & 0x007FFFFFu) sc = __uint_as_float((__float_as_uint(sc) & 0x7F800000u) + 0x00800000u);
     double eb = 0.0, e8 = 0.0;
 #pragma unroll
     for (int r = 0; r < kMaxPerLane; ++r) {
@@ -401,14 +407,11 @@ int lowp_steps(int precision, int k) {
 mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q, int ldq_bytes,
                                const float* scale, int64_t n, int32_t k, const float* d_lo_thr,
                                PairSink cand, hipStream_t s) {
+    (void)k;
     if (n < 2) return MRC_OK;
-    TileOrder ord;
-    int64_t grid = 0;
-    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
-    const int nk = lowp_steps(precision, k);
     ScopedTimer tm(ctx, "compare_lowp", s);
-    if (precision == MRC_PREC_BF16) return launch_compare_bf16(ctx, q, ldq_bytes, n, nk, d_lo_thr, cand, s);
-    return launch_compare_fp8(ctx, q, ldq_bytes, scale, n, nk, d_lo_thr, ord, grid, cand, s);
+    if (precision == MRC_PREC_BF16) return launch_compare_bf16(ctx, q, ldq_bytes, n, d_lo_thr, cand, s);
+    return launch_compare_fp8(ctx, q, ldq_bytes, scale, n, d_lo_thr, cand, s);
 }
 
 // Accumulation slack of a low-precision score relative to |a_i||a_j|. BF16

@@ -403,6 +403,12 @@ def test_lowp_band_covers_quantisation_error():
         assert mrc.lowp_band(eb[ii], eb[jj], k).max() == 0.02
         # fp8 with per-row scale
         codes, scale = mrc.fp8_quantise_rows(shat)
+        # power-of-two scales just covering each row: max|s| / scale lies in
+        # (224, 448], so the largest code (its rounding) lies in [224, 448]
+        nz = scale > 0
+        assert np.all(np.frexp(scale[nz].astype(np.float64))[0] == 0.5)
+        top = np.abs(mrc.fp8_e4m3fn_value(codes)).max(axis=1)
+        assert np.all((top[nz] >= 224.0) & (top[nz] <= 448.0))
         q8 = mrc.fp8_dequantise_rows(codes, scale)
         e8 = mrc.row_quant_error(shat, q8)
         lp8 = np.einsum("pc,pc->p", q8[ii], q8[jj])
