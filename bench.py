@@ -54,8 +54,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--workload", default="plain_full", choices=["plain_full", "precision"],
-                    help="plain_full: 20k docs, k=64 (default); precision: 200k docs, k=256")
+    ap.add_argument("--workload", default="plain_full", choices=["plain_full", "precision", "serving"],
+                    help="plain_full: 20k docs, k=64 (default); precision: 200k docs, k=256; "
+                         "serving: 1M-signature database, k=128, query stream")
+    ap.add_argument("--serve-seconds", type=float, default=4.0,
+                    help="serving workload: length of each offered-load run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -143,6 +146,9 @@ def main():
     from synth import corpus as synth
 
     prec = {"fp32": mrc.PREC_FP32, "bf16": mrc.PREC_BF16, "fp8": mrc.PREC_FP8}[a.precision]
+    if a.workload == "serving":
+        print(json.dumps(serving(a, mrc, synth, prec)))
+        return
     spec_idx = 1 if a.workload == "plain_full" else 2
     cs = synth.CONFIGS[spec_idx]
     k, tau = cs.k, cs.tau
@@ -413,6 +419,131 @@ def extras(mrc, ctx, c, off, tok, sig, model, k, tau, cap, shat, sign_ms, counts
     q["database_rows"] = n
     ex["query"] = q
     return ex
+
+
+def percentile_ms(x, q):
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def serving(a, mrc, synth, prec):
+    """Serving form: a 1,000,000-signature database (k = 128, FP32 + BF16 copies)
+    resident in HBM, queried by new documents. Reports the database build
+    (documents signed per second at that scale), closed-loop batch throughput
+    of mrc_query, and the serving loop under Poisson arrivals at fractions of
+    its measured saturation rate (p50 / p99 latency from submit to result)."""
+    import torch
+    spec_idx = 3
+    cs = synth.CONFIGS[spec_idx]
+    k, tau = cs.k, 0.9
+    log(f"generating the database corpus ({cs.n_docs} docs)")
+    c = synth.generate(spec_idx)
+    n = c.n_docs
+    log(f"corpus: {n} docs, {c.tokens.size} tokens")
+    torch.cuda.set_device(0)
+    ctx = mrc.mrc_ctx_create(0)
+    off = torch.from_numpy(c.offsets).cuda()
+    tok = torch.from_numpy(c.tokens).cuda()
+    sig = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    # database build: model + signatures of all documents (the first call warms up)
+    model, _ = mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(k), sig_out=sig)
+    del model
+    torch.cuda.synchronize()
+    kms, wall, (model, _) = timed(mrc, ctx, "sign_counts",
+                                  lambda: mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(k),
+                                                                 sig_out=sig), 3)
+    build = {"docs": n, "tokens": int(c.tokens.size), "build_and_sign_ms": wall,
+             "docs_signed_per_s_build_and_sign": n / (wall / 1e3), "sign_counts_kernel_ms": kms}
+    log(f"build + sign: {wall:.1f} ms ({n / (wall / 1e3):.3g} docs/s)")
+    db = mrc.mrc_db_create(ctx, n + 65536, k, precisions=(mrc.PREC_BF16,))
+    mrc.mrc_db_insert(db, sig)
+    torch.cuda.synchronize()
+    del off, tok, sig
+    torch.cuda.empty_cache()
+    qc = synth.generate_queries(cs, 12000, seed=31, median=400, sigma=1.2, hi=20000, near_of=c, near_frac=0.2)
+    del c
+    qo = torch.from_numpy(qc.offsets).cuda()
+    qt = torch.from_numpy(qc.tokens).cuda()
+    docs = [qc.doc(i) for i in range(qc.n_docs)]
+    out = {"metric": "near-dup pairs compared/s & docs signed/s at stated recall; p50/p99 query ms",
+           "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp32": "f32", "bf16": "bf16", "fp8": "fp8e4m3"}[a.precision],
+           "data": "synthetic (seeded Zipf/topic/lognormal generator; database 1M docs, queries lognormal "
+                   "median 400, sigma 1.2, 20-20,000 tokens, 20% near duplicates of database docs)",
+           "config": {"workload": f"serving_db: {n} signatures x k={k} resident (FP32 + BF16), top-16 + tau={tau}",
+                      "n_db": n, "k": k, "tau": tau, "precision": a.precision},
+           "database_build": build}
+    # closed-loop batches through mrc_query (queries already on the device)
+    batch = {}
+    for pname, p in [("fp32", mrc.PREC_FP32), ("bf16", mrc.PREC_BF16)]:
+        rows = {}
+        for b in (1, 16, 256, 4096):
+            o1 = (qo[:b + 1] - qo[0]).contiguous()
+            t1 = qt[int(qc.offsets[0]):int(qc.offsets[b])].contiguous()
+            mrc.mrc_query(ctx, db, model, o1, t1, 16, tau, p)
+            torch.cuda.synchronize()
+            reps = 20 if b < 256 else 5
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                mrc.mrc_query(ctx, db, model, o1, t1, 16, tau, p)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            rows[str(b)] = {"ms": dt * 1e3, "docs_per_s": b / dt, "pairs_per_s": b * n / dt}
+        batch[pname] = rows
+        log(f"mrc_query {pname}: " + ", ".join(f"b={b} {r['ms']:.2f} ms" for b, r in rows.items()))
+    out["query_batches"] = batch
+    # serving loop: saturation (everything submitted at once), then Poisson arrivals
+    srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=prec,
+                              max_wait_us=500)
+
+    def run(arrival_gaps):
+        tickets = []
+        t0 = time.perf_counter()
+        due = t0
+        for i, g in enumerate(arrival_gaps):
+            due += g
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+                if due - now > 2e-4:
+                    time.sleep((due - now) * 0.5)
+            tk = mrc.mrc_serve_submit(srv, docs[i % len(docs)])
+            tickets.append(tk)
+        res = [mrc.mrc_serve_poll(srv, tk, wait_ms=120000) for tk in tickets if tk is not None]
+        wall = time.perf_counter() - t0
+        lat = [r.t_done_ms - r.t_submit_ms for r in res if r is not None and r.status == 0]
+        first = min(r.t_submit_ms for r in res)
+        last = max(r.t_done_ms for r in res)
+        return {"offered": len(arrival_gaps), "admitted": len(res), "completed": len(lat),
+                "p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
+                "docs_per_s": len(lat) / ((last - first) / 1e3), "wall_s": wall}
+
+    sat = run([0.0] * 8192)
+    sat_rate = sat["docs_per_s"]
+    log(f"serving saturation: {sat_rate:.0f} docs/s, p50 {sat['p50_ms']:.1f} ms, p99 {sat['p99_ms']:.1f} ms")
+    rng = np.random.default_rng(41)
+    loads = {}
+    for frac in (0.25, 0.5, 0.8, 0.95):
+        lam = frac * sat_rate
+        m = int(min(max(lam * a.serve_seconds, 200), 60000))
+        r = run(rng.exponential(1.0 / lam, m).tolist())
+        r["offered_docs_per_s"] = lam
+        loads[str(frac)] = r
+        log(f"load {frac}: offered {lam:.0f}/s, achieved {r['docs_per_s']:.0f}/s, p50 {r['p50_ms']:.2f} ms, "
+            f"p99 {r['p99_ms']:.2f} ms")
+    mrc.mrc_serve_stop(srv)
+    out["serving"] = {"saturation": sat, "poisson": loads, "max_batch": 4096, "n_streams": 2,
+                      "precision": a.precision}
+    out["value"] = sat_rate * n
+    out["unit"] = "pairs/s"
+    out["steps"] = 1
+    out["warmup"] = 1
+    out["ms_per_step"] = 1e3 / sat_rate
+    out["p50_query_ms_at_0.5_load"] = loads["0.5"]["p50_ms"]
+    out["p99_query_ms_at_0.5_load"] = loads["0.5"]["p99_ms"]
+    out["note"] = ("value = serving-loop queries/s at saturation x database rows; ms_per_step = ms per query "
+                   "at saturation; latencies are submit-to-result on the host clock")
+    return out
 
 
 if __name__ == "__main__":

@@ -26,6 +26,7 @@
 // is part of, gives the same bits. |w_d| is the square root of that exact sum,
 // rounded once to float64.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -536,51 +537,137 @@ __global__ __launch_bounds__(256) void k_df_atomic(const int64_t* __restrict__ o
 
 // One wavefront per document over its distinct-term list (same exact sums as
 // the hash passes, so the same signature bits).
+// mantissa(x) << exponent(x) for a float 1 <= x < 32: x * 2^23, an integer
+// below 2^28.
+__device__ __forceinline__ uint32_t idf_scaled(float x) {
+    const uint32_t b = __float_as_uint(x);
+    return ((b & 0x7FFFFFu) | 0x800000u) << ((b >> 23) - 127u);
+}
+
+// c * 2^32 for a float 1 <= c < 2^24 (the value mrc_dev::fixed32 gives, from
+// the bits alone).
+__device__ __forceinline__ unsigned long long fixed32_ge1(float c) {
+    const uint32_t b = __float_as_uint(c);
+    return (unsigned long long)((b & 0x7FFFFFu) | 0x800000u) << ((b >> 23) - 127u + 9u);
+}
+
+// Entries per lane and pass of k_sign_counts (512 per wavefront pass: one
+// pass covers most documents).
+constexpr int kSignPer = 8;
+
 __global__ __launch_bounds__(256) void k_sign_counts(const int64_t* __restrict__ off, int64_t n,
                                                      const int32_t* __restrict__ term,
                                                      const int32_t* __restrict__ tfv,
                                                      const int32_t* __restrict__ nnz, PassArgs a,
                                                      const unsigned long long* __restrict__ err) {
     extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int R = kSignPer;
     const int kpad = (a.k + 1) & ~1;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     unsigned long long* bins = (unsigned long long*)smem + (size_t)wave * kpad;
+    double* rinv = (double*)smem + (size_t)4 * kpad;  // 1 / |r_j|, staged once per workgroup
     if (pass_disabled(err)) return;
     for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
-    for (int64_t d = (int64_t)blockIdx.x * 4 + wave; d < n; d += (int64_t)gridDim.x * 4) {
-        const int64_t o = off[d];
-        const int m = nnz[d];
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+    for (int j = threadIdx.x; j < a.k; j += 256) rinv[j] = a.rinv[j];
+    __syncthreads();
+    const int64_t stride = (int64_t)gridDim.x * 4;
+    const int64_t d0 = (int64_t)blockIdx.x * 4 + wave;
+    if (d0 >= n) return;
+    // Entries e0 .. e0 + 64 R - 1 of a document's count list, lane-interleaved
+    // (lanes past the end read the last entry, so the loads need no branches;
+    // which entries are real is decided where they are used).
+    const int64_t last = max(off[n] - 1, (int64_t)0);  // the lists hold max(T, 1) entries
+    auto load_chunk = [&](int64_t o, int m, int e0, int (&t)[R], int (&f)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int64_t p = min(max(o + min(e0 + r * 64 + lane, m - 1), (int64_t)0), last);
+            t[r] = term[p];
+            f[r] = tfv[p];
+        }
+    };
+    auto gather = [&](const int (&t)[R], int m, int e0, TermInfo (&ti)[R]) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) ti[r] = a.tinfo[e0 + r * 64 + lane < m ? t[r] : 0];
+    };
+    // (without a document that far ahead the loads re-read the last one: no
+    // branches, so every wait below is exact)
+    auto doc_at = [&](int64_t dd, int64_t& o, int& m) {
+        const int64_t dl = min(dd, n - 1);
+        o = off[dl];
+        m = dd < n ? nnz[dl] : 0;
+    };
+    // Software pipeline over this wavefront's documents d, d + stride, ...:
+    // iteration d holds d's tf and term info, d+1's list entries (loaded one
+    // iteration ago) and issues d+1's term-info gathers and d+2's list loads
+    // before it waits for anything, so both latencies overlap a document's sums,
+    // reduction and write.
+    int f_c[R], t_n[R], f_n[R], t_nn[R], f_nn[R];
+    TermInfo ti_c[R], ti_n[R];
+    int64_t o_c, o_n, o_nn;
+    int m_c, m_n, m_nn;
+    doc_at(d0, o_c, m_c);
+    doc_at(d0 + stride, o_n, m_n);
+    {
+        int t_c[R];
+        load_chunk(o_c, max(m_c, 1), 0, t_c, f_c);
+        load_chunk(o_n, max(m_n, 1), 0, t_n, f_n);
+        gather(t_c, m_c, 0, ti_c);
+    }
+    for (int64_t d = d0; d < n; d += stride) {
+        doc_at(d + 2 * stride, o_nn, m_nn);
+        gather(t_n, m_n, 0, ti_n);
+        load_chunk(o_nn, max(m_nn, 1), 0, t_nn, f_nn);
+        __builtin_amdgcn_sched_barrier(0);  // the requests above go out before any wait
+        // |w_d|^2 exactly: (tf idf)^2 = A^2 2^-46 with the integer
+        // A = tf (mantissa(idf) << exponent(idf)) < 2^50, split at bit 25
+        // into three partial products (< 2^51 each; a pass adds at most R)
         u128 nacc = 0;
-        for (int e0 = 0; e0 < m; e0 += 256) {
-            int t_r[4], f_r[4];
+        auto sums = [&](const int (&f_r)[R], const TermInfo (&ti_r)[R], int e0) {
+            uint64_t s2 = 0, s1 = 0, s0 = 0;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int e = e0 + r * 64 + lane;
-                t_r[r] = e < m ? term[o + e] : -1;
-                f_r[r] = e < m ? tfv[o + e] : 0;
+            for (int r = 0; r < R; ++r) {
+                if (e0 + r * 64 >= m_c) break;  // (wavefront-uniform) no entries left
+                const bool ok = e0 + r * 64 + lane < m_c;
+                const uint32_t f = ok ? (uint32_t)f_r[r] : 0u;
+                const uint64_t A = (uint64_t)f * idf_scaled(ti_r[r].idf);
+                const uint32_t hi = (uint32_t)(A >> 25), lo = (uint32_t)A & 0x1FFFFFFu;
+                s2 += (uint64_t)hi * hi;
+                s1 += (uint64_t)hi * lo;
+                s0 += (uint64_t)lo * lo;
+                if (ok && ti_r[r].part >= 0)
+                    atomicAdd(&bins[ti_r[r].part], (unsigned long long)f * fixed32_ge1(ref_coef(a, ti_r[r].idf)));
             }
-            TermInfo ti_r[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) ti_r[r] = t_r[r] >= 0 ? a.tinfo[t_r[r]] : TermInfo{1.f, -1};
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                if (t_r[r] < 0) continue;
-                nacc += term_sq_fixed((uint32_t)f_r[r], ti_r[r].idf);
-                if (ti_r[r].part >= 0)
-                    atomicAdd(&bins[ti_r[r].part],
-                              (unsigned long long)f_r[r] * mrc_dev::fixed32(ref_coef(a, ti_r[r].idf)));
-            }
+            nacc += ((u128)s2 << 50) + ((u128)s1 << 26) + (u128)s0;
+        };
+        sums(f_c, ti_c, 0);
+        for (int e0 = 64 * R; e0 < m_c; e0 += 64 * R) {  // longer lists (rare): the rest, synchronously
+            int t_x[R], f_x[R];
+            TermInfo ti_x[R];
+            load_chunk(o_c, m_c, e0, t_x, f_x);
+            gather(t_x, m_c, e0, ti_x);
+            sums(f_x, ti_x, e0);
         }
         const double nrm = norm_from_fixed(wave_sum_u128(nacc));
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        write_signature(a, d, bins, nrm, lane, 64);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-        __builtin_amdgcn_wave_barrier();
+        // one wavefront owns `bins`, and LDS executes its operations in order:
+        // compiler-only fences (and no global loads here) keep the requests of
+        // the next documents in flight
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        float* out = a.sig + d * a.k;
+        for (int j = lane; j < a.k; j += 64)
+            out[j] = (float)(nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * rinv[j] / nrm : 0.0);
+        if (lane == 0 && a.norm) a.norm[d] = (float)nrm;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        // rotate the pipeline
+        o_c = o_n, m_c = m_n, o_n = o_nn, m_n = m_nn;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            f_c[r] = f_n[r];
+            ti_c[r] = ti_n[r];
+            t_n[r] = t_nn[r];
+            f_n[r] = f_nn[r];
+        }
     }
 }
 
@@ -720,10 +807,13 @@ mrc_status launch_sign_counts(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* 
     a.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
     a.sig = sig_out;
     a.norm = norm_out;
-    const size_t lds = (size_t)4 * (size_t)((m->k + 1) & ~1) * 8;
+    const size_t lds = (size_t)5 * (size_t)((m->k + 1) & ~1) * 8;  // 4 wavefronts' bins + rinv
     ScopedTimer tm(ctx, "sign_counts", s);
-    hipLaunchKernelGGL(k_sign_counts, dim3(grid_for(n, 4, 256 * 16)), dim3(256), lds, s, docs->offsets, n, c.term,
-                       c.tf, c.nnz, a, (const unsigned long long*)ctx->d_flags);
+    // persistent: every wavefront walks its documents with the next one's
+    // loads in flight
+    const int64_t grid = persistent_grid(ctx, (const void*)k_sign_counts, 256, ceil_div(n, 4));
+    hipLaunchKernelGGL(k_sign_counts, dim3((unsigned)grid), dim3(256), lds, s, docs->offsets, n, c.term, c.tf,
+                       c.nnz, a, (const unsigned long long*)ctx->d_flags);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }
