@@ -34,9 +34,9 @@ def sources():
                   if f.endswith((".hip", ".cpp")))
 
 
-# Per-source extra flags: the all-pairs kernels keep their matrix-core
-# accumulators in VGPRs (their epilogues read every accumulator).
-EXTRA = {"compare.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
+# Per-source extra flags: the 64x64 FP32 all-pairs kernels keep their
+# matrix-core accumulators in VGPRs (their epilogues read every accumulator).
+EXTRA = {"allpairs_f32_small.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 
 def _compile(src: str) -> str:

@@ -1,0 +1,129 @@
+// FP32 plain path of the all-pairs comparison for short signatures (k <= 64)
+// and very long ones (k > 512, where the 128x128 tiles of allpairs_f32.hip run
+// out of registers): the same chain (every score bit-identical to
+// acc = fmaf(u_ic, u_jc, acc), c = 0..k-1, on the FP32 matrix cores), over
+// 64x64 wavefront tiles with two wavefronts per SIMD. With few components per
+// pair a tile's products are short, and the second wavefront's products hide
+// one wavefront's flag walk, which dense candidate sets make long. Built with
+// the accumulators in VGPRs (its epilogue reads every accumulator).
+#include "allpairs.h"
+#include "common.h"
+
+using namespace mrc;
+
+namespace {
+
+// Persistent wavefronts: workgroup p runs on XCD p % 8 and its wavefronts walk
+// that XCD's contiguous share of the band-ordered tiles. Each tile is 64x64;
+// the 16-column chunks are fully unrolled (NC even) and the first chunk of
+// the next tile is loaded during the last chunk of the current one; the next
+// tile's coordinates are found before the current tile's products.
+template <int NC>
+__global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u, int n, float tau, TileOrder ord,
+                                                     PairSink sink) {
+    static_assert(NC % 2 == 0, "even chunk count");
+    __shared__ TileLds lds;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    PairStage st{lds.stage[wave], 0};
+    float* scr = lds.scr[wave];
+    const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
+    const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
+    const int64_t stride = per_xcd_blocks * 4;
+    int64_t t = t_lo + bx * 4 + wave;
+    if (t >= t_hi) return;
+    TileOrder::Cursor cur = ord.seek(t);
+    int bi, bj;
+    ord.tile(cur, t, &bi, &bj);
+    // fragment (16-row block x of the tile, chunk c) of a 64-row panel p
+    auto frag = [&](const float* p, int x, int c) { return *(const f32x4*)(p + ((int64_t)x * NC + c) * 256); };
+    auto panel = [&](int blk) { return u + ((int64_t)blk * 4 * NC * 64 + lane) * 4; };
+    const float* pa = panel(bi);
+    const float* pb = panel(bj);
+    f32x4 a[2][4], b[2][4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+        a[0][x] = frag(pa, x, 0);
+        b[0][x] = frag(pb, x, 0);
+    }
+    while (true) {
+        const int64_t tn = t + stride;
+        const bool more = tn < t_hi;
+        int ni = 0, nj = 0;
+        if (more) ord.tile(cur, tn, &ni, &nj);
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int row0 = bi * kWT, col0 = bj * kWT;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const int cur_b = c & 1, nxt = cur_b ^ 1;
+            if (c + 1 < NC) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[nxt][x] = frag(pa, x, c + 1);
+                    b[nxt][x] = frag(pb, x, c + 1);
+                }
+            } else if (more) {
+                // first chunk of the next tile (NC even: it goes to buffer 0)
+                pa = panel(ni);
+                pb = panel(nj);
+#pragma unroll
+                for (int x = 0; x < 4; ++x) {
+                    a[nxt][x] = frag(pa, x, 0);
+                    b[nxt][x] = frag(pb, x, 0);
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur_b][x][m], b[cur_b][y][m], acc[x][y], 0,
+                                                                         0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
+        const int ib = row0 + 4 * lg, jb = col0 + li;
+        tile_epilogue(acc, tau, interior, ib, jb, n, scr, st, sink);
+        if (!more) break;
+        t = tn;
+        bi = ni;
+        bj = nj;
+    }
+    st.flush(sink);
+}
+
+}  // namespace
+
+namespace mrc {
+
+mrc_status launch_compare_f32_small(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
+                                    PairSink sink, hipStream_t s) {
+    if (n < 2) return MRC_OK;
+    TileOrder ord;
+    int64_t grid = 0;
+    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
+    const int nc = mfma_chunks(k);
+    ScopedTimer tm(ctx, "compare_f32", s);
+    switch (nc) {
+#define MRC_NC(c)                                                                                        \
+    case c: {                                                                                            \
+        const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_f32<c>, 256, grid);            \
+        hipLaunchKernelGGL(k_compare_f32<c>, dim3((unsigned)pgrid), dim3(256), 0, s, umfma, (int)n, tau, ord,   \
+                           sink);                                                                        \
+    } break;
+        MRC_NC(2) MRC_NC(4) MRC_NC(48) MRC_NC(64)
+#undef MRC_NC
+        default: return fail(MRC_E_INVAL, "chunk count not instantiated for the 64x64 kernel");
+    }
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
+}  // namespace mrc

@@ -368,7 +368,7 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
     st.n_pairs_compared = n * (n - 1) / 2;
     unsigned long long* counter = (unsigned long long*)(ctx->d_flags + 4);
     if (opts->precision == MRC_PREC_FP32) {
-        const int64_t n_pad = ceil_div(n > 0 ? n : 1, 64) * 64, kp = 16 * (int64_t)mfma_chunks(k);
+        const int64_t n_pad = ceil_div(n > 0 ? n : 1, 128) * 128, kp = 16 * (int64_t)mfma_chunks(k);  // 128-row tiles
         void* umfma = nullptr;
         MRC_TRY(scratch(ctx, "cmp_unit_mfma", (size_t)(n_pad * kp) * sizeof(float), &umfma));
         MRC_TRY(clear_words(ctx, ctx->d_flags, 16, s));

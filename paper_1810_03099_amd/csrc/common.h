@@ -196,6 +196,9 @@ struct PairSink {
 
 mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
                               PairSink sink, hipStream_t s);
+// 64x64-tile form of the same (allpairs_f32_small.hip; k <= 64 or k > 512).
+mrc_status launch_compare_f32_small(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
+                                    PairSink sink, hipStream_t s);
 
 // Even number of 16x16 matrix-core steps (32 BF16 or 128 FP8 components)
 // covering k: the column padding of the query kernels' code layouts.

@@ -6,11 +6,8 @@
 //    smallest one >= max|u|/448, so that the matrix cores can apply it as an
 //    E8M0 operand scale), and per-row error norms |u - dequantised| used to
 //    bound low-precision scores.
-//  * k_compare_f32: the plain path. Every pair i < j gets the score
-//    acc = 0; acc = fmaf(u_ic, u_jc, acc), c = 0..k-1, computed on the FP32
-//    matrix cores (whose 16x16x4 step is that chain over its four k-values),
-//    persistent wavefronts over 64x64 upper-triangle tiles; pairs with
-//    acc >= tau are appended to the output.
+//  * the plain FP32 path (allpairs_f32.hip) and the candidate search over the
+//    BF16 / FP8 codes (lds_allpairs.hip) consume k_normalise's layouts;
 //  * launch_compare_lowp: the candidate search over the BF16 / FP8 codes
 //    (LDS-tiled kernels of lds_allpairs.hip), emitting the candidates that
 //    k_rescore then decides with the plain chain.
@@ -144,94 +141,6 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
     }
 }
 
-// ---------------------------------------------------------------- FP32 plain path
-
-// Persistent wavefronts: workgroup p runs on XCD p % 8 and its wavefronts walk
-// that XCD's contiguous share of the band-ordered tiles. Each tile is 64x64;
-// the 16-column chunks are fully unrolled (NC even) and the first chunk of
-// the next tile is loaded during the last chunk of the current one; the next
-// tile's coordinates are found before the current tile's products.
-template <int NC>
-__global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u, int n, float tau, TileOrder ord,
-                                                     PairSink sink) {
-    static_assert(NC % 2 == 0, "even chunk count");
-    __shared__ TileLds lds;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int li = lane & 15, lg = lane >> 4;
-    PairStage st{lds.stage[wave], 0};
-    float* scr = lds.scr[wave];
-    const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
-    const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
-    const int64_t stride = per_xcd_blocks * 4;
-    int64_t t = t_lo + bx * 4 + wave;
-    if (t >= t_hi) return;
-    TileOrder::Cursor cur = ord.seek(t);
-    int bi, bj;
-    ord.tile(cur, t, &bi, &bj);
-    // fragment (16-row block x of the tile, chunk c) of a 64-row panel p
-    auto frag = [&](const float* p, int x, int c) { return *(const f32x4*)(p + ((int64_t)x * NC + c) * 256); };
-    auto panel = [&](int blk) { return u + ((int64_t)blk * 4 * NC * 64 + lane) * 4; };
-    const float* pa = panel(bi);
-    const float* pb = panel(bj);
-    f32x4 a[2][4], b[2][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x) {
-        a[0][x] = frag(pa, x, 0);
-        b[0][x] = frag(pb, x, 0);
-    }
-    while (true) {
-        const int64_t tn = t + stride;
-        const bool more = tn < t_hi;
-        int ni = 0, nj = 0;
-        if (more) ord.tile(cur, tn, &ni, &nj);
-        f32x4 acc[4][4];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
-        const int row0 = bi * kWT, col0 = bj * kWT;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const int cur_b = c & 1, nxt = cur_b ^ 1;
-            if (c + 1 < NC) {
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[nxt][x] = frag(pa, x, c + 1);
-                    b[nxt][x] = frag(pb, x, c + 1);
-                }
-            } else if (more) {
-                // first chunk of the next tile (NC even: it goes to buffer 0)
-                pa = panel(ni);
-                pb = panel(nj);
-#pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    a[nxt][x] = frag(pa, x, 0);
-                    b[nxt][x] = frag(pb, x, 0);
-                }
-            }
-            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-            for (int m = 0; m < 4; ++m)
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y)
-                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[cur_b][x][m], b[cur_b][y][m], acc[x][y], 0,
-                                                                         0, 0);
-            __builtin_amdgcn_sched_barrier(0);
-        }
-        const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
-        const int ib = row0 + 4 * lg, jb = col0 + li;
-        tile_epilogue(acc, tau, interior, ib, jb, n, scr, st, sink);
-        if (!more) break;
-        t = tn;
-        bi = ni;
-        bj = nj;
-    }
-    st.flush(sink);
-}
-
 // lo_thr = tau - max(nominal, band(e_max, e_max)) with e_max the largest row error.
 __device__ __forceinline__ float lowp_band(float ei, float ej, float nominal, float acc_unit) {
     const float b = ei + ej + ei * ej + acc_unit * (1.f + ei) * (1.f + ej) + 9.5367431640625e-07f;  // + 2^-20
@@ -352,7 +261,7 @@ mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k
                             float* umfma) {
     if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
     NormOut o{unit, k, bf16, k, fp8, k, scale, err, n, umfma, 16 * mfma_chunks(k), n, 1};
-    if (umfma) o.n_pad = ceil_div(n, 64) * 64;
+    if (umfma) o.n_pad = ceil_div(n, 128) * 128;  // the FP32 kernel's 128-row tiles
     return launch_normalise_rows(ctx, sig, n, k, o, s);
 }
 
@@ -371,30 +280,6 @@ int mfma_chunks(int k) {
     for (int c : {2, 4, 6, 8, 12, 16, 24, 32, 48, 64})
         if (nc <= c) return c;
     return -1;
-}
-
-mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
-                              PairSink sink, hipStream_t s) {
-    if (n < 2) return MRC_OK;
-    TileOrder ord;
-    int64_t grid = 0;
-    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
-    const int nc = mfma_chunks(k);
-    ScopedTimer tm(ctx, "compare_f32", s);
-    switch (nc) {
-#define MRC_NC(c)                                                                                        \
-    case c: {                                                                                            \
-        const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_f32<c>, 256, grid);            \
-        hipLaunchKernelGGL(k_compare_f32<c>, dim3((unsigned)pgrid), dim3(256), 0, s, umfma, (int)n, tau, ord,   \
-                           sink);                                                                        \
-    } break;
-        MRC_NC(2) MRC_NC(4) MRC_NC(6) MRC_NC(8) MRC_NC(12) MRC_NC(16) MRC_NC(24) MRC_NC(32)
-        MRC_NC(48) MRC_NC(64)
-#undef MRC_NC
-        default: return fail(MRC_E_INVAL, "k exceeds 1024");
-    }
-    MRC_HIP_TRY(ctx, hipGetLastError());
-    return MRC_OK;
 }
 
 int lowp_steps(int precision, int k) {
