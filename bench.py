@@ -421,6 +421,49 @@ def extras(mrc, ctx, c, off, tok, sig, model, k, tau, cap, shat, sign_ms, counts
     return ex
 
 
+def serving_fp8(mrc, synth, ctx, c, qc, run, tau):
+    """Serving with an FP8 database at scale: 4,000,000 rows x k = 256 (FP8 codes
+    + row scales + the FP32 rescoring copy), built from four copies of the
+    1,000,000 signed documents, under a 50% insert / 50% query stream of
+    documents of 20-50,000 tokens with an 80% admission cap; the same stream
+    against the FP32 plain path on the same database."""
+    import torch
+    k = 256
+    n = c.n_docs
+    off = torch.from_numpy(c.offsets).cuda()
+    tok = torch.from_numpy(c.tokens).cuda()
+    sig = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    model, _ = mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(k), sig_out=sig)
+    del off, tok
+    db = mrc.mrc_db_create(ctx, 4 * n + 400_000, k, precisions=(mrc.PREC_FP8,))
+    for _ in range(4):
+        mrc.mrc_db_insert(db, sig)
+    torch.cuda.synchronize()
+    del sig
+    torch.cuda.empty_cache()
+    rows, _ = mrc.mrc_db_size(db)
+    log(f"FP8 database: {rows} rows x k={k}")
+    docs = [qc.doc(i) for i in range(qc.n_docs)]
+    res = {"database_rows": rows, "k": k, "hbm_frac": 0.8,
+           "database": "four copies of the 1,000,000 signed documents (FP8 codes + scales + FP32 copy)",
+           "stream": "alternating insert / query, lengths lognormal median 400, sigma 1.2, 20-50,000 tokens"}
+    rng = np.random.default_rng(43)
+    for pname, p in [("fp8", mrc.PREC_FP8), ("fp32", mrc.PREC_FP32)]:
+        srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=p,
+                                  max_wait_us=500, hbm_frac=0.8)
+        sat = run([0.0] * 4096, srv=srv, docs=docs, mixed=True)
+        lam = 0.5 * sat["docs_per_s"]
+        half = run(rng.exponential(1.0 / lam, int(min(max(lam * 3.0, 200), 40000))).tolist(), srv=srv, docs=docs,
+                   mixed=True)
+        half["offered_docs_per_s"] = lam
+        mrc.mrc_serve_stop(srv)
+        res[pname] = {"saturation": sat, "poisson_0.5": half}
+        log(f"FP8-scale serving {pname}: saturation {sat['docs_per_s']:.0f} docs/s; at 0.5 load query p50 "
+            f"{half['query_p50_ms']:.2f} ms, p99 {half['query_p99_ms']:.2f} ms")
+    res["database_rows_after"] = mrc.mrc_db_size(db)[0]
+    return res
+
+
 def percentile_ms(x, q):
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
 
@@ -460,7 +503,7 @@ def serving(a, mrc, synth, prec):
     del off, tok, sig
     torch.cuda.empty_cache()
     qc = synth.generate_queries(cs, 12000, seed=31, median=400, sigma=1.2, hi=20000, near_of=c, near_frac=0.2)
-    del c
+    qc5 = synth.generate_queries(cs, 12000, seed=37, median=400, sigma=1.2, hi=50000, near_of=c, near_frac=0.2)
     qo = torch.from_numpy(qc.offsets).cuda()
     qt = torch.from_numpy(qc.tokens).cuda()
     docs = [qc.doc(i) for i in range(qc.n_docs)]
@@ -494,8 +537,10 @@ def serving(a, mrc, synth, prec):
     # serving loop: saturation (everything submitted at once), then Poisson arrivals
     srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=prec,
                               max_wait_us=500)
+    state = {"srv": srv}
 
-    def run(arrival_gaps):
+    def run(arrival_gaps, srv=None, docs=docs, mixed=False):
+        srv = srv if srv is not None else state["srv"]
         tickets = []
         t0 = time.perf_counter()
         due = t0
@@ -507,16 +552,23 @@ def serving(a, mrc, synth, prec):
                     break
                 if due - now > 2e-4:
                     time.sleep((due - now) * 0.5)
-            tk = mrc.mrc_serve_submit(srv, docs[i % len(docs)])
-            tickets.append(tk)
-        res = [mrc.mrc_serve_poll(srv, tk, wait_ms=120000) for tk in tickets if tk is not None]
+            kind = mrc.REQ_INSERT if mixed and i % 2 else mrc.REQ_QUERY
+            tk = mrc.mrc_serve_submit(srv, docs[i % len(docs)], kind)
+            tickets.append((tk, kind))
+        res = [(mrc.mrc_serve_poll(srv, tk, wait_ms=120000), kind) for tk, kind in tickets if tk is not None]
         wall = time.perf_counter() - t0
-        lat = [r.t_done_ms - r.t_submit_ms for r in res if r is not None and r.status == 0]
-        first = min(r.t_submit_ms for r in res)
-        last = max(r.t_done_ms for r in res)
-        return {"offered": len(arrival_gaps), "admitted": len(res), "completed": len(lat),
-                "p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
-                "docs_per_s": len(lat) / ((last - first) / 1e3), "wall_s": wall}
+        ok = [(r, kind) for r, kind in res if r is not None and r.status == 0]
+        lat = [r.t_done_ms - r.t_submit_ms for r, _ in ok]
+        latq = [r.t_done_ms - r.t_submit_ms for r, kind in ok if kind == mrc.REQ_QUERY]
+        first = min(r.t_submit_ms for r, _ in res)
+        last = max(r.t_done_ms for r, _ in res)
+        out = {"offered": len(arrival_gaps), "admitted": len(res), "completed": len(lat),
+               "p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
+               "docs_per_s": len(lat) / ((last - first) / 1e3), "wall_s": wall}
+        if mixed:
+            out["query_p50_ms"] = percentile_ms(latq, 50)
+            out["query_p99_ms"] = percentile_ms(latq, 99)
+        return out
 
     sat = run([0.0] * 8192)
     sat_rate = sat["docs_per_s"]
@@ -534,6 +586,10 @@ def serving(a, mrc, synth, prec):
     mrc.mrc_serve_stop(srv)
     out["serving"] = {"saturation": sat, "poisson": loads, "max_batch": 4096, "n_streams": 2,
                       "precision": a.precision}
+    del db, model, qo, qt
+    torch.cuda.empty_cache()
+    out["serving_fp8_at_scale"] = serving_fp8(mrc, synth, ctx, c, qc5, run, tau)
+    del c
     out["value"] = sat_rate * n
     out["unit"] = "pairs/s"
     out["steps"] = 1

@@ -94,6 +94,7 @@ struct mrc_db {
     uint8_t* d_fp8 = nullptr;    // [cap_pad][ld8]
     float* d_scale = nullptr;    // [cap_pad]
     float* d_err = nullptr;      // [2][cap_pad]: bf16 then fp8 row error bounds
+    float* d_errmax = nullptr;   // [2]: largest bf16 / fp8 row error bound of the committed rows
     size_t bytes = 0;
     std::mutex mu;
 };
@@ -265,6 +266,9 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t db_rows, const mrc_
 
 // Normalise and append unit signatures to a database.
 mrc_status db_append(mrc_db* db, const float* sig, int64_t n, int64_t first, hipStream_t s);
+// Raise errmax[0] / errmax[1] to the largest of the n row error bounds e16[i] /
+// e8[i] (non-negative floats).
+mrc_status launch_err_max(mrc_ctx* ctx, const float* e16, const float* e8, int64_t n, float* errmax, hipStream_t s);
 
 // Upper-triangle tile schedule for the all-pairs kernels. Tile rows are grouped
 // in bands of kBand rows; a band lists its tiles column by column (inside a

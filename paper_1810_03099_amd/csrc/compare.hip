@@ -275,6 +275,30 @@ mrc_status launch_normalise_rows(mrc_ctx* ctx, const float* sig, int64_t n, int3
     return MRC_OK;
 }
 
+__global__ __launch_bounds__(256) void k_err_max(const float* __restrict__ e16, const float* __restrict__ e8,
+                                                 int64_t n, float* __restrict__ errmax) {
+    float m16 = 0.f, m8 = 0.f;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        m16 = fmaxf(m16, e16[i]);
+        m8 = fmaxf(m8, e8[i]);
+    }
+    m16 = mrc_dev::wave_max(m16);
+    m8 = mrc_dev::wave_max(m8);
+    // non-negative floats order like their bit patterns
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax((unsigned int*)&errmax[0], __float_as_uint(m16));
+        atomicMax((unsigned int*)&errmax[1], __float_as_uint(m8));
+    }
+}
+
+mrc_status launch_err_max(mrc_ctx* ctx, const float* e16, const float* e8, int64_t n, float* errmax, hipStream_t s) {
+    if (n <= 0) return MRC_OK;
+    hipLaunchKernelGGL(k_err_max, dim3((unsigned)std::min<int64_t>(ceil_div(n, 256), 1024)), dim3(256), 0, s, e16, e8,
+                       n, errmax);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    return MRC_OK;
+}
+
 int mfma_chunks(int k) {
     const int nc = (int)ceil_div(k, 16);
     for (int c : {2, 4, 6, 8, 12, 16, 24, 32, 48, 64})

@@ -29,6 +29,7 @@ void free_db(mrc_db* db) {
     dev_free(c, db->d_fp8, (size_t)db->cap_pad * L.ld8);
     dev_free(c, db->d_scale, (size_t)db->cap_pad * 4);
     dev_free(c, db->d_err, (size_t)db->cap_pad * 8);
+    dev_free(c, db->d_errmax, 8);
     delete db;
 }
 
@@ -49,6 +50,7 @@ mrc_status alloc_db(mrc_ctx* ctx, int64_t capacity, int32_t k, uint32_t precisio
         st = dev_alloc(ctx, (void**)&db->d_fp8, (size_t)db->cap_pad * L.ld8);
     if (st == MRC_OK) st = dev_alloc(ctx, (void**)&db->d_scale, (size_t)db->cap_pad * 4);
     if (st == MRC_OK) st = dev_alloc(ctx, (void**)&db->d_err, (size_t)db->cap_pad * 8);
+    if (st == MRC_OK) st = dev_alloc(ctx, (void**)&db->d_errmax, 8);
     if (st != MRC_OK) {
         free_db(db);
         return st;
@@ -58,6 +60,7 @@ mrc_status alloc_db(mrc_ctx* ctx, int64_t capacity, int32_t k, uint32_t precisio
     if (e == hipSuccess && db->d_fp8) e = hipMemset(db->d_fp8, 0, (size_t)db->cap_pad * L.ld8);
     if (e == hipSuccess) e = hipMemset(db->d_scale, 0, (size_t)db->cap_pad * 4);
     if (e == hipSuccess) e = hipMemset(db->d_err, 0, (size_t)db->cap_pad * 8);
+    if (e == hipSuccess) e = hipMemset(db->d_errmax, 0, 8);
     if (e != hipSuccess) {
         free_db(db);
         return hip_fail(ctx, e, "database clear", __FILE__, __LINE__);
@@ -85,7 +88,10 @@ mrc_status db_append(mrc_db* db, const float* sig, int64_t n, int64_t first, hip
     NormLayout o{nullptr, 0, db->d_bf16 ? db->d_bf16 + first * L.ldb : nullptr, L.ldb,
                  db->d_fp8 ? db->d_fp8 + first * L.ld8 : nullptr, L.ld8, db->d_scale + first,
                  db->d_err + first, db->cap_pad, db->d_unit + first * L.kp, L.kp, n};
-    return launch_normalise_rows(db->ctx, sig, n, db->k, o, s);
+    MRC_TRY(launch_normalise_rows(db->ctx, sig, n, db->k, o, s));
+    // the queries' rescoring band uses the largest row error, kept up to date here
+    // (before the rows are committed) so that a query never scans the database for it
+    return launch_err_max(db->ctx, db->d_err + first, db->d_err + db->cap_pad + first, n, db->d_errmax, s);
 }
 
 }  // namespace mrc

@@ -11,10 +11,12 @@
 // database. Lists are merged per workgroup in LDS, then per query.
 //
 // FP32 scores are the plain chain (exact). For BF16/FP8 a first pass gives
-// the low-precision 16th score L16; a second pass collects every row whose
-// low-precision score is >= min(L16 - 2 delta, tau - delta) (delta: the
-// largest rescoring band), which provably contains the exact top-16 and all
-// rows >= tau; those candidates are rescored with the FP32 chain.
+// each query's 16 best rows by the low-precision score, and E16, the smallest
+// exact (chain) score among them; a second pass collects every row whose
+// low-precision score is >= min(E16 - delta, tau - delta) (delta: the largest
+// rescoring band), which provably contains the exact top-16 (the exact 16th
+// best is >= E16) and all rows >= tau; those candidates are rescored with the
+// FP32 chain.
 #include <algorithm>
 
 #include "common.h"
@@ -278,14 +280,51 @@ __global__ __launch_bounds__(256) void k_query_merge(const float* __restrict__ p
     if (lane == 0 && n_hits && hits) n_hits[q] = hits[q];
 }
 
-// thr[q] = min(L16[q] - 2 delta, tau - delta)
-__global__ void k_query_thr(const float* __restrict__ l16, int nq, float tau, const float* __restrict__ delta,
+// thr[q] = min(E16[q] - delta, tau - delta)
+__global__ void k_query_thr(const float* __restrict__ e16, int nq, float tau, const float* __restrict__ delta,
                             float* __restrict__ thr) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nq) return;
     const float d = *delta;
-    const float a = l16[q] - 2.f * d;
-    thr[q] = fminf(a, tau - d);
+    thr[q] = fminf(e16[q] - d, tau - d);
+}
+
+// The plain FP32 chain acc = fmaf(q_c, r_c, acc), c = 0..k-1, of a
+// natural-order query row and a database row in the matrix-core layout (each
+// 16-component block stored with its 4x4 sub-blocks transposed): a block is
+// read as four 16-byte loads, then consumed in component order.
+__device__ __forceinline__ float chain_score(const float* __restrict__ qu, const float* __restrict__ dr, int k) {
+    float acc = 0.f;
+    for (int c0 = 0; c0 < k; c0 += 16) {
+        f32x4 blk[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) blk[j] = *(const f32x4*)(dr + c0 + 4 * j);
+        const int m = min(16, k - c0);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            if (c < m) acc = __builtin_fmaf(qu[c0 + c], blk[c & 3][c >> 2], acc);
+    }
+    return acc;
+}
+
+// E16[q]: the exact (chain) score of the 16th best of the query's 16 best rows
+// by the low-precision score (-inf with fewer than 16 rows). The exact 16th
+// best over all rows is at least this, so a row can only enter the exact
+// top 16 if its low-precision score is >= E16 - delta.
+__global__ __launch_bounds__(256) void k_query_e16(const mrc_hit* __restrict__ lp_top, int nq,
+                                                   const float* __restrict__ qunit, int k,
+                                                   const float* __restrict__ db_umfma, int kp,
+                                                   float* __restrict__ e16) {
+    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (q >= nq) return;
+    float v = INFINITY;
+    if (lane < kTop) {
+        const int64_t row = lp_top[(int64_t)q * kTop + lane].id;
+        v = row < 0 ? -INFINITY : chain_score(qunit + (int64_t)q * k, db_umfma + row * kp, k);
+    }
+    for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
+    if (lane == 0) e16[q] = v;
 }
 
 // Exact decisions for the collected candidates of each query (one workgroup
@@ -319,9 +358,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
     for (int e = threadIdx.x; e < nc; e += 256) {
         const int64_t pk = cand[(int64_t)q * cap + e];
         const int row = (int)(pk >> 32);
-        const float* dr = db_umfma + (int64_t)row * kp;
-        float acc = 0.f;
-        for (int c = 0; c < k; ++c) acc = __builtin_fmaf(qu[c], dr[mrc_dev::mfma_col(c)], acc);
+        const float acc = chain_score(qu, db_umfma + (int64_t)row * kp, k);
         hits += acc >= tau ? 1 : 0;
         if (better(acc, row, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, acc, row);
     }
@@ -378,11 +415,12 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
     }
 }
 
-__global__ void k_max_err(const float* __restrict__ e1, int64_t n1, const float* __restrict__ e2, int64_t n2,
+// delta = the largest rescoring band between the database rows (db_max: their
+// largest error bound, kept at insert) and the queries' rows e2[0..n2).
+__global__ void k_max_err(const float* __restrict__ db_max, const float* __restrict__ e2, int64_t n2,
                           float nominal, float acc_unit, float* __restrict__ delta) {
     __shared__ float red[16];
-    float m = 0.f;
-    for (int64_t i = threadIdx.x; i < n1; i += 1024) m = fmaxf(m, e1[i]);
+    float m = *db_max;
     for (int64_t i = threadIdx.x; i < n2; i += 1024) m = fmaxf(m, e2[i]);
     m = mrc_dev::wave_max(m);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
@@ -502,10 +540,11 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
                        (const int32_t*)pi, gx, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
                        (int32_t*)nullptr, (float*)l16);
-    const float* db_err = db->d_err + (bf ? 0 : db->cap_pad);
     const float* q_err = (const float*)qerr + (bf ? 0 : nq_pad);
-    hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db_err, rows, q_err, nq, 0.02f,
+    hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db->d_errmax + (bf ? 0 : 1), q_err, nq, 0.02f,
                        lowp_acc_unit(precision, k), (float*)delta);
+    hipLaunchKernelGGL(k_query_e16, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const mrc_hit*)mtop, (int)nq,
+                       (const float*)unit, k, db->d_unit, L.kp, (float*)l16);
     hipLaunchKernelGGL(k_query_thr, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s, (const float*)l16, (int)nq,
                        tau, (const float*)delta, (float*)thr);
     MRC_HIP_TRY(ctx, hipGetLastError());
