@@ -57,8 +57,11 @@ int Scheduler::poll(uint64_t ticket, Result* out, int wait_ms) {
     }
 }
 
-// Take requests of the head's kind, in arrival order, while the batch stays
-// within max_batch, max_batch_tokens and the memory cap. Called with mu_ held.
+// Take requests of the head's kind, in arrival order (requests of the other
+// kind are passed over, and stay at the front for the next batch), while the
+// batch stays within max_batch, max_batch_tokens and the memory cap. The
+// oldest request always goes in the next batch, so neither kind starves; a
+// query sees the rows committed before its batch starts. Called with mu_ held.
 bool Scheduler::form_batch(std::unique_lock<std::mutex>& lk, Batch* b) {
     (void)lk;
     b->reqs.clear();
@@ -68,21 +71,31 @@ bool Scheduler::form_batch(std::unique_lock<std::mutex>& lk, Batch* b) {
     b->kind = queue_.front().kind;
     int64_t n = 0, toks = 0;
     size_t bytes = 0;
-    for (const Request& r : queue_) {
-        if (r.kind != b->kind || n >= opt_.max_batch) break;
+    std::vector<size_t> take;
+    for (size_t i = 0; i < queue_.size() && n < opt_.max_batch; ++i) {
+        const Request& r = queue_[i];
+        if (r.kind != b->kind) continue;
         const int64_t t2 = toks + (int64_t)r.tokens.size();
         if (n > 0 && t2 > opt_.max_batch_tokens) break;
         const size_t by = ex_->batch_bytes(b->kind, n + 1, t2);
         if (in_flight_bytes_ + by > opt_.mem_cap) break;
+        take.push_back(i);
         ++n;
         toks = t2;
         bytes = by;
     }
     if (n == 0) return false;
-    for (int64_t i = 0; i < n; ++i) {
-        b->reqs.push_back(std::move(queue_.front()));
-        queue_.pop_front();
+    std::deque<Request> rest;
+    size_t t = 0;
+    for (size_t i = 0; i < queue_.size(); ++i) {
+        if (t < take.size() && take[t] == i) {
+            b->reqs.push_back(std::move(queue_[i]));
+            ++t;
+        } else {
+            rest.push_back(std::move(queue_[i]));
+        }
     }
+    queue_.swap(rest);
     b->tokens = toks;
     b->bytes = bytes;
     return true;

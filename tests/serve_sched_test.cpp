@@ -78,6 +78,36 @@ static void test_basic_and_fifo() {
     std::printf("OK basic_fifo_batches batches=%d\n", ex.batches.load());
 }
 
+static void test_mixed_kinds_batch_together() {
+    // one slot kept busy by a first request while 64 alternating inserts and
+    // queries queue up: they must leave in two batches of 32 (one per kind),
+    // each in arrival order, not in 64 batches of one
+    Fake ex(1, 20000, 1);
+    Options o;
+    o.max_batch = 64;
+    o.max_wait_us = 0;
+    Scheduler s(&ex, o);
+    std::vector<int32_t> tok(10, 1);
+    uint64_t first;
+    CHECK(s.submit(tok.data(), 5, kQuery, &first) == kOk);
+    std::this_thread::sleep_for(std::chrono::milliseconds(5));   // the slot picks it up
+    std::vector<uint64_t> t;
+    for (int i = 0; i < 64; ++i) {
+        uint64_t k;
+        CHECK(s.submit(tok.data(), 1 + i % 9, i % 2 ? kQuery : kInsert, &k) == kOk);
+        t.push_back(k);
+    }
+    for (int i = 0; i < 64; ++i) {
+        Result r;
+        CHECK(s.poll(t[i], &r, 10000) == kOk && r.status == kOk);
+        CHECK(r.kind == (i % 2 ? kQuery : kInsert) && r.n_hits == 1 + i % 9);
+    }
+    Result r;
+    CHECK(s.poll(first, &r, 10000) == kOk);
+    CHECK(ex.order_ok.load() && ex.max_batch_seen.load() == 32 && ex.batches.load() == 3);
+    std::printf("OK mixed_kinds batches=%d\n", ex.batches.load());
+}
+
 static void test_memory_admission() {
     // every token costs 1000 bytes; cap 150000: at most ~150 tokens in flight
     Fake ex(4, 3000, 1000);
@@ -179,6 +209,7 @@ static void test_concurrent_submitters_and_stop() {
 
 int main() {
     test_basic_and_fifo();
+    test_mixed_kinds_batch_together();
     test_memory_admission();
     test_queue_full_and_failures();
     test_concurrent_submitters_and_stop();
