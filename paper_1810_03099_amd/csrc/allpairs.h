@@ -35,12 +35,12 @@ struct PairStage {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(sink.counter, (unsigned long long)n);
         base = __shfl(base, 0, 64);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         for (int e = lane; e < n; e += 64) {
             const int64_t dst = (int64_t)base + e;
             if (dst < sink.capacity) sink.pairs[dst] = buf[e];
         }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         n = 0;
     }
@@ -101,7 +101,7 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
         pos = st.n + incl - cnt;
         st.n += total;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     while (m) {
         const int sl = __ffs(m) - 1;
@@ -115,7 +115,7 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
         }
         ++pos;
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
 }
 

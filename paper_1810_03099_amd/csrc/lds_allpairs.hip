@@ -73,19 +73,6 @@ __device__ __forceinline__ f32x16 mma(const i32x8& a, const i32x8& b, const f32x
 // E8M0 code of a power-of-two float scale (its biased exponent; 0 for 0).
 __device__ __forceinline__ int e8m0(float s) { return (int)((__float_as_uint(s) >> 23) & 0xFFu); }
 
-// Stage the flagged entries of one result slot across the wavefront.
-__device__ __forceinline__ void stage_add(PairStage& st, const PairSink& sink, bool flag, int i, int j, float s) {
-    const unsigned long long m = __ballot(flag);
-    if (m == 0) return;
-    const int cnt = __popcll(m);
-    if (st.n + cnt > kStageB) st.flush(sink);
-    if (flag) {
-        const int r = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        st.buf[st.n + r] = mrc_pair{i, j, s, 0};
-    }
-    st.n += cnt;
-}
-
 template <int V>
 using ic = std::integral_constant<int, V>;
 
@@ -325,24 +312,61 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
         for (int i = 1; i < 16; ++i) mall = fmaxf(mall, mx[i]);
         if (__ballot(mall >= thr) != 0) {
             float* scr = lds.scr[wave];
+            const int c = (lane & 31);
 #pragma unroll
             for (int x = 0; x < 4; ++x)
 #pragma unroll
                 for (int y = 0; y < 4; ++y) {
                     if (__ballot(mx[x * 4 + y] >= thr) == 0) continue;
+                    // park the block, then each lane finds its flagged values
+                    // (row 8 (i / 4) + 4 (l / 32) + i % 4) and reads them back by index
 #pragma unroll
                     for (int i = 0; i < 16; ++i) scr[i * 64 + lane] = acc[x][y][i];
                     __builtin_amdgcn_sched_barrier(0);
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
-#pragma nounroll
+                    const int rb = row0 + x * 32 + 4 * (lane >> 5), cc = col0 + y * 32 + c;
+                    uint32_t m = 0;
+#pragma unroll
                     for (int i = 0; i < 16; ++i) {
-                        const float v = scr[i * 64 + lane];
-                        const int r = row0 + x * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
-                        const int c = col0 + y * 32 + (lane & 31);
-                        stage_add(st, cand, v >= thr && r < c && c < n, r, c, v);
+                        const int r = rb + 8 * (i >> 2) + (i & 3);
+                        m |= (scr[i * 64 + lane] >= thr && r < cc && cc < n ? 1u : 0u) << i;
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                    const int cnt = __popc(m);
+                    int incl = cnt;
+#pragma unroll
+                    for (int off = 1; off < 64; off <<= 1) {
+                        const int u = __shfl_up(incl, off, 64);
+                        if (lane >= off) incl += u;
+                    }
+                    const int total = __shfl(incl, 63, 64);
+                    if (total == 0) continue;
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (st.n + total > kStageB) st.flush(cand);
+                    const bool direct = total > kStageB;  // more than a stage: straight to the output
+                    int64_t pos;
+                    if (direct) {
+                        unsigned long long base = 0;
+                        if (lane == 0) base = atomicAdd(cand.counter, (unsigned long long)total);
+                        pos = (int64_t)__shfl(base, 0, 64) + incl - cnt;
+                    } else {
+                        pos = st.n + incl - cnt;
+                        st.n += total;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    while (m) {
+                        const int i = __ffs(m) - 1;
+                        m &= m - 1;
+                        const mrc_pair pr{rb + 8 * (i >> 2) + (i & 3), cc, scr[i * 64 + lane], 0};
+                        if (direct) {
+                            if (pos < cand.capacity) cand.pairs[pos] = pr;
+                        } else {
+                            st.buf[pos] = pr;
+                        }
+                        ++pos;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                 }
         }
