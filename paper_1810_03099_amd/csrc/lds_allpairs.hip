@@ -188,6 +188,18 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
     read_step(ic<0>{}, 0, fa[0], fb[0]);
 
     f32x16 acc[4][4];
+    float mx[16];  // largest score of each 32x32 block of the finished tile
+    // three-input maxima: 16 values in 8 instructions
+    auto tree = [&](int x, int y) __attribute__((always_inline)) {
+        float m0 = fmaxf(fmaxf(acc[x][y][0], acc[x][y][1]), acc[x][y][2]);
+        float m1 = fmaxf(fmaxf(acc[x][y][3], acc[x][y][4]), acc[x][y][5]);
+        float m2 = fmaxf(fmaxf(acc[x][y][6], acc[x][y][7]), acc[x][y][8]);
+        float m3 = fmaxf(fmaxf(acc[x][y][9], acc[x][y][10]), acc[x][y][11]);
+        float m4 = fmaxf(fmaxf(acc[x][y][12], acc[x][y][13]), acc[x][y][14]);
+        m0 = fmaxf(fmaxf(m0, m1), acc[x][y][15]);
+        m2 = fmaxf(fmaxf(m2, m3), m4);
+        return fmaxf(m0, m2);
+    };
     // One chunk in buffer b. The loads of the following chunk (of this block
     // pair, or the first of the next pair) go to the other buffer, one after
     // each product of the first step; the reads of step s + 1 are issued
@@ -196,8 +208,9 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
     // barrier that makes that chunk visible. FP8 fragments are twice as wide:
     // there the A fragments have one buffer, fragment x of the next step read
     // right after the four products that use fragment x of this one.
-    auto chunk = [&](auto bc, int kc, bool more, __amdgpu_buffer_rsrc_t nqa, __amdgpu_buffer_rsrc_t nqb)
+    auto chunk = [&](auto bc, int kc, bool more, __amdgpu_buffer_rsrc_t nqa, __amdgpu_buffer_rsrc_t nqb, auto lc)
         __attribute__((always_inline)) {
+        constexpr bool lastc = decltype(lc)::value;  // the block pair's last chunk
         constexpr int b = decltype(bc)::value;
         const bool next_here = kc + 1 < NKC;
         // what the loads fetch: the next chunk of this pair, else the first of
@@ -231,7 +244,26 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
                 }
             }
             __builtin_amdgcn_sched_barrier(0);
-            if constexpr (kFp8) {
+            if (lastc && s + 1 == F::kSteps) {
+                // last products of the block pair: the max tree of block j - 4
+                // goes in after the product of block j (its last product, four
+                // products back, has finished), the last four after the loop
+                const auto& fa_s = kFp8 ? fa[0] : fa[s & 1];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    acc[j >> 2][j & 3] = mma(fa_s[j >> 2], fb[s & 1][j & 3], acc[j >> 2][j & 3], sa[j >> 2], sb[j & 3]);
+                    if (j >= 4) mx[j - 4] = tree((j - 4) >> 2, (j - 4) & 3);
+                }
+#pragma unroll
+                for (int j = 12; j < 16; ++j) mx[j] = tree(j >> 2, j & 3);
+                __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+#pragma unroll
+                for (int g = 0; g < 12; ++g) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x002, 24, 0);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            } else if constexpr (kFp8) {
 #pragma unroll
                 for (int x = 0; x < 4; ++x) {
                     if (s == 0) {
@@ -284,29 +316,18 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
             for (int y = 0; y < 4; ++y) acc[x][y] = f32x16{};
         int kc = 0;
 #pragma unroll
-        for (; kc + 2 <= NKC; kc += 2) {
-            chunk(ic<P>{}, kc, more, nqa, nqb);
-            chunk(ic<P ^ 1>{}, kc + 1, more, nqa, nqb);
+        for (; kc + 2 < NKC; kc += 2) {
+            chunk(ic<P>{}, kc, more, nqa, nqb, std::false_type{});
+            chunk(ic<P ^ 1>{}, kc + 1, more, nqa, nqb, std::false_type{});
         }
-        if (NKC & 1) chunk(ic<P>{}, kc, more, nqa, nqb);
-        // ---- candidates of this wavefront's 128x128 quarter
+        if constexpr ((NKC & 1) != 0) {
+            chunk(ic<P>{}, kc, more, nqa, nqb, std::true_type{});
+        } else {
+            chunk(ic<P>{}, kc, more, nqa, nqb, std::false_type{});
+            chunk(ic<P ^ 1>{}, kc + 1, more, nqa, nqb, std::true_type{});
+        }
+        // ---- candidates of this wavefront's 128x128 quarter (mx: from the last chunk)
         const int row0 = bi * kBM + wr * 128, col0 = bj * kBM + wc * 128;
-        float mx[16];
-#pragma unroll
-        for (int x = 0; x < 4; ++x)
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                // three-input maxima: 16 values in 8 instructions
-                float m0 = fmaxf(fmaxf(acc[x][y][0], acc[x][y][1]), acc[x][y][2]);
-                float m1 = fmaxf(fmaxf(acc[x][y][3], acc[x][y][4]), acc[x][y][5]);
-                float m2 = fmaxf(fmaxf(acc[x][y][6], acc[x][y][7]), acc[x][y][8]);
-                float m3 = fmaxf(fmaxf(acc[x][y][9], acc[x][y][10]), acc[x][y][11]);
-                float m4 = fmaxf(fmaxf(acc[x][y][12], acc[x][y][13]), acc[x][y][14]);
-                m0 = fmaxf(fmaxf(m0, m1), acc[x][y][15]);
-                m2 = fmaxf(fmaxf(m2, m3), m4);
-                mx[x * 4 + y] = fmaxf(m0, m2);
-                __builtin_amdgcn_sched_barrier(0);
-            }
         float mall = mx[0];
 #pragma unroll
         for (int i = 1; i < 16; ++i) mall = fmaxf(mall, mx[i]);
