@@ -332,6 +332,15 @@ mrc_status mrc_serve_start(mrc_ctx* ctx, mrc_db* db, const mrc_model* model,
 /* Submit one document (host int32 tokens, copied before return). */
 mrc_status mrc_serve_submit(mrc_server* srv, const int32_t* tokens, int64_t len, int32_t kind,
                             uint64_t* ticket);
+/* Submit n documents in one call (a front end that receives several at once):
+ * host CSR arrays, document i being tokens[offsets[i], offsets[i + 1]), int64
+ * offsets[n + 1], int32 tokens; all copied before return. They are queued in
+ * order while the queue has room; *n_accepted (always written) says how many
+ * went in, and tickets[0, *n_accepted) are theirs. Returns MRC_OK when all
+ * were queued, MRC_E_BUSY when the queue filled first, MRC_E_INVAL (nothing
+ * queued) for bad offsets or a token id outside [0, vocab). */
+mrc_status mrc_serve_submit_many(mrc_server* srv, const int64_t* offsets, const int32_t* tokens, int64_t n,
+                                 int32_t kind, uint64_t* tickets, int64_t* n_accepted);
 /* Fetch a result: MRC_OK with the result when done, MRC_E_BUSY while pending,
  * MRC_E_INVAL for an unknown ticket. wait_ms > 0 blocks up to that long. */
 mrc_status mrc_serve_poll(mrc_server* srv, uint64_t ticket, mrc_result* out, int32_t wait_ms);

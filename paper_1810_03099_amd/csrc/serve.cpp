@@ -213,6 +213,25 @@ mrc_status mrc_serve_submit(mrc_server* srv, const int32_t* tokens, int64_t len,
     return MRC_OK;
 }
 
+mrc_status mrc_serve_submit_many(mrc_server* srv, const int64_t* offsets, const int32_t* tokens, int64_t n,
+                                 int32_t kind, uint64_t* tickets, int64_t* n_accepted) {
+    if (!n_accepted) return fail(MRC_E_INVAL, "mrc_serve_submit_many: NULL n_accepted");
+    *n_accepted = 0;
+    if (!srv || n < 0 || (n > 0 && (!offsets || !tickets)))
+        return fail(MRC_E_INVAL, "mrc_serve_submit_many: bad argument");
+    if (n > 0 && offsets[0] < 0) return fail(MRC_E_INVAL, "mrc_serve_submit_many: negative offset");
+    for (int64_t d = 0; d < n; ++d) {
+        if (offsets[d + 1] < offsets[d]) return fail(MRC_E_INVAL, "mrc_serve_submit_many: offsets decrease");
+        for (int64_t i = offsets[d]; i < offsets[d + 1]; ++i)
+            if (tokens[i] < 0 || tokens[i] >= srv->vocab)
+                return fail(MRC_E_INVAL, "mrc_serve_submit_many: token id outside [0, vocab)");
+    }
+    const int rc = srv->sched->submit_many(offsets, tokens, n, kind, tickets, n_accepted);
+    if (rc == mrc_serve::kBusy) return fail(MRC_E_BUSY, "mrc_serve_submit_many: queue full");
+    if (rc != mrc_serve::kOk) return fail(rc, "mrc_serve_submit_many: rejected");
+    return MRC_OK;
+}
+
 mrc_status mrc_serve_poll(mrc_server* srv, uint64_t ticket, mrc_result* out, int32_t wait_ms) {
     if (!srv || !out) return fail(MRC_E_INVAL, "mrc_serve_poll: NULL argument");
     mrc_serve::Result r;

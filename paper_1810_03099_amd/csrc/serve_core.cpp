@@ -39,6 +39,36 @@ int Scheduler::submit(const int32_t* tokens, int64_t len, int kind, uint64_t* ti
     return kOk;
 }
 
+int Scheduler::submit_many(const int64_t* offsets, const int32_t* tokens, int64_t n, int kind, uint64_t* tickets,
+                           int64_t* accepted) {
+    if (!accepted) return kInval;
+    *accepted = 0;
+    if (n < 0 || (n > 0 && (!offsets || !tickets)) || (kind != kQuery && kind != kInsert)) return kInval;
+    for (int64_t i = 0; i < n; ++i)
+        if (offsets[i + 1] < offsets[i] || (offsets[i + 1] > offsets[i] && !tokens)) return kInval;
+    std::vector<Request> rs((size_t)n);
+    for (int64_t i = 0; i < n; ++i) {
+        rs[i].kind = kind;
+        rs[i].tokens.assign(tokens + offsets[i], tokens + offsets[i + 1]);
+    }
+    std::lock_guard<std::mutex> g(mu_);
+    if (stopping_) return kState;
+    int64_t i = 0;
+    for (; i < n && (int)queue_.size() < opt_.max_queue; ++i) {
+        Request& r = rs[i];
+        r.ticket = next_ticket_++;
+        r.t_submit = now_ms();
+        tickets[i] = r.ticket;
+        pending_[r.ticket] = true;
+        queue_.push_back(std::move(r));
+        ++st_.submitted;
+    }
+    *accepted = i;
+    st_.rejected += (uint64_t)(n - i);
+    if (i) cv_work_.notify_all();
+    return i == n ? kOk : kBusy;
+}
+
 int Scheduler::poll(uint64_t ticket, Result* out, int wait_ms) {
     std::unique_lock<std::mutex> lk(mu_);
     auto deadline = std::chrono::steady_clock::now() + std::chrono::milliseconds(std::max(0, wait_ms));
@@ -85,17 +115,22 @@ bool Scheduler::form_batch(std::unique_lock<std::mutex>& lk, Batch* b) {
         bytes = by;
     }
     if (n == 0) return false;
-    std::deque<Request> rest;
+    // only the prefix up to the last request taken changes: the skipped
+    // requests of other kinds in it go back to the front in their order
+    const size_t end = take.back() + 1;
+    std::vector<Request> skipped;
+    skipped.reserve(end - take.size());
     size_t t = 0;
-    for (size_t i = 0; i < queue_.size(); ++i) {
+    for (size_t i = 0; i < end; ++i) {
         if (t < take.size() && take[t] == i) {
             b->reqs.push_back(std::move(queue_[i]));
             ++t;
         } else {
-            rest.push_back(std::move(queue_[i]));
+            skipped.push_back(std::move(queue_[i]));
         }
     }
-    queue_.swap(rest);
+    queue_.erase(queue_.begin(), queue_.begin() + (std::ptrdiff_t)end);
+    for (size_t i = skipped.size(); i-- > 0;) queue_.push_front(std::move(skipped[i]));
     b->tokens = toks;
     b->bytes = bytes;
     return true;

@@ -79,6 +79,12 @@ class Scheduler {
     Scheduler(Executor* ex, const Options& o);
     ~Scheduler();
     int submit(const int32_t* tokens, int64_t len, int kind, uint64_t* ticket);
+    // n documents at once (document i is tokens[offsets[i], offsets[i + 1])),
+    // queued in order under one lock while the queue has room: *accepted of
+    // them go in, with tickets[0, *accepted). kOk when all did, kBusy when the
+    // queue filled first.
+    int submit_many(const int64_t* offsets, const int32_t* tokens, int64_t n, int kind, uint64_t* tickets,
+                    int64_t* accepted);
     // kOk with the result (removed from the table), kBusy while pending,
     // kInval for an unknown ticket. wait_ms > 0 blocks up to that long.
     int poll(uint64_t ticket, Result* out, int wait_ms);

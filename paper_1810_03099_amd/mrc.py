@@ -37,7 +37,7 @@ EXPORTS = (
     "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_compare", "mrc_normalise", "mrc_score_pairs",
     "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
     "mrc_db_destroy", "mrc_db_insert", "mrc_db_insert_docs", "mrc_db_size", "mrc_db_save", "mrc_db_load",
-    "mrc_query", "mrc_serve_start", "mrc_serve_submit", "mrc_serve_poll", "mrc_serve_stop",
+    "mrc_query", "mrc_serve_start", "mrc_serve_submit", "mrc_serve_submit_many", "mrc_serve_poll", "mrc_serve_stop",
 )
 
 
@@ -130,6 +130,7 @@ _SIGS = {
     "mrc_query": [_P, _P, _P, C.POINTER(MrcDocs), C.c_int32, C.c_float, C.c_int32, _P, _P, _P],
     "mrc_serve_start": [_P, _P, _P, C.POINTER(MrcServeOpts), C.POINTER(_P)],
     "mrc_serve_submit": [_P, _P, C.c_int64, C.c_int32, C.POINTER(C.c_uint64)],
+    "mrc_serve_submit_many": [_P, _P, _P, C.c_int64, C.c_int32, _P, C.POINTER(C.c_int64)],
     "mrc_serve_poll": [_P, C.c_uint64, C.POINTER(MrcResult), C.c_int32],
     "mrc_serve_stop": [_P],
 }
@@ -510,6 +511,21 @@ def mrc_serve_submit(srv, tokens: np.ndarray, kind=REQ_QUERY):
         return None
     _check(st, "mrc_serve_submit")
     return ticket.value
+
+
+def mrc_serve_submit_many(srv, offsets: np.ndarray, tokens: np.ndarray, kind=REQ_QUERY):
+    """Submit len(offsets) - 1 documents (host CSR arrays) in one call; returns
+    the tickets of those queued (fewer than asked when the queue filled)."""
+    o = np.ascontiguousarray(offsets, dtype=np.int64)
+    t = np.ascontiguousarray(tokens, dtype=np.int32)
+    n = max(int(o.size) - 1, 0)
+    tickets = np.zeros(max(n, 1), dtype=np.uint64)
+    acc = C.c_int64(0)
+    st = lib().mrc_serve_submit_many(srv, o.ctypes.data if o.size else None, t.ctypes.data if t.size else None, n,
+                                     int(kind), tickets.ctypes.data, C.byref(acc))
+    if st != MRC_E_BUSY:
+        _check(st, "mrc_serve_submit_many")
+    return tickets[:acc.value].tolist()
 
 
 def mrc_serve_poll(srv, ticket, wait_ms=0):

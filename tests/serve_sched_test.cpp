@@ -108,6 +108,49 @@ static void test_mixed_kinds_batch_together() {
     std::printf("OK mixed_kinds batches=%d\n", ex.batches.load());
 }
 
+static void test_submit_many() {
+    // CSR submission: tickets in order, one result per document; a full queue
+    // takes a prefix; bad offsets queue nothing
+    Fake ex(1, 3000, 1);
+    Options o;
+    o.max_batch = 16;
+    o.max_queue = 40;
+    o.max_wait_us = 0;
+    Scheduler s(&ex, o);
+    std::vector<int64_t> off(1, 0);
+    std::vector<int32_t> tok;
+    for (int d = 0; d < 64; ++d) {
+        for (int j = 0; j < d % 11; ++j) tok.push_back(d);
+        off.push_back((int64_t)tok.size());
+    }
+    std::vector<uint64_t> t(64);
+    int64_t acc = -1;
+    CHECK(s.submit_many(off.data(), tok.data(), 30, kQuery, t.data(), &acc) == kOk && acc == 30);
+    for (int d = 1; d < 30; ++d) CHECK(t[d] == t[d - 1] + 1);
+    for (int d = 0; d < 30; ++d) {
+        Result r;
+        CHECK(s.poll(t[d], &r, 10000) == kOk && r.status == kOk && r.n_hits == d % 11);
+    }
+    // one slot busy with a long first request, then 64 documents into a queue of 40
+    uint64_t first;
+    int32_t one = 1;
+    CHECK(s.submit(&one, 1, kQuery, &first) == kOk);
+    std::this_thread::sleep_for(std::chrono::milliseconds(1));
+    CHECK(s.submit_many(off.data(), tok.data(), 64, kInsert, t.data(), &acc) == kBusy);
+    CHECK(acc >= 39 && acc < 64);
+    for (int64_t d = 0; d < acc; ++d) {
+        Result r;
+        CHECK(s.poll(t[d], &r, 10000) == kOk && r.status == kOk && r.kind == kInsert && r.n_hits == d % 11);
+    }
+    Result r;
+    CHECK(s.poll(first, &r, 10000) == kOk);
+    std::vector<int64_t> bad = {0, 3, 2, 5};
+    CHECK(s.submit_many(bad.data(), tok.data(), 3, kQuery, t.data(), &acc) == kInval && acc == 0);
+    CHECK(s.submit_many(off.data(), tok.data(), 2, 9, t.data(), &acc) == kInval && acc == 0);
+    CHECK(s.submit_many(off.data(), tok.data(), 0, kQuery, t.data(), &acc) == kOk && acc == 0);
+    std::printf("OK submit_many accepted_of_64=%ld\n", (long)acc);
+}
+
 static void test_memory_admission() {
     // every token costs 1000 bytes; cap 150000: at most ~150 tokens in flight
     Fake ex(4, 3000, 1000);
@@ -210,6 +253,7 @@ static void test_concurrent_submitters_and_stop() {
 int main() {
     test_basic_and_fifo();
     test_mixed_kinds_batch_together();
+    test_submit_many();
     test_memory_admission();
     test_queue_full_and_failures();
     test_concurrent_submitters_and_stop();

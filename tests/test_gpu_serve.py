@@ -116,3 +116,28 @@ def test_admission_refuses_over_cap(lib, env):
     with pytest.raises(lib.MrcError):
         lib.mrc_serve_submit(srv, np.array([env["dbc"].vocab + 5], np.int32))
     lib.mrc_serve_stop(srv)
+
+
+def test_submit_many_equals_alone(lib, env):
+    # all queries in one CSR call: each result equals the query run alone
+    qc = env["qc"]
+    srv = lib.mrc_serve_start(env["ctx"], env["db"], env["model"], max_batch=64, n_streams=2, topk=16, tau=TAU,
+                              precision=lib.PREC_BF16, max_wait_us=300)
+    tickets = lib.mrc_serve_submit_many(srv, qc.offsets, qc.tokens)
+    assert len(tickets) == qc.n_docs and tickets == sorted(tickets)
+    for i, tk in enumerate(tickets):
+        r = lib.mrc_serve_poll(srv, tk, wait_ms=60000)
+        assert r is not None and r.status == 0 and r.kind == lib.REQ_QUERY
+        ids, sc, hits = alone(lib, env, qc.doc(i), lib.PREC_FP32)
+        valid = ids >= 0
+        np.testing.assert_array_equal(np.array([r.top[p].id for p in range(r.n_top)]), ids[valid])
+        np.testing.assert_array_equal(np.array([r.top[p].s for p in range(r.n_top)], np.float32).view(np.uint32),
+                                      sc[valid].view(np.uint32))
+        assert r.n_hits == hits
+    # a token id outside the vocabulary anywhere rejects the whole call (host check)
+    bad_tok = qc.tokens[: int(qc.offsets[3])].copy()
+    bad_tok[-1] = env["dbc"].vocab
+    with pytest.raises(lib.MrcError):
+        lib.mrc_serve_submit_many(srv, qc.offsets[:4], bad_tok)
+    lib.mrc_serve_stop(srv)
+    flush(f"  submit_many: {qc.n_docs} queries in one call == alone")
