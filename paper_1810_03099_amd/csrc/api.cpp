@@ -63,10 +63,26 @@ size_t model_layout(size_t V, size_t k, size_t off[7]) {
     return total;
 }
 
+// The context keeps the table block of one destroyed model for the next build
+// of the same size, so that rebuilding a model costs no device allocation or
+// free. The kept block still counts against the budget; the context frees it
+// when a build of another size needs the room, and on destroy. Callers
+// synchronise the device before handing a block back.
 void free_model(mrc_model* m) {
     if (!m) return;
     mrc_ctx* c = m->ctx;
-    dev_free(c, m->d_df, m->bytes);
+    void* old = nullptr;
+    size_t old_bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(c->mu);
+        if (m->d_df) {
+            old = c->model_spare;
+            old_bytes = c->model_spare_bytes;
+            c->model_spare = m->d_df;
+            c->model_spare_bytes = m->bytes;
+        }
+    }
+    dev_free(c, old, old_bytes);
     dev_free(c, m->d_hash, (size_t)m->vocab * 8);
     delete m;
 }
@@ -79,7 +95,22 @@ mrc_status alloc_model(mrc_ctx* ctx, int32_t V, int32_t k, mrc_model** out) {
     size_t off[7];
     m->bytes = model_layout((size_t)V, (size_t)k, off);
     char* base = nullptr;
-    const mrc_status st = dev_alloc(ctx, (void**)&base, m->bytes);
+    void* spare = nullptr;
+    size_t spare_bytes = 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        spare = ctx->model_spare;
+        spare_bytes = ctx->model_spare_bytes;
+        ctx->model_spare = nullptr;
+        ctx->model_spare_bytes = 0;
+    }
+    mrc_status st = MRC_OK;
+    if (spare && spare_bytes == m->bytes) {
+        base = (char*)spare;
+    } else {
+        dev_free(ctx, spare, spare_bytes);
+        st = dev_alloc(ctx, (void**)&base, m->bytes);
+    }
     if (st != MRC_OK) {
         delete m;
         return st;

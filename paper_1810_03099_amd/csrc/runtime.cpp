@@ -209,6 +209,7 @@ mrc_status mrc_ctx_destroy(mrc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     timer_collect(ctx);
     for (auto& kv : ctx->scratch) (void)hipFree(kv.second.first);
+    if (ctx->model_spare) (void)hipFree(ctx->model_spare);
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);
     if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);

@@ -67,6 +67,23 @@ def test_build_and_sign_match_oracle(lib, ctx, cfg, n_docs, k):
     np.testing.assert_allclose(norm, onorm, rtol=2e-6)
 
 
+def test_rebuild_reuses_tables_without_stale_values(lib, ctx):
+    # a destroyed model's device block is kept for the next build of the same
+    # size: a model built into it must equal the oracle's, and one of another
+    # size must still build correctly after it
+    a = synth.generate(0, n_docs=1500, seed=11)
+    b = synth.generate(0, n_docs=900, seed=12)
+    for c in (a, b, a):
+        gm, omodel, sig, _, osig, _ = _run(lib, ctx, c, 16)
+        _check_model(lib, gm, omodel, c.vocab)
+        assert np.abs(sig - osig).max() <= SIG_TOL
+        gm.close()
+    c = synth.generate(1, n_docs=700)
+    gm, omodel, sig, _, osig, _ = _run(lib, ctx, c, 64)
+    _check_model(lib, gm, omodel, c.vocab)
+    assert np.abs(sig - osig).max() <= SIG_TOL
+
+
 @pytest.mark.parametrize("mode,kw", [
     (om.SEL_ALL, {}),
     (om.SEL_REGION, {"lo": 100, "hi": 2100}),
