@@ -126,8 +126,8 @@ struct PassArgs {
     int ref_idf;       // 1: rho_t = idf_t, so c_t = idf^2
     float* sig;
     float* norm;
-    // COUNT: distinct terms and counts of document d at [off[d], off[d] + nnz[d]);
-    // the document's remaining slots up to off[d + 1] hold term -1
+    // COUNT: distinct terms and counts of document d at [off[d], off[d] + nnz[d])
+    // (the document's remaining slots up to off[d + 1] are not written)
     int32_t* cnt_term;
     int32_t* cnt_tf;
     int32_t* cnt_nnz;
@@ -340,7 +340,6 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
                 const int sl = used[u];
                 emit_term<MODE_COUNT>(a, d, o, keys[sl], (unsigned)cnt[sl], 0.0, u, nullptr);
             }
-            for (int u = nu + tid; u < L; u += TEAM) a.cnt_term[o + u] = kEmpty;  // unused slots
             if (tid == 0) a.cnt_nnz[d] = nu;
         } else if constexpr (MODE == MODE_CSR) {
             int* tcount = (int*)red;
@@ -436,9 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
             }
             __syncthreads();
             if constexpr (MODE == MODE_COUNT) {
-                const int nu = *tcount;
-                for (int64_t u = nu + tid; u < L; u += kBlock) a.cnt_term[o + u] = kEmpty;  // unused slots
-                if (tid == 0) a.cnt_nnz[d] = nu;
+                if (tid == 0) a.cnt_nnz[d] = *tcount;
             } else {
                 if (tid == 0) a.nnz_tail[d] = *tcount;
             }
@@ -457,35 +454,71 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
 
 // ------------------------------------------------------------ df from counts
 
-// One workgroup per (vocabulary slice, document range): the distinct terms
-// listed in the range's token slots (slots holding -1 are unused) that fall
-// inside the slice are counted in LDS, two 16-bit counters per word (a term
-// is listed at most once per document and a range holds at most 65535
+// One workgroup per (vocabulary slice, document range): the distinct terms of
+// the range's documents (entries [off[d], off[d] + nnz[d]) of the count lists)
+// that fall inside the slice are counted in LDS, two 16-bit counters per word
+// (a term is listed at most once per document and a range holds at most 65535
 // documents), and the slice's counts are written to partial[range][...].
+// One wavefront per document: the entries of its next document and the list
+// bounds of the one after are requested before the current one is counted, so
+// the load latency overlaps the LDS atomics.
 constexpr int kHistThreads = 1024;
+constexpr int kHistPer = 8;  // entries per lane and pass (512 per wavefront pass: one pass for most documents)
 __global__ __launch_bounds__(kHistThreads) void k_df_hist(const int64_t* __restrict__ off, int64_t n,
-                                                          const int32_t* __restrict__ term, int groups,
+                                                          const int32_t* __restrict__ term,
+                                                          const int32_t* __restrict__ nnz, int groups,
                                                           uint32_t* __restrict__ partial, int64_t words,
                                                           const unsigned long long* __restrict__ err) {
+    constexpr int U = kHistPer, W = kHistThreads / 64;
     __shared__ uint32_t h[kHistSlice / 2];
     if (pass_disabled(err)) return;
     const int slice = blockIdx.x / groups, g = blockIdx.x % groups;
     const int t0 = slice * kHistSlice;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int i = threadIdx.x; i < kHistSlice / 2; i += kHistThreads) h[i] = 0u;
     __syncthreads();
-    const int64_t e0 = off[n * g / groups], e1 = off[n * (g + 1) / groups];
-    constexpr int U = 8;
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += (int64_t)U * kHistThreads) {
-        int32_t v[U];
+    const int64_t d_lo = n * g / groups, d_hi = n * (g + 1) / groups;
+    // list bounds of document d (past the range: the range's last document, no entries)
+    auto bounds = [&](int64_t d, int64_t& o, int& m) {
+        const int64_t dl = min(d, d_hi - 1);
+        o = off[dl];
+        m = d < d_hi ? nnz[dl] : 0;
+    };
+    // entries e0 .. e0 + 64 U - 1 (-1 past the end)
+    auto load = [&](int64_t o, int m, int e0, int32_t (&v)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t x = e + (int64_t)u * kHistThreads;
-            v[u] = x < e1 ? term[x] : -1;
+            const int e = e0 + u * 64 + lane;
+            v[u] = e < m ? term[o + e] : -1;
         }
+    };
+    auto count = [&](const int32_t (&v)[U]) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const unsigned t = (unsigned)(v[u] - t0);
             if (v[u] >= 0 && t < (unsigned)kHistSlice) atomicAdd(&h[t >> 1], 1u << ((t & 1u) * 16u));
+        }
+    };
+    const int64_t d0 = d_lo + wave;
+    if (d0 < d_hi) {
+        int64_t o_c, o_n, o_nn;
+        int m_c, m_n, m_nn;
+        int32_t v_c[U], v_n[U];
+        bounds(d0, o_c, m_c);
+        bounds(d0 + W, o_n, m_n);
+        load(o_c, m_c, 0, v_c);
+        for (int64_t d = d0; d < d_hi; d += W) {
+            bounds(d + 2 * W, o_nn, m_nn);
+            load(o_n, m_n, 0, v_n);
+            count(v_c);
+            for (int e0 = 64 * U; e0 < m_c; e0 += 64 * U) {  // longer lists (rare)
+                int32_t v_x[U];
+                load(o_c, m_c, e0, v_x);
+                count(v_x);
+            }
+            o_c = o_n, m_c = m_n, o_n = o_nn, m_n = m_nn;
+#pragma unroll
+            for (int u = 0; u < U; ++u) v_c[u] = v_n[u];
         }
     }
     __syncthreads();
@@ -788,7 +821,7 @@ mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* d_
     void* partial = nullptr;
     MRC_TRY(scratch(ctx, "df_partial", (size_t)groups * (size_t)words * sizeof(uint32_t), &partial));
     hipLaunchKernelGGL(k_df_hist, dim3((unsigned)(slices * groups)), dim3(kHistThreads), 0, s, docs->offsets, n,
-                       c.term, (int)groups, (uint32_t*)partial, words, err);
+                       c.term, c.nnz, (int)groups, (uint32_t*)partial, words, err);
     MRC_HIP_TRY(ctx, hipGetLastError());
     hipLaunchKernelGGL(k_df_sum, dim3((unsigned)ceil_div(words, 64)), dim3(256), 0, s, (const uint32_t*)partial,
                        (int)groups, words, V, d_df);
