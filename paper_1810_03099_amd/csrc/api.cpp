@@ -435,7 +435,7 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
         MRC_TRY(clear_words(ctx, ctx->d_flags, 32, s));
         NormLayout o{(float*)unit, k, prec == MRC_PREC_BF16 ? (uint16_t*)q : nullptr, ldq,
                      prec == MRC_PREC_FP8 ? (uint8_t*)q : nullptr, ldq, (float*)scale, (float*)err, n_pad,
-                     nullptr, 0, n_pad};
+                     nullptr, 0, n_pad, 0, prec == MRC_PREC_BF16 ? 1 : 2};
         MRC_TRY(launch_normalise_rows(ctx, sig, n, k, o, s));
         const float* err_p = (const float*)err + (prec == MRC_PREC_BF16 ? 0 : n_pad);
         float* d_lo = (float*)(ctx->d_flags + 22);

@@ -232,6 +232,7 @@ struct NormLayout {
     float* umfma;     int ld_mfma;
     int64_t n_pad;
     int frag = 0;
+    int errs = 3;     // row errors formed: bit 0 BF16, bit 1 FP8 (the other half of err is 0)
 };
 
 // Offset of component c of row r in the fragment-major FP32 layout with nc

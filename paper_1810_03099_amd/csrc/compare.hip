@@ -120,12 +120,16 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
         const int c = lane + 64 * r;
         if (c >= k) continue;
         const uint16_t b = bf16_rne(v[r]);
-        const double db = (double)v[r] - (double)bf16_value(b);
-        eb += db * db;
+        if (o.errs & 1) {
+            const double db = (double)v[r] - (double)bf16_value(b);
+            eb += db * db;
+        }
         if (o.bf16) o.bf16[row * o.ld_bf16 + c] = b;
         const uint8_t q = sc > 0.f ? e4m3fn_rne(v[r] / sc) : (uint8_t)0;
-        const double d8 = (double)v[r] - (double)e4m3fn_value(q) * (double)sc;
-        e8 += d8 * d8;
+        if (o.errs & 2) {
+            const double d8 = (double)v[r] - (double)e4m3fn_value(q) * (double)sc;
+            e8 += d8 * d8;
+        }
         if (o.fp8) o.fp8[row * o.ld_fp8 + c] = q;
     }
     eb = mrc_dev::wave_sum(eb);
@@ -134,6 +138,157 @@ __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig
         if (o.scale) o.scale[row] = sc;
         if (o.err) {
             // round the float64 norms up to float so the stored value bounds the error
+            float fb = (float)sqrt(eb), f8 = (float)sqrt(e8);
+            o.err[row] = (double)fb < sqrt(eb) ? nextafterf(fb, INFINITY) : fb;
+            o.err[o.ld_err + row] = (double)f8 < sqrt(e8) ? nextafterf(f8, INFINITY) : f8;
+        }
+    }
+}
+
+// The same quantities for k a multiple of 4, with 16-byte row accesses: LPR
+// lanes per row (64 / LPR rows per wavefront), lane li holding the float4
+// groups c = 4 (li + LPR q), q < VPL, of its row. The results depend on k
+// alone (not on which accesses can be vector ones: bit b of `wide` says the
+// input (b = 0), unit (1), bf16 (2) and fp8 (3) rows are 16-, 8- or 4-byte
+// aligned accordingly); they are those of k_normalise up to the summation
+// order of |sig|^2.
+template <int LPR>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+template <int LPR>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+template <int LPR>
+__device__ __forceinline__ float group_max(float v) {
+#pragma unroll
+    for (int off = LPR / 2; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <int LPR, int VPL>
+__global__ __launch_bounds__(256) void k_normalise_vec(const float* __restrict__ sig, int64_t n, int k, NormOut o,
+                                                       int wide) {
+    constexpr int RPW = 64 / LPR;
+    const int lane = threadIdx.x & 63, li = lane % LPR;
+    const int64_t row = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + lane / LPR;
+    const bool live = row < n;
+    if (row >= o.n_pad) return;  // (whole row groups: the shuffles below stay within a group)
+    const int nc = o.ld_mfma / 16;
+    auto put_mfma = [&](int c, float x) {
+        o.umfma[o.frag ? frag_offset(row, c, nc) : row * o.ld_mfma + mfma_col(c)] = x;
+    };
+    // padding columns [k, ld) (all columns of padding rows)
+    const int c_pad = live ? k : 0;
+    if (o.unit)
+        for (int c = c_pad + li; c < o.ld_unit; c += LPR) o.unit[row * o.ld_unit + c] = 0.f;
+    if (o.bf16)
+        for (int c = c_pad + li; c < o.ld_bf16; c += LPR) o.bf16[row * o.ld_bf16 + c] = 0;
+    if (o.fp8)
+        for (int c = c_pad + li; c < o.ld_fp8; c += LPR) o.fp8[row * o.ld_fp8 + c] = 0;
+    if (o.umfma)
+        for (int c = c_pad + li; c < o.ld_mfma; c += LPR) put_mfma(c, 0.f);
+    if (!live) {
+        if (li == 0) {
+            if (o.scale) o.scale[row] = 0.f;
+            if (o.err) o.err[row] = o.err[o.ld_err + row] = 0.f;
+        }
+        return;
+    }
+    const float* x = sig + row * k;
+    float4 v[VPL];
+    float s2 = 0.f;
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+        const int c = 4 * (li + LPR * q);
+        if (c >= k) v[q] = float4{0.f, 0.f, 0.f, 0.f};
+        else if (wide & 1) v[q] = *(const float4*)(x + c);
+        else v[q] = float4{x[c], x[c + 1], x[c + 2], x[c + 3]};
+        s2 = fmaf(v[q].x, v[q].x, s2);
+        s2 = fmaf(v[q].y, v[q].y, s2);
+        s2 = fmaf(v[q].z, v[q].z, s2);
+        s2 = fmaf(v[q].w, v[q].w, s2);
+    }
+    const float nrm = sqrtf(group_sum<LPR>(s2));
+    float amax = 0.f;
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+        const int c = 4 * (li + LPR * q);
+        v[q].x = nrm > 0.f ? v[q].x / nrm : 0.f;
+        v[q].y = nrm > 0.f ? v[q].y / nrm : 0.f;
+        v[q].z = nrm > 0.f ? v[q].z / nrm : 0.f;
+        v[q].w = nrm > 0.f ? v[q].w / nrm : 0.f;
+        amax = fmaxf(amax, fmaxf(fmaxf(fabsf(v[q].x), fabsf(v[q].y)), fmaxf(fabsf(v[q].z), fabsf(v[q].w))));
+        if (c < k) {
+            if (o.unit) {
+                float* pu = o.unit + row * o.ld_unit + c;
+                if (wide & 2) {
+                    *(float4*)pu = v[q];
+                } else {
+                    pu[0] = v[q].x, pu[1] = v[q].y, pu[2] = v[q].z, pu[3] = v[q].w;
+                }
+            }
+            if (o.umfma) {
+                put_mfma(c, v[q].x);
+                put_mfma(c + 1, v[q].y);
+                put_mfma(c + 2, v[q].z);
+                put_mfma(c + 3, v[q].w);
+            }
+        }
+    }
+    amax = group_max<LPR>(amax);
+    // smallest power of two >= amax / 448 (see k_normalise); dividing by it is
+    // multiplying by its exact reciprocal
+    float sc = amax / 448.0f;
+    if (__float_as_uint(sc) & 0x007FFFFFu) sc = __uint_as_float((__float_as_uint(sc) & 0x7F800000u) + 0x00800000u);
+    const float inv_sc = sc > 0.f ? 1.0f / sc : 0.f;
+    double eb = 0.0, e8 = 0.0;
+#pragma unroll
+    for (int q = 0; q < VPL; ++q) {
+        const int c = 4 * (li + LPR * q);
+        if (c >= k) continue;
+        const float u4[4] = {v[q].x, v[q].y, v[q].z, v[q].w};
+        uint16_t b[4];
+        uint8_t f8[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            b[j] = bf16_rne(u4[j]);
+            if (o.errs & 1) {
+                const double db = (double)u4[j] - (double)bf16_value(b[j]);
+                eb += db * db;
+            }
+            f8[j] = (o.fp8 || (o.errs & 2)) && sc > 0.f ? e4m3fn_rne(u4[j] * inv_sc) : (uint8_t)0;
+            if (o.errs & 2) {
+                const double d8 = (double)u4[j] - (double)e4m3fn_value(f8[j]) * (double)sc;
+                e8 += d8 * d8;
+            }
+        }
+        if (o.bf16) {
+            uint16_t* pb = o.bf16 + row * o.ld_bf16 + c;
+            if (wide & 4)
+                *(uint2*)pb = uint2{(uint32_t)b[0] | ((uint32_t)b[1] << 16), (uint32_t)b[2] | ((uint32_t)b[3] << 16)};
+            else
+                for (int j = 0; j < 4; ++j) pb[j] = b[j];
+        }
+        if (o.fp8) {
+            uint8_t* p8 = o.fp8 + row * o.ld_fp8 + c;
+            if (wide & 8)
+                *(uint32_t*)p8 =
+                    (uint32_t)f8[0] | ((uint32_t)f8[1] << 8) | ((uint32_t)f8[2] << 16) | ((uint32_t)f8[3] << 24);
+            else
+                for (int j = 0; j < 4; ++j) p8[j] = f8[j];
+        }
+    }
+    eb = group_sum<LPR>(eb);
+    e8 = group_sum<LPR>(e8);
+    if (li == 0) {
+        if (o.scale) o.scale[row] = sc;
+        if (o.err) {
             float fb = (float)sqrt(eb), f8 = (float)sqrt(e8);
             o.err[row] = (double)fb < sqrt(eb) ? nextafterf(fb, INFINITY) : fb;
             o.err[o.ld_err + row] = (double)f8 < sqrt(e8) ? nextafterf(f8, INFINITY) : f8;
@@ -270,7 +425,31 @@ mrc_status launch_normalise_rows(mrc_ctx* ctx, const float* sig, int64_t n, int3
     if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
     if (o.n_pad == 0) return MRC_OK;
     ScopedTimer tm(ctx, "normalise", s);
-    hipLaunchKernelGGL(k_normalise, dim3((unsigned)ceil_div(o.n_pad, 4)), dim3(256), 0, s, sig, n, k, o);
+    // k a multiple of 4: four components per lane, vector accesses where the
+    // rows are aligned for them (the results do not depend on which)
+    auto al = [](const void* p, unsigned a) { return ((uintptr_t)p & (a - 1)) == 0; };
+    const int wide = (al(sig, 16) ? 1 : 0) | (o.unit && al(o.unit, 16) && o.ld_unit % 4 == 0 ? 2 : 0) |
+                     (o.bf16 && al(o.bf16, 8) && o.ld_bf16 % 4 == 0 ? 4 : 0) |
+                     (o.fp8 && al(o.fp8, 4) && o.ld_fp8 % 4 == 0 ? 8 : 0);
+    if (k % 4 == 0) {
+        int lpr = 4;
+        while (lpr < 64 && 4 * lpr < k) lpr *= 2;
+        const int vpl = (int)ceil_div(k, 4 * lpr);
+        const int64_t rows_per_block = 4 * (64 / lpr);
+        const dim3 grid((unsigned)ceil_div(o.n_pad, rows_per_block));
+        switch (lpr * 8 + vpl) {
+#define MRC_NV(L, V)                                                                              \
+    case L * 8 + V:                                                                               \
+        hipLaunchKernelGGL((k_normalise_vec<L, V>), grid, dim3(256), 0, s, sig, n, k, o, wide);   \
+        break;
+            MRC_NV(4, 1) MRC_NV(8, 1) MRC_NV(16, 1) MRC_NV(32, 1) MRC_NV(64, 1) MRC_NV(64, 2) MRC_NV(64, 3)
+            MRC_NV(64, 4)
+#undef MRC_NV
+            default: return fail(MRC_E_INVAL, "normalise: no row shape for this k");
+        }
+    } else {
+        hipLaunchKernelGGL(k_normalise, dim3((unsigned)ceil_div(o.n_pad, 4)), dim3(256), 0, s, sig, n, k, o);
+    }
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }

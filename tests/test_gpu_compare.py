@@ -111,11 +111,14 @@ def test_score_pairs_matches_chain(lib, ctx):
     np.testing.assert_array_equal(out.view(np.uint32), ref.view(np.uint32))
 
 
-def test_quantisers_match_oracle(lib, ctx):
-    c, sig = _signed(lib, ctx, 2, 800, 256)
+@pytest.mark.parametrize("cfg,n,k", [(2, 800, 256), (1, 500, 20), (2, 300, 300), (2, 200, 1024), (1, 300, 18)])
+def test_quantisers_match_oracle(lib, ctx, cfg, n, k):
+    # k a multiple of 4: 4, 8, ..., 64 lanes per row and 1-4 float4 groups per
+    # lane; k = 18: one component per lane
+    c, sig = _signed(lib, ctx, cfg, n, k)
     q = lib.mrc_normalise(ctx, sig, unit=True, bf16=True, fp8=True, err=True)
     unit = q["unit"].cpu().numpy()
-    osig = om.sign(c.offsets, c.tokens, om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=256)))[0]
+    osig = om.sign(c.offsets, c.tokens, om.build_model(c.offsets, c.tokens, c.vocab, om.RefSpec(k=k)))[0]
     assert np.abs(unit - om.normalise(osig)).max() <= 1e-5
     np.testing.assert_array_equal(q["bf16"].cpu().numpy().view(np.uint16), om.bf16_codes(unit))
     codes, scale = om.fp8_quantise_rows(unit)
@@ -126,3 +129,17 @@ def test_quantisers_match_oracle(lib, ctx):
     e8 = om.row_quant_error(unit, om.fp8_dequantise_rows(codes, scale))
     assert np.all(err[0] >= eb) and np.all(err[0] <= eb * (1 + 1e-6) + 1e-30)
     assert np.all(err[1] >= e8) and np.all(err[1] <= e8 * (1 + 1e-6) + 1e-30)
+
+
+def test_normalise_alignment_independent(lib, ctx):
+    # the same rows from a 16-byte aligned and a 4-byte aligned buffer give the same bits
+    import torch
+    c, sig = _signed(lib, ctx, 1, 300, 64)
+    buf = torch.zeros(sig.numel() + 1, dtype=torch.float32, device=sig.device)
+    mis = buf[1:].view(sig.shape)
+    mis.copy_(sig)
+    assert mis.data_ptr() % 16 != 0
+    a = lib.mrc_normalise(ctx, sig, unit=True, bf16=True, fp8=True, err=True)
+    b = lib.mrc_normalise(ctx, mis, unit=True, bf16=True, fp8=True, err=True)
+    for key in ("unit", "bf16", "fp8", "scale", "err"):
+        np.testing.assert_array_equal(a[key].cpu().numpy().view(np.uint8), b[key].cpu().numpy().view(np.uint8))
