@@ -707,8 +707,11 @@ __global__ __launch_bounds__(256) void k_sign_counts(const int64_t* __restrict__
 // ------------------------------------------------------------------- driver
 
 constexpr int kShortTeam = 64, kShortLog2 = 10, kShortPer = kShortMax / 64;      // 1024 slots
+constexpr int kMidMax = 2048;                                                    // medium documents up to here:
+constexpr int kMidTeam = 256, kMidLog2 = 12, kMidPer = kMidMax / 256;            // 4096 slots, 4 workgroups per CU
 constexpr int kMedTeam = 256, kMedLog2 = 13, kMedPer = kMediumMax / 256;         // 8192 slots
 static_assert((1 << kShortLog2) >= 2 * kShortMax, "short table load factor");
+static_assert((1 << kMidLog2) >= 2 * kMidMax, "mid table load factor");
 static_assert((1 << kMedLog2) >= 2 * kMediumMax, "medium table load factor");
 static_assert((1 << kMedLog2) <= 65536, "slot indices are stored as uint16");
 
@@ -740,10 +743,15 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const Pass
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
+        // the medium list in two passes by length: up to kMidMax tokens with
+        // half-size tables (twice the workgroups per CU), then the rest
+        const size_t lds_mid = team_lds_bytes(kpad, 1 << kMidLog2);
+        hipLaunchKernelGGL((k_doc_lds<MODE, kMidTeam, kMidLog2, kMidPer>), dim3(grid_for(n, 1, 256 * 4)), dim3(kBlock),
+                           lds_mid, s, docs->offsets, n, kShortMax, kMidMax, docs->tokens, V, a, err, med_list);
+        MRC_HIP_TRY(ctx, hipGetLastError());
         const size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
-        const int grid = grid_for(n, 1, 256 * 2);
-        hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid), dim3(kBlock), lds, s,
-                           docs->offsets, n, kShortMax, kMediumMax, docs->tokens, V, a, err, med_list);
+        hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid_for(n, 1, 256 * 2)), dim3(kBlock),
+                           lds, s, docs->offsets, n, kMidMax, kMediumMax, docs->tokens, V, a, err, med_list);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
