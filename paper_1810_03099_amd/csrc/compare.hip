@@ -1,13 +1,14 @@
 // Signature comparison (Eq. 1 applied to two signatures; the similarity that
 // Eq. 2 calls multi reference cosine).
 //
-//  * k_normalise: unit signatures u = sig / |sig| (float32), their bfloat16
-//    codes, float8 e4m3fn codes with a per-row power-of-two scale (the
-//    smallest one >= max|u|/448, so that the matrix cores can apply it as an
-//    E8M0 operand scale), and per-row error norms |u - dequantised| used to
-//    bound low-precision scores.
+//  * k_normalise_vec (k a multiple of 4; k_normalise otherwise): unit
+//    signatures u = sig / |sig| (float32), their bfloat16 codes, float8
+//    e4m3fn codes with a per-row power-of-two scale (the smallest one >=
+//    max|u|/448, so that the matrix cores can apply it as an E8M0 operand
+//    scale), and per-row error norms |u - dequantised| used to bound
+//    low-precision scores.
 //  * the plain FP32 path (allpairs_f32.hip) and the candidate search over the
-//    BF16 / FP8 codes (lds_allpairs.hip) consume k_normalise's layouts;
+//    BF16 / FP8 codes (lds_allpairs.hip) consume these layouts;
 //  * launch_compare_lowp: the candidate search over the BF16 / FP8 codes
 //    (LDS-tiled kernels of lds_allpairs.hip), emitting the candidates that
 //    k_rescore then decides with the plain chain.

@@ -2,6 +2,9 @@
 // named scratch buffers, and per-kernel HIP-event timing.
 #include <algorithm>
 #include <cstdio>
+#include <map>
+#include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -153,12 +156,28 @@ mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, 
 }
 
 int64_t persistent_grid(mrc_ctx* ctx, const void* kernel, int block, int64_t cap) {
+    // the occupancy and CU count of a (device, kernel, block size) are asked
+    // of the runtime once per process
+    static std::mutex mu;
+    static std::map<std::tuple<int, const void*, int>, std::pair<int, int>> known;
     int per_cu = 1, cus = 256;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
-        per_cu = 1;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess || cus < 1)
-        cus = 256;
-    (void)hipGetLastError();
+    {
+        std::lock_guard<std::mutex> g(mu);
+        const auto key = std::make_tuple(ctx->device, kernel, block);
+        auto it = known.find(key);
+        if (it != known.end()) {
+            per_cu = it->second.first;
+            cus = it->second.second;
+        } else {
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu < 1)
+                per_cu = 1;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess ||
+                cus < 1)
+                cus = 256;
+            (void)hipGetLastError();
+            known[key] = {per_cu, cus};
+        }
+    }
     int64_t g = (int64_t)per_cu * cus;
     cap = (cap + 7) / 8 * 8;
     if (g > cap) g = cap;
