@@ -6,17 +6,18 @@
 //
 // Queries go in groups of 16 as the B operand of 16x16 matrix-core tiles
 // whose A operand is 64 database rows, so lane (li, lg) of a wavefront holds
-// the scores of query li against 16 of the 64 rows; it keeps a private
-// top-16 list in registers while the wavefront streams its share of the
-// database. Lists are merged per workgroup in LDS, then per query.
+// the scores of query li against 16 of the 64 rows.
 //
-// FP32 scores are the plain chain (exact). For BF16/FP8 a first pass gives
-// each query's 16 best rows by the low-precision score, and E16, the smallest
-// exact (chain) score among them; a second pass collects every row whose
-// low-precision score is >= min(E16 - delta, tau - delta) (delta: the largest
-// rescoring band), which provably contains the exact top-16 (the exact 16th
-// best is >= E16) and all rows >= tau; those candidates are rescored with the
-// FP32 chain.
+// Two passes. The first gives each query its 16 best rows of a prefix of the
+// database (every lane keeps a private top-16 list in registers while the
+// wavefront streams its share of the prefix; lists are merged per workgroup
+// in LDS, then per query) and E16, the smallest exact (chain) score among
+// those rows: the exact 16th best over all rows is at least E16. The second
+// pass collects every row whose score is >= min(E16 - delta, tau - delta)
+// (delta: the largest rescoring band of the BF16/FP8 codes, 0 for FP32 scores,
+// which are the plain chain itself), with up to 4 query groups per wavefront
+// sharing each database fragment; the candidates, a superset of the exact
+// top-16 and of all rows >= tau, are then scored with the FP32 chain.
 #include <algorithm>
 
 #include "common.h"
@@ -32,6 +33,7 @@ typedef int i32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTop = 16;
 constexpr int kTileRows = 64;
+constexpr int64_t kPrefixMin = 16384;  // rows of the first pass: this many, or 1/16 of the database
 
 template <int PREC> struct QT;
 template <> struct QT<MRC_PREC_FP32> {
@@ -97,16 +99,15 @@ struct ScanArgs {
     const uint8_t* db;        // [rows_pad][ld_db] codes (FP32: matrix-core layout floats)
     int ld_db;                // bytes per row
     const float* db_scale;    // FP8 row scales
-    int64_t rows;             // database snapshot
+    int64_t rows;             // rows scanned (a prefix of the database snapshot, or all of it)
     const uint8_t* q;         // [nq_pad][ld_q] query codes, same layout
     int ld_q;
     const float* q_scale;
     int nq;
     float tau;
-    // MODE_TOP: per-workgroup top lists and hit counts
+    // MODE_TOP: per-workgroup top lists
     float* part_s;            // [nq][gx][kTop]
     int32_t* part_id;
-    int32_t* hits;            // [nq] (FP32 only), zeroed
     // MODE_COLLECT: candidates with score >= thr[q]
     const float* thr;
     int64_t* cand;            // [nq][cap] packed (id << 32 | float bits)
@@ -116,26 +117,35 @@ struct ScanArgs {
 
 enum { MODE_TOP = 0, MODE_COLLECT = 1 };
 
-template <int PREC, int NK, int MODE>
+// One workgroup per (share of the database, block of 16 G queries): its 4
+// wavefronts take turns over the share's 64-row tiles, and each wavefront
+// holds the G query groups' fragments, so every database fragment it loads
+// feeds G products (G > 1: collection only, where a lane keeps no lists).
+template <int PREC, int NK, int MODE, int G>
 __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     using T = QT<PREC>;
-    __shared__ float ls[16][16][kTop];    // [query][list = wave*4 + lg][entry]
-    __shared__ int lid[16][16][kTop];
-    __shared__ int lhits[16];
+    static_assert(MODE == MODE_COLLECT || G == 1, "top lists for one query group per wavefront");
+    __shared__ float ls[256][kTop];    // 16 lists per query: 4 wavefronts x 4 lane groups
+    __shared__ int lid[256][kTop];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
-    const int q = blockIdx.y * 16 + li;
-    const bool qvalid = q < a.nq;
-    if (threadIdx.x < 16) lhits[threadIdx.x] = 0;
-    __syncthreads();
-    // query fragments for every chunk stay in registers
-    typename T::F qb[NK];
-    const uint8_t* pq = a.q + (int64_t)(blockIdx.y * 16 + li) * a.ld_q + lg * T::kLaneBytes;
+    // query fragments of every group and chunk stay in registers (rows of the
+    // padded query arrays: every group of the block is readable)
+    typename T::F qb[G][NK];
+    int q[G];
+    bool qvalid[G];
+    float qsc[G], thr[G];
 #pragma unroll
-    for (int c = 0; c < NK; ++c) qb[c] = T::load(pq + c * T::kChunkBytes);
-    const float qsc = (PREC == MRC_PREC_FP8) ? a.q_scale[blockIdx.y * 16 + li] : 1.f;
-    const float thr = (MODE == MODE_COLLECT && qvalid) ? a.thr[q] : 0.f;
+    for (int g = 0; g < G; ++g) {
+        q[g] = (blockIdx.y * G + g) * 16 + li;
+        qvalid[g] = q[g] < a.nq;
+        const uint8_t* pq = a.q + (int64_t)q[g] * a.ld_q + lg * T::kLaneBytes;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
+        qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
+        thr[g] = (MODE == MODE_COLLECT && qvalid[g]) ? a.thr[q[g]] : 0.f;
+    }
     float ts[kTop];
     int tid_[kTop];
 #pragma unroll
@@ -143,15 +153,16 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
         ts[p] = -INFINITY;
         tid_[p] = 0x7fffffff;
     }
-    int hits = 0;
     const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
     const int64_t stride = (int64_t)gridDim.x * 4;
     for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += stride) {
         const int64_t row0 = t * kTileRows;
         const uint8_t* pa = a.db + (row0 + li) * a.ld_db + lg * T::kLaneBytes;
-        f32x4 acc[4];
+        f32x4 acc[G][4];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) acc[x] = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int x = 0; x < 4; ++x) acc[g][x] = f32x4{0.f, 0.f, 0.f, 0.f};
         typename T::F fa[2][4];
 #pragma unroll
         for (int x = 0; x < 4; ++x) fa[0][x] = T::load(pa + (int64_t)16 * x * a.ld_db);
@@ -160,37 +171,61 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
             const int cur = c & 1, nxt = cur ^ 1;
             if (c + 1 < NK) {
 #pragma unroll
-                for (int x = 0; x < 4; ++x) fa[nxt][x] = T::load(pa + (int64_t)16 * x * a.ld_db + (c + 1) * T::kChunkBytes);
+                for (int x = 0; x < 4; ++x)
+                    fa[nxt][x] = T::load(pa + (int64_t)16 * x * a.ld_db + (c + 1) * T::kChunkBytes);
             }
 #pragma unroll
-            for (int x = 0; x < 4; ++x) acc[x] = T::mma(fa[cur][x], qb[c], acc[x]);
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) acc[g][x] = T::mma(fa[cur][x], qb[g][c], acc[g][x]);
         }
-        // lane holds query li against rows row0 + 16x + 4lg + r (ascending ids in this order)
+        // lane holds query li of each group against rows row0 + 16x + 4lg + r
+        // (ascending ids in this order)
+        if (PREC == MRC_PREC_FP8) {
 #pragma unroll
-        for (int x = 0; x < 4; ++x)
+            for (int x = 0; x < 4; ++x) {
+                const f32x4 sc = *(const f32x4*)(a.db_scale + row0 + 16 * x + 4 * lg);  // rows padded to 64
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t row = row0 + 16 * x + 4 * lg + r;
-                float v = acc[x][r];
-                if (PREC == MRC_PREC_FP8) v = v * a.db_scale[row] * qsc;
-                const bool ok = qvalid && row < a.rows;
-                if (MODE == MODE_TOP) {
-                    if (ok && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1])) top_insert(ts, tid_, v, (int)row);
-                    if (PREC == MRC_PREC_FP32) hits += (ok && v >= a.tau) ? 1 : 0;
-                } else if (ok && v >= thr) {
-                    const int e = atomicAdd(&a.ccount[q], 1);
-                    if (e < a.cap) a.cand[(int64_t)q * a.cap + e] = ((int64_t)row << 32) | (int64_t)__float_as_uint(v);
-                }
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[g][x][r] = acc[g][x][r] * sc[r] * qsc[g];
             }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            // the lane's largest score decides whether any of its 16 can matter:
+            // below the list's last entry or below the collection threshold,
+            // the tile changes nothing
+            float mx = -INFINITY;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                mx = fmaxf(mx, fmaxf(fmaxf(acc[g][x][0], acc[g][x][1]), fmaxf(acc[g][x][2], acc[g][x][3])));
+            const bool skip = MODE == MODE_TOP ? mx < ts[kTop - 1] : mx < thr[g];
+            if (skip || !qvalid[g]) continue;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int64_t row = row0 + 16 * x + 4 * lg + r;
+                    const float v = acc[g][x][r];
+                    const bool ok = row < a.rows;
+                    if (MODE == MODE_TOP) {
+                        if (ok && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1])) top_insert(ts, tid_, v, (int)row);
+                    } else if (ok && v >= thr[g]) {
+                        const int e = atomicAdd(&a.ccount[q[g]], 1);
+                        if (e < a.cap)
+                            a.cand[(int64_t)q[g] * a.cap + e] = ((int64_t)row << 32) | (int64_t)__float_as_uint(v);
+                    }
+                }
+        }
     }
     if (MODE == MODE_COLLECT) return;
     // workgroup merge: 16 lists (4 wavefronts x 4 lane groups) per query
 #pragma unroll
     for (int p = 0; p < kTop; ++p) {
-        ls[li][wave * 4 + lg][p] = ts[p];
-        lid[li][wave * 4 + lg][p] = tid_[p];
+        ls[li * 16 + wave * 4 + lg][p] = ts[p];
+        lid[li * 16 + wave * 4 + lg][p] = tid_[p];
     }
-    if (PREC == MRC_PREC_FP32 && hits) atomicAdd(&lhits[li], hits);
     __syncthreads();
     if (threadIdx.x < 16) {
         const int qq = blockIdx.y * 16 + threadIdx.x;
@@ -206,10 +241,10 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
                 int bidx = 0x7fffffff;
                 for (int l = 0; l < 16; ++l) {
                     if (head[l] < kTop) {
-                        const float s = ls[threadIdx.x][l][head[l]];
-                        const int id = lid[threadIdx.x][l][head[l]];
-                        if (better(s, id, bs, bidx)) {
-                            bs = s;
+                        const float sv = ls[threadIdx.x * 16 + l][head[l]];
+                        const int id = lid[threadIdx.x * 16 + l][head[l]];
+                        if (better(sv, id, bs, bidx)) {
+                            bs = sv;
                             bidx = id;
                             bl = l;
                         }
@@ -219,7 +254,6 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
                 oi[p] = bidx;
                 head[bl] += 1;
             }
-            if (PREC == MRC_PREC_FP32 && lhits[threadIdx.x]) atomicAdd(&a.hits[qq], lhits[threadIdx.x]);
         }
     }
 }
@@ -334,7 +368,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
                                                      int cap, const float* __restrict__ qunit, int k,
                                                      const float* __restrict__ db_umfma, int kp, float tau, int topk,
                                                      mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
-                                                     unsigned long long* __restrict__ err) {
+                                                     int flags, unsigned long long* __restrict__ err) {
     __shared__ float ss[4][kTop];
     __shared__ int si[4][kTop];
     __shared__ int shits;
@@ -409,7 +443,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
             hd[bw] += 1;
             out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
             out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
-            out[(int64_t)q * topk + p].flags = 1;
+            out[(int64_t)q * topk + p].flags = flags;
         }
         n_hits[q] = shits;
     }
@@ -433,28 +467,40 @@ __global__ void k_max_err(const float* __restrict__ db_max, const float* __restr
     }
 }
 
-template <int PREC, int MODE>
-mrc_status launch_scan(mrc_ctx* ctx, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
-#define MRC_Q(c) case c: hipLaunchKernelGGL((k_query_scan<PREC, c, MODE>), grid, dim3(256), 0, s, a); break;
-    if (PREC == MRC_PREC_FP32) {
-        switch (nk) {
-            MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) MRC_Q(24) MRC_Q(32)
-            default: return fail(MRC_E_INVAL, "query: unsupported k");
-        }
-    } else if (PREC == MRC_PREC_BF16) {
-        switch (nk) {
-            MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(10) MRC_Q(12) MRC_Q(16)
-            default: return fail(MRC_E_INVAL, "query: unsupported k");
-        }
+// G query groups per wavefront when their fragments fit in 128 registers.
+template <int PREC, int MODE, int G, int NK>
+bool launch_scan_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
+    if constexpr (G == 1 || G * NK * QT<PREC>::kLaneBytes / 4 <= 128) {
+        hipLaunchKernelGGL((k_query_scan<PREC, NK, MODE, G>), grid, dim3(256), 0, s, a);
+        return true;
     } else {
-        switch (nk) {
-            MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8)
-            default: return fail(MRC_E_INVAL, "query: unsupported k");
-        }
+        return false;
+    }
+}
+
+template <int PREC, int MODE, int G>
+mrc_status launch_scan(mrc_ctx* ctx, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+    bool ok = false;
+#define MRC_Q(c) case c: ok = launch_scan_nk<PREC, MODE, G, c>(a, grid, s); break;
+    if constexpr (PREC == MRC_PREC_FP32) {
+        switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) MRC_Q(24) MRC_Q(32) default: break; }
+    } else if constexpr (PREC == MRC_PREC_BF16) {
+        switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(10) MRC_Q(12) MRC_Q(16) default: break; }
+    } else {
+        switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) default: break; }
     }
 #undef MRC_Q
+    if (!ok) return fail(MRC_E_INVAL, "query: unsupported k");
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
+}
+
+template <int PREC>
+mrc_status launch_scan_any(mrc_ctx* ctx, int mode, int g, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+    if (mode == MODE_TOP) return launch_scan<PREC, MODE_TOP, 1>(ctx, nk, a, grid, s);
+    if (g == 4) return launch_scan<PREC, MODE_COLLECT, 4>(ctx, nk, a, grid, s);
+    if (g == 2) return launch_scan<PREC, MODE_COLLECT, 2>(ctx, nk, a, grid, s);
+    return launch_scan<PREC, MODE_COLLECT, 1>(ctx, nk, a, grid, s);
 }
 
 }  // namespace
@@ -490,65 +536,82 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
                  (float*)umf, L.kp, nq_pad};
     MRC_TRY(launch_normalise_rows(ctx, (const float*)sig, nq, k, o, s));
     if (nq == 0) return MRC_OK;
-    const int groups = (int)ceil_div(nq, 16);
-    const int64_t tiles = std::max<int64_t>(1, ceil_div(rows, kTileRows));
-    int gx = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), ceil_div(tiles, 4)));
-    dim3 grid(gx, groups);
-    void *ps, *pi, *hits;
-    MRC_TRY(scratch(ctx, "q_part_s", (size_t)nq * gx * kTop * 4, &ps));
-    MRC_TRY(scratch(ctx, "q_part_id", (size_t)nq * gx * kTop * 4, &pi));
-    MRC_TRY(scratch(ctx, "q_hits", (size_t)nq * 4, &hits));
-    MRC_HIP_TRY(ctx, hipMemsetAsync(hits, 0, (size_t)nq * 4, s));
+    const bool fp32 = precision == MRC_PREC_FP32, bf = precision == MRC_PREC_BF16;
+    if ((bf && !db->d_bf16) || (precision == MRC_PREC_FP8 && !db->d_fp8))
+        return fail(MRC_E_STATE, "mrc_query: the database holds no copy in this precision");
     ScanArgs a{};
-    a.rows = rows;
     a.nq = (int)nq;
     a.tau = tau;
-    a.part_s = (float*)ps;
-    a.part_id = (int32_t*)pi;
-    a.hits = (int32_t*)hits;
-    ScopedTimer tm(ctx, "query", s);
-    if (precision == MRC_PREC_FP32) {
+    int nk, lane_regs;
+    if (fp32) {
         a.db = (const uint8_t*)db->d_unit;
         a.ld_db = L.kp * 4;
         a.q = (const uint8_t*)umf;
-        a.ld_q = L.kp * 4;
-        MRC_TRY((launch_scan<MRC_PREC_FP32, MODE_TOP>(ctx, L.kp / 16, a, grid, s)));
-        hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
-                           (const int32_t*)pi, gx, (int)nq, topk, (const int32_t*)hits, topk_out, n_hits,
-                           (float*)nullptr);
-        MRC_HIP_TRY(ctx, hipGetLastError());
-        return MRC_OK;
+        nk = L.kp / 16;
+        lane_regs = 4;
+    } else {
+        a.db = bf ? (const uint8_t*)db->d_bf16 : db->d_fp8;
+        a.ld_db = bf ? L.ldb * 2 : L.ld8;
+        a.db_scale = db->d_scale;
+        a.q = bf ? (const uint8_t*)qb : (const uint8_t*)q8;
+        a.q_scale = (const float*)qsc;
+        nk = bf ? L.ldb / 32 : L.ld8 / 128;
+        lane_regs = bf ? 4 : 8;
     }
-    if ((precision == MRC_PREC_BF16 && !db->d_bf16) || (precision == MRC_PREC_FP8 && !db->d_fp8))
-        return fail(MRC_E_STATE, "mrc_query: the database holds no copy in this precision");
-    const bool bf = precision == MRC_PREC_BF16;
-    a.db = bf ? (const uint8_t*)db->d_bf16 : db->d_fp8;
-    a.ld_db = bf ? L.ldb * 2 : L.ld8;
-    a.db_scale = db->d_scale;
-    a.q = bf ? (const uint8_t*)qb : (const uint8_t*)q8;
     a.ld_q = a.ld_db;
-    a.q_scale = (const float*)qsc;
-    const int nk = bf ? L.ldb / 32 : L.ld8 / 128;
-    void *l16, *thr, *delta, *cand, *cc, *mtop;
+    auto scan = [&](int mode, int g, dim3 grid) {
+        if (fp32) return launch_scan_any<MRC_PREC_FP32>(ctx, mode, g, nk, a, grid, s);
+        if (bf) return launch_scan_any<MRC_PREC_BF16>(ctx, mode, g, nk, a, grid, s);
+        return launch_scan_any<MRC_PREC_FP8>(ctx, mode, g, nk, a, grid, s);
+    };
+    auto grid_for_rows = [&](int64_t r, int64_t groups) {
+        const int64_t tiles = std::max<int64_t>(1, ceil_div(r, kTileRows));
+        const int gx = (int)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), ceil_div(tiles, 4)));
+        return dim3(gx, (unsigned)groups);
+    };
+    ScopedTimer tm(ctx, "query", s);
+    // pass 1: each query's 16 best rows of a prefix of the database (a lower
+    // bound for the whole: any 16 rows' smallest exact score is at most the
+    // exact 16th best), their exact scores, and the collection threshold
+    // thr = min(E16 - delta, tau - delta) (delta = 0 for FP32 scores, which
+    // are the chain itself). FP8's band is wide: its first pass takes the
+    // whole database, so that E16 is as high as it can be
+    const int64_t sample = precision == MRC_PREC_FP8
+                               ? rows
+                               : std::min<int64_t>(rows, std::max<int64_t>(kPrefixMin, ceil_div(rows, 16)));
+    const dim3 g1 = grid_for_rows(sample, ceil_div(nq, 16));
+    void *ps, *pi, *l16, *thr, *delta, *cand, *cc, *mtop;
+    MRC_TRY(scratch(ctx, "q_part_s", (size_t)nq * g1.x * kTop * 4, &ps));
+    MRC_TRY(scratch(ctx, "q_part_id", (size_t)nq * g1.x * kTop * 4, &pi));
     MRC_TRY(scratch(ctx, "q_l16", (size_t)nq * 4, &l16));
     MRC_TRY(scratch(ctx, "q_thr", (size_t)nq * 4, &thr));
     MRC_TRY(scratch(ctx, "q_delta", 256, &delta));
     MRC_TRY(scratch(ctx, "q_top_lp", (size_t)nq * kTop * sizeof(mrc_hit), &mtop));
-    // pass 1: low-precision top-16 -> L16
-    if (bf) MRC_TRY((launch_scan<MRC_PREC_BF16, MODE_TOP>(ctx, nk, a, grid, s)));
-    else MRC_TRY((launch_scan<MRC_PREC_FP8, MODE_TOP>(ctx, nk, a, grid, s)));
+    a.rows = sample;
+    a.part_s = (float*)ps;
+    a.part_id = (int32_t*)pi;
+    MRC_TRY(scan(MODE_TOP, 1, g1));
     hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
-                       (const int32_t*)pi, gx, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
-                       (int32_t*)nullptr, (float*)l16);
-    const float* q_err = (const float*)qerr + (bf ? 0 : nq_pad);
-    hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db->d_errmax + (bf ? 0 : 1), q_err, nq, 0.02f,
-                       lowp_acc_unit(precision, k), (float*)delta);
+                       (const int32_t*)pi, (int)g1.x, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
+                       (int32_t*)nullptr, (float*)nullptr);
+    if (fp32) {
+        MRC_TRY(clear_words(ctx, (int64_t*)delta, 1, s));
+    } else {
+        const float* q_err = (const float*)qerr + (bf ? 0 : nq_pad);
+        hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db->d_errmax + (bf ? 0 : 1), q_err, nq, 0.02f,
+                           lowp_acc_unit(precision, k), (float*)delta);
+    }
     hipLaunchKernelGGL(k_query_e16, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const mrc_hit*)mtop, (int)nq,
                        (const float*)unit, k, db->d_unit, L.kp, (float*)l16);
     hipLaunchKernelGGL(k_query_thr, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s, (const float*)l16, (int)nq,
                        tau, (const float*)delta, (float*)thr);
     MRC_HIP_TRY(ctx, hipGetLastError());
-    // pass 2: collect candidates, rescore exactly; grow the per-query capacity on overflow
+    // pass 2: every row at or above the threshold, G query groups per
+    // wavefront, then exact decisions; grow the per-query capacity on overflow
+    int g = nq <= 16 ? 1 : nq <= 48 ? 2 : 4;
+    while (g > 1 && g * nk * lane_regs > 128) g /= 2;
+    a.rows = rows;
+    const dim3 g2 = grid_for_rows(rows, ceil_div(nq, 16 * g));
     int cap = 2048;
     auto it = ctx->scratch.find("q_cand");
     if (it != ctx->scratch.end()) cap = std::max<int64_t>(cap, (int64_t)(it->second.second / 8 / nq));
@@ -561,11 +624,10 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         a.cand = (int64_t*)cand;
         a.ccount = (int32_t*)cc;
         a.cap = cap;
-        if (bf) MRC_TRY((launch_scan<MRC_PREC_BF16, MODE_COLLECT>(ctx, nk, a, grid, s)));
-        else MRC_TRY((launch_scan<MRC_PREC_FP8, MODE_COLLECT>(ctx, nk, a, grid, s)));
+        MRC_TRY(scan(MODE_COLLECT, g, g2));
         hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)cand,
                            (const int32_t*)cc, cap, (const float*)unit, k, db->d_unit, L.kp, tau, topk, topk_out,
-                           n_hits, (unsigned long long*)ctx->d_flags);
+                           n_hits, fp32 ? 0 : 1, (unsigned long long*)ctx->d_flags);
         MRC_HIP_TRY(ctx, hipGetLastError());
         int64_t flag = 0;
         MRC_HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flags, 8, hipMemcpyDeviceToHost, s));

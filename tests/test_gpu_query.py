@@ -72,6 +72,30 @@ def test_query_equals_exact_chain(lib, ctx, setup, prec):
     flush(f"  {prec}: mean hits {hits.mean():.2f}, queries with a hit {int((hits > 0).sum())}")
 
 
+@pytest.mark.parametrize("nq", [10, 40, 200])
+def test_query_prefix_threshold_exact(lib, ctx, nq):
+    # 20,000 rows: the first pass sees a 16,384-row prefix, whose 16th best is
+    # only a lower bound; batches of 10, 40 and 200 queries run the collection
+    # with 1, 2 and 4 query groups per wavefront
+    dbc = synth.generate(1)
+    qc = synth.generate_queries(synth.CONFIGS[1], nq, seed=101 + nq, median=300, sigma=1.2, hi=6000, near_of=dbc,
+                                near_frac=0.4)
+    o, t = device_docs(dbc)
+    model = lib.mrc_build_vocab_idf(ctx, o, t, dbc.vocab, lib.ref_spec(64))
+    db = lib.mrc_db_create(ctx, dbc.n_docs, 64, precisions=(lib.PREC_BF16, lib.PREC_FP8))
+    lib.mrc_db_insert_docs(db, model, o, t)
+    qo, qt = device_docs(qc)
+    dbunit = lib.mrc_normalise(ctx, lib.mrc_sign(ctx, model, o, t))["unit"].cpu().numpy()
+    qunit = lib.mrc_normalise(ctx, lib.mrc_sign(ctx, model, qo, qt))["unit"].cpu().numpy()
+    wids, wsc, whits = chain_topk(qunit, dbunit, 16, TAU)
+    for p in (lib.PREC_FP32, lib.PREC_BF16, lib.PREC_FP8):
+        ids, sc, hits = lib.mrc_query(ctx, db, model, qo, qt, 16, TAU, p)
+        np.testing.assert_array_equal(ids.cpu().numpy(), wids)
+        np.testing.assert_array_equal(sc.cpu().numpy().view(np.uint32), wsc.view(np.uint32))
+        np.testing.assert_array_equal(hits.cpu().numpy(), whits)
+    flush(f"  nq={nq}: 20,000 rows, prefix threshold, all forms == exact chain; mean hits {whits.mean():.2f}")
+
+
 def test_query_vs_fp64_oracle(lib, ctx, setup):
     dbc, qc = setup["dbc"], setup["qc"]
     omodel = om.build_model(dbc.offsets, dbc.tokens, dbc.vocab, om.RefSpec(k=64))
