@@ -63,6 +63,10 @@ size_t model_layout(size_t V, size_t k, size_t off[7]) {
     return total;
 }
 
+}  // namespace
+
+namespace mrc {
+
 // The context keeps the table block of one destroyed model for the next build
 // of the same size, so that rebuilding a model costs no device allocation or
 // free. The kept block still counts against the budget; the context frees it
@@ -85,7 +89,12 @@ void free_model(mrc_model* m) {
     dev_free(c, old, old_bytes);
     dev_free(c, m->d_hash, (size_t)m->vocab * 8);
     delete m;
+    ctx_release(c);
 }
+
+}  // namespace mrc
+
+namespace {
 
 mrc_status alloc_model(mrc_ctx* ctx, int32_t V, int32_t k, mrc_model** out) {
     mrc_model* m = new mrc_model();
@@ -122,6 +131,7 @@ mrc_status alloc_model(mrc_ctx* ctx, int32_t V, int32_t k, mrc_model** out) {
     m->d_tinfo = (TermInfo*)(base + off[4]);
     m->d_rnorm = (double*)(base + off[5]);
     m->d_rinv = (double*)(base + off[6]);
+    ctx_retain(ctx);
     *out = m;
     return MRC_OK;
 }
@@ -210,6 +220,13 @@ mrc_status mrc_build_and_sign(mrc_ctx* ctx, const mrc_docs* corpus, int32_t voca
 
 mrc_status mrc_model_destroy(mrc_model* model) {
     if (!model) return MRC_OK;
+    {
+        std::lock_guard<std::mutex> g(model->ctx->mu);
+        if (model->users > 0) {  // a server still uses it: the last one to stop frees it
+            model->closing = true;
+            return MRC_OK;
+        }
+    }
     (void)hipSetDevice(model->ctx->device);
     (void)hipDeviceSynchronize();
     free_model(model);

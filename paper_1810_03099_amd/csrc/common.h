@@ -64,6 +64,11 @@ struct mrc_ctx {
     int tile_order_nb = -1;      // the band table in scratch "tile_order" is for this many tile rows
     void* model_spare = nullptr; // table block of the last destroyed model, kept for the next build
     size_t model_spare_bytes = 0;
+    // Models and databases hold their context: destroyed while any of them
+    // lives, the context is only marked (closing) and the last one released
+    // frees it, so handles may be destroyed in any order.
+    int live = 0;
+    bool closing = false;
 };
 
 struct mrc_model {
@@ -82,6 +87,8 @@ struct mrc_model {
     double* d_rinv = nullptr;        // [k]  1 / |r_j|
     uint64_t* d_hash = nullptr;      // [V]  MD5 term hashes (built on first use)
     size_t bytes = 0;                // the one device block holding d_df .. d_rinv (at d_df)
+    mutable int users = 0;           // servers using the model (guarded by ctx->mu)
+    mutable bool closing = false;    // destroyed while in use: freed when the last server stops
 };
 
 struct mrc_db {
@@ -99,11 +106,21 @@ struct mrc_db {
     float* d_errmax = nullptr;   // [2]: largest bf16 / fp8 row error bound of the committed rows
     size_t bytes = 0;
     std::mutex mu;
+    int users = 0;               // servers using the database (guarded by ctx->mu)
+    bool closing = false;        // destroyed while in use: freed when the last server stops
 };
 
 namespace mrc {
 
 mrc_status hip_fail(mrc_ctx* ctx, hipError_t e, const char* what, const char* file, int line);
+
+// Context lifetime (see mrc_ctx::live): an object that holds the context
+// retains it when created and releases it when freed; the release that ends
+// a closing context frees it.
+void ctx_retain(mrc_ctx* ctx);
+void ctx_release(mrc_ctx* ctx);
+void free_model(mrc_model* m);
+void free_db(mrc_db* db);
 
 // Device allocation accounted against the context budget.
 mrc_status dev_alloc(mrc_ctx* ctx, void** p, size_t bytes);
@@ -354,7 +371,7 @@ int mfma_chunks(int k);
 
 // Sizes of the length classes the document kernels use.
 constexpr int kShortMax = 512;    // one wavefront per document, LDS hash table
-constexpr int kMediumMax = 4096;  // one 256-thread workgroup per document, LDS hash table
+constexpr int kMediumMax = 8192;  // one 256-thread workgroup per document, LDS hash table
 constexpr int kLongBlocks = 64;   // workgroups of the long-document pass (each owns a [V] table)
 constexpr int64_t kMaxDocLen = 1 << 22;  // longest document (exact 64/128-bit sums below this)
 

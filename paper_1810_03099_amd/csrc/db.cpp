@@ -20,6 +20,10 @@ mrc_status ctx_ready(mrc_ctx* ctx, const char* fn) {
     return MRC_OK;
 }
 
+}  // namespace
+
+namespace mrc {
+
 void free_db(mrc_db* db) {
     if (!db) return;
     mrc_ctx* c = db->ctx;
@@ -31,13 +35,19 @@ void free_db(mrc_db* db) {
     dev_free(c, db->d_err, (size_t)db->cap_pad * 8);
     dev_free(c, db->d_errmax, 8);
     delete db;
+    ctx_release(c);
 }
+
+}  // namespace mrc
+
+namespace {
 
 mrc_status alloc_db(mrc_ctx* ctx, int64_t capacity, int32_t k, uint32_t precisions, mrc_db** out) {
     if (capacity < 1 || k < 1 || k > 1024) return fail(MRC_E_INVAL, "mrc_db_create: bad capacity or k");
     if (capacity > 0x7FFFFFFFLL - 64) return fail(MRC_E_INVAL, "mrc_db_create: capacity above 2^31 rows");
     mrc_db* db = new mrc_db();
     db->ctx = ctx;
+    ctx_retain(ctx);
     db->capacity = capacity;
     db->cap_pad = ceil_div(capacity, 64) * 64;
     db->k = k;
@@ -107,6 +117,13 @@ mrc_status mrc_db_create(mrc_ctx* ctx, int64_t capacity, int32_t k, uint32_t pre
 
 mrc_status mrc_db_destroy(mrc_db* db) {
     if (!db) return MRC_OK;
+    {
+        std::lock_guard<std::mutex> g(db->ctx->mu);
+        if (db->users > 0) {  // a server still uses it: the last one to stop frees it
+            db->closing = true;
+            return MRC_OK;
+        }
+    }
     (void)hipSetDevice(db->ctx->device);
     (void)hipDeviceSynchronize();
     free_db(db);

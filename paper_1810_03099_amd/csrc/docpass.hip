@@ -709,11 +709,14 @@ __global__ __launch_bounds__(256) void k_sign_counts(const int64_t* __restrict__
 constexpr int kShortTeam = 64, kShortLog2 = 10, kShortPer = kShortMax / 64;      // 1024 slots
 constexpr int kMidMax = 2048;                                                    // medium documents up to here:
 constexpr int kMidTeam = 256, kMidLog2 = 12, kMidPer = kMidMax / 256;            // 4096 slots, 4 workgroups per CU
-constexpr int kMedTeam = 256, kMedLog2 = 13, kMedPer = kMediumMax / 256;         // 8192 slots
+constexpr int kMedMax = 4096;
+constexpr int kMedTeam = 256, kMedLog2 = 13, kMedPer = kMedMax / 256;            // 8192 slots
+constexpr int kBigTeam = 256, kBigLog2 = 14, kBigPer = kMediumMax / 256;         // 16384 slots, 1 workgroup per CU
 static_assert((1 << kShortLog2) >= 2 * kShortMax, "short table load factor");
 static_assert((1 << kMidLog2) >= 2 * kMidMax, "mid table load factor");
-static_assert((1 << kMedLog2) >= 2 * kMediumMax, "medium table load factor");
-static_assert((1 << kMedLog2) <= 65536, "slot indices are stored as uint16");
+static_assert((1 << kMedLog2) >= 2 * kMedMax, "medium table load factor");
+static_assert((1 << kBigLog2) >= 2 * kMediumMax, "large table load factor");
+static_assert((1 << kBigLog2) <= 65536, "slot indices are stored as uint16");
 
 int grid_for(int64_t n_items_upper, int teams_per_block, int cap) {
     int64_t g = ceil_div(n_items_upper, teams_per_block);
@@ -743,15 +746,20 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const Pass
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
-        // the medium list in two passes by length: up to kMidMax tokens with
-        // half-size tables (twice the workgroups per CU), then the rest
+        // the medium list in three passes by length: up to kMidMax tokens with
+        // 4096-slot tables (four workgroups per CU), up to kMedMax with 8192
+        // slots, up to kMediumMax with 16384 (147 KB: one workgroup per CU)
         const size_t lds_mid = team_lds_bytes(kpad, 1 << kMidLog2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kMidTeam, kMidLog2, kMidPer>), dim3(grid_for(n, 1, 256 * 4)), dim3(kBlock),
                            lds_mid, s, docs->offsets, n, kShortMax, kMidMax, docs->tokens, V, a, err, med_list);
         MRC_HIP_TRY(ctx, hipGetLastError());
         const size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid_for(n, 1, 256 * 2)), dim3(kBlock),
-                           lds, s, docs->offsets, n, kMidMax, kMediumMax, docs->tokens, V, a, err, med_list);
+                           lds, s, docs->offsets, n, kMidMax, kMedMax, docs->tokens, V, a, err, med_list);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+        const size_t lds_big = team_lds_bytes(kpad, 1 << kBigLog2);
+        hipLaunchKernelGGL((k_doc_lds<MODE, kBigTeam, kBigLog2, kBigPer>), dim3(grid_for(n, 1, 256)), dim3(kBlock),
+                           lds_big, s, docs->offsets, n, kMedMax, kMediumMax, docs->tokens, V, a, err, med_list);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {

@@ -185,6 +185,32 @@ int64_t persistent_grid(mrc_ctx* ctx, const void* kernel, int block, int64_t cap
     return g < 8 ? 8 : g;
 }
 
+void ctx_free_now(mrc_ctx* ctx) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    timer_collect(ctx);
+    for (auto& kv : ctx->scratch) (void)hipFree(kv.second.first);
+    if (ctx->model_spare) (void)hipFree(ctx->model_spare);
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
+    delete ctx;
+}
+
+void ctx_retain(mrc_ctx* ctx) {
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ++ctx->live;
+}
+
+void ctx_release(mrc_ctx* ctx) {
+    bool now;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        now = --ctx->live == 0 && ctx->closing;
+    }
+    if (now) ctx_free_now(ctx);
+}
+
 }  // namespace mrc
 
 using namespace mrc;
@@ -224,15 +250,12 @@ mrc_status mrc_ctx_create(mrc_ctx** out, int32_t device, size_t hbm_budget_bytes
 
 mrc_status mrc_ctx_destroy(mrc_ctx* ctx) {
     if (!ctx) return MRC_OK;
-    (void)hipSetDevice(ctx->device);
-    (void)hipDeviceSynchronize();
-    timer_collect(ctx);
-    for (auto& kv : ctx->scratch) (void)hipFree(kv.second.first);
-    if (ctx->model_spare) (void)hipFree(ctx->model_spare);
-    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
-    if (ctx->d_flags) (void)hipFree(ctx->d_flags);
-    if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
-    delete ctx;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->closing = true;
+        if (ctx->live > 0) return MRC_OK;  // the last model or database frees it
+    }
+    ctx_free_now(ctx);
     return MRC_OK;
 }
 

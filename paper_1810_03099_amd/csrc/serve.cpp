@@ -169,6 +169,8 @@ struct mrc_server {
     GpuExecutor* ex = nullptr;
     mrc_serve::Scheduler* sched = nullptr;
     int32_t vocab = 0;
+    mrc_db* db = nullptr;            // used (not owned): destroying them waits for the server
+    const mrc_model* model = nullptr;
 };
 
 extern "C" {
@@ -199,6 +201,16 @@ mrc_status mrc_serve_start(mrc_ctx* ctx, mrc_db* db, const mrc_model* model, con
     so.mem_cap = (size_t)(opts->hbm_frac * (double)ctx->budget);
     so.max_wait_us = opts->max_wait_us;
     srv->sched = new mrc_serve::Scheduler(srv->ex, so);
+    srv->db = db;
+    srv->model = model;
+    {
+        std::lock_guard<std::mutex> g(db->ctx->mu);
+        ++db->users;
+    }
+    {
+        std::lock_guard<std::mutex> g(model->ctx->mu);
+        ++model->users;
+    }
     *out = srv;
     return MRC_OK;
 }
@@ -259,7 +271,25 @@ mrc_status mrc_serve_stop(mrc_server* srv) {
     srv->sched->stop();
     delete srv->sched;
     delete srv->ex;
+    // a database or model destroyed while this server ran is freed now
+    mrc_db* db = srv->db;
+    mrc_model* model = const_cast<mrc_model*>(srv->model);
     delete srv;
+    bool free_db_now, free_model_now;
+    {
+        std::lock_guard<std::mutex> g(db->ctx->mu);
+        free_db_now = --db->users == 0 && db->closing;
+    }
+    {
+        std::lock_guard<std::mutex> g(model->ctx->mu);
+        free_model_now = --model->users == 0 && model->closing;
+    }
+    if (free_db_now || free_model_now) {
+        (void)hipSetDevice(db->ctx->device);
+        (void)hipDeviceSynchronize();
+    }
+    if (free_db_now) free_db(db);
+    if (free_model_now) free_model(model);
     return MRC_OK;
 }
 

@@ -141,3 +141,26 @@ def test_submit_many_equals_alone(lib, env):
         lib.mrc_serve_submit_many(srv, qc.offsets[:4], bad_tok)
     lib.mrc_serve_stop(srv)
     flush(f"  submit_many: {qc.n_docs} queries in one call == alone")
+
+
+@pytest.mark.parametrize("order", ["ctx_first", "db_first"])
+def test_handles_destroyed_in_any_order(lib, order):
+    # a context destroyed before its model and database, and a database and
+    # model destroyed while a server uses them, are freed only when the last
+    # holder goes; the server keeps answering meanwhile
+    c = synth.generate(0, n_docs=300)
+    o, t = device_docs(c)
+    ctx = lib.mrc_ctx_create(0)
+    m = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(16))
+    db = lib.mrc_db_create(ctx, 400, 16)
+    lib.mrc_db_insert_docs(db, m, o, t)
+    srv = lib.mrc_serve_start(ctx, db, m, max_batch=8, n_streams=1, topk=4, tau=TAU)
+    if order == "ctx_first":
+        ctx.close()
+    db.close()
+    m.close()
+    r = lib.mrc_serve_poll(srv, lib.mrc_serve_submit(srv, c.doc(3)), wait_ms=60000)
+    assert r is not None and r.status == 0 and r.n_hits >= 1 and r.top[0].s >= 0.999
+    lib.mrc_serve_stop(srv)
+    if order == "db_first":
+        ctx.close()

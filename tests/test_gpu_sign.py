@@ -99,13 +99,14 @@ def test_reference_modes(lib, ctx, mode, kw):
 
 
 def test_edge_documents(lib, ctx):
-    """Empty documents, one-token documents, the largest id, documents in every
-    length class (LDS wavefront / LDS workgroup / global table), 50,000
-    repeats of one id."""
+    """Empty documents, one-token documents, the largest id, documents on both
+    sides of every length-class boundary (LDS wavefront up to 512 tokens; LDS
+    workgroup tables of 4096, 8192 and 16384 slots up to 2048, 4096 and 8192;
+    global tables beyond), 50,000 repeats of one id."""
     rng = np.random.default_rng(4)
     V = 4096
     docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
-    for L in (1, 63, 64, 65, 511, 512, 513, 4095, 4096, 4097, 9999, 10001, 30000):
+    for L in (1, 63, 64, 65, 511, 512, 513, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 9999, 10001, 30000):
         docs.append(rng.zipf(1.3, L).astype(np.int64) % V)
     docs.append(np.full(50_000, 7, np.int32))
     docs.append(np.arange(V, dtype=np.int32))
@@ -122,7 +123,7 @@ def _edge_corpus():
     rng = np.random.default_rng(4)
     V = 4096
     docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
-    for L in (1, 63, 64, 65, 511, 512, 513, 4095, 4096, 4097, 9999, 10001, 30000):
+    for L in (1, 63, 64, 65, 511, 512, 513, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 9999, 10001, 30000):
         docs.append(rng.zipf(1.3, L).astype(np.int64) % V)
     docs.append(np.full(50_000, 7, np.int32))
     docs += [rng.integers(0, V, int(rng.integers(0, 300))) for _ in range(200)]
