@@ -143,6 +143,9 @@ typedef struct {
  * memory the context itself allocates (scratch, models, databases); 0 means
  * 80% of the device's memory. */
 mrc_status mrc_ctx_create(mrc_ctx** out, int32_t device, size_t hbm_budget_bytes);
+/* Destroy a context. Models and databases created on it keep it alive: with
+ * any of them left, the context is freed when the last one is destroyed (no
+ * further calls on the context itself are allowed after this one). */
 mrc_status mrc_ctx_destroy(mrc_ctx* ctx);
 /* Device bytes currently allocated by the context (scratch + owned objects). */
 mrc_status mrc_ctx_memory(const mrc_ctx* ctx, size_t* used, size_t* budget);
@@ -168,6 +171,8 @@ const char* mrc_last_error(void);
  * tokens. */
 mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
                                const mrc_ref_spec* spec, mrc_model** out, void* hip_stream);
+/* Destroy a model (waits for the device). A model that a running server
+ * uses is freed when the last such server stops. */
 mrc_status mrc_model_destroy(mrc_model* model);
 /* Shape of a model: number of model documents, vocabulary, k, V' (listed
  * terms) and the selected positions [lo, hi). Any output may be NULL. */
@@ -274,6 +279,8 @@ mrc_status mrc_exact_cosine(mrc_ctx* ctx, const mrc_model* model, const mrc_docs
  * Ids are assigned in insertion order from 0; the database is append-only. */
 mrc_status mrc_db_create(mrc_ctx* ctx, int64_t capacity, int32_t k, uint32_t precisions,
                          mrc_db** out);
+/* Destroy a database (waits for the device). A database that a running
+ * server uses is freed when the last such server stops. */
 mrc_status mrc_db_destroy(mrc_db* db);
 /* Append n signatures (device float [n][k], raw or unit). first_id: host, may
  * be NULL. Errors: MRC_E_OVERFLOW when capacity would be exceeded. */
@@ -344,7 +351,8 @@ mrc_status mrc_serve_submit_many(mrc_server* srv, const int64_t* offsets, const 
 /* Fetch a result: MRC_OK with the result when done, MRC_E_BUSY while pending,
  * MRC_E_INVAL for an unknown ticket. wait_ms > 0 blocks up to that long. */
 mrc_status mrc_serve_poll(mrc_server* srv, uint64_t ticket, mrc_result* out, int32_t wait_ms);
-/* Drain outstanding requests and stop. */
+/* Drain outstanding requests and stop; frees the database and model too if
+ * they were destroyed while the server ran. */
 mrc_status mrc_serve_stop(mrc_server* srv);
 
 #ifdef __cplusplus
