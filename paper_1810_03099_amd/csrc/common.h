@@ -155,9 +155,10 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 mrc_status clear_words(mrc_ctx* ctx, int64_t* p, int n, hipStream_t s);
 
 // Clear the error word and check offsets on the device (kErrOffsets = bit 0);
-// the document kernels return at once when it is set. With `lists` (2n int32)
-// it also lists the medium documents in lists[0..) and the long ones in
-// lists[n..), their counts in ctx->d_flags[1] and [2].
+// the document kernels return at once when it is set. With `lists`
+// (kClasses n int32) it also lists the documents above kShortMax tokens by
+// length class, their counts in ctx->d_flags[kClassCount + c] (it clears
+// words 0 .. kClassCount + kClasses - 1 first).
 mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s, int32_t* lists = nullptr);
 
 // Distinct terms of each document of a corpus with their counts, at the
@@ -371,7 +372,14 @@ int mfma_chunks(int k);
 
 // Sizes of the length classes the document kernels use.
 constexpr int kShortMax = 512;    // one wavefront per document, LDS hash table
-constexpr int kMediumMax = 8192;  // one 256-thread workgroup per document, LDS hash table
+constexpr int kMidMax = 2048;     // one 256-thread workgroup per document: 4096-slot table
+constexpr int kMedMax = 4096;     //   ... 8192-slot table
+constexpr int kMediumMax = 8192;  //   ... 16384-slot table; longer documents: global tables
+// Documents above kShortMax are listed by length class (c = 0: up to kMidMax,
+// 1: kMedMax, 2: kMediumMax, 3: longer) in lists[c n ..), with the class
+// counts in context words kClassCount + c.
+constexpr int kClasses = 4;
+constexpr int kClassCount = 9;
 constexpr int kLongBlocks = 64;   // workgroups of the long-document pass (each owns a [V] table)
 constexpr int64_t kMaxDocLen = 1 << 22;  // longest document (exact 64/128-bit sums below this)
 

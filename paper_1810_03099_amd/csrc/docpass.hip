@@ -184,14 +184,15 @@ __device__ __forceinline__ void write_signature(const PassArgs& a, int64_t d, co
 // Offsets check before any token is read: offsets[0] = 0, non-decreasing,
 // offsets[n] <= n_tokens, no document longer than kMaxDocLen. Sets error bits;
 // the document kernels then return at once. With `lists` set, it also lists
-// the medium documents (kShortMax < L <= kMediumMax) in lists[0..) and the
-// long ones in lists[n..), with their counts in err[1] and err[2] (one atomic
-// per wavefront and class), so the medium and long kernels visit only theirs.
+// the documents above kShortMax tokens by length class (lists[c n ..), counts
+// in err[kClassCount + c], one atomic per wavefront and class), so that each
+// listed pass visits only its own documents.
 __global__ __launch_bounds__(256) void k_validate_offsets(const int64_t* __restrict__ off, int64_t n,
                                                           int64_t n_tokens, unsigned long long* __restrict__ err,
                                                           int32_t* __restrict__ lists) {
     const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool bad = false, too_long = false, med = false, lng = false;
+    bool bad = false, too_long = false;
+    int cls = -1;
     if (d <= n) {
         const int64_t o = off[d];
         if (d == 0) bad = o != 0;
@@ -200,8 +201,7 @@ __global__ __launch_bounds__(256) void k_validate_offsets(const int64_t* __restr
             bad = bad || o > n_tokens || o < 0;
         } else {
             const int64_t L = off[d + 1] - o;
-            med = L > kShortMax && L <= kMediumMax;
-            lng = L > kMediumMax;
+            cls = L <= kShortMax ? -1 : L <= kMidMax ? 0 : L <= kMedMax ? 1 : L <= kMediumMax ? 2 : 3;
             too_long = L > kMaxDocLen;
         }
     }
@@ -211,13 +211,13 @@ __global__ __launch_bounds__(256) void k_validate_offsets(const int64_t* __restr
     const int lane = __lane_id();
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const bool f = c == 0 ? med : lng;
+    for (int c = 0; c < kClasses; ++c) {
+        const bool f = cls == c;
         const unsigned long long m = __ballot(f);
         if (m == 0) continue;
         const int leader = __ffsll((long long)m) - 1;
         unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(err + 1 + c, (unsigned long long)__popcll(m));
+        if (lane == leader) base = atomicAdd(err + kClassCount + c, (unsigned long long)__popcll(m));
         base = __shfl(base, leader, 64);
         if (f) lists[(int64_t)c * n + (int64_t)base + __popcll(m & below)] = (int32_t)d;
     }
@@ -239,14 +239,15 @@ __host__ __device__ constexpr size_t team_lds_bytes(int kpad, int slots) {
     return (size_t)kpad * 8 + (size_t)slots * 9 + 16 + 64;
 }
 
-// Short (list == nullptr: every document with L <= hi_len) or medium (the
-// documents listed by k_validate_offsets, count in err[1]) documents.
+// Short (list == nullptr: every document with L <= hi_len) or listed (one
+// length class of k_validate_offsets, *count of them) documents.
 template <int MODE, int TEAM, int LOG2_SLOTS, int MAXPER>
 __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ off, int64_t n_docs,
                                                     int lo_len, int hi_len,
                                                     const int32_t* __restrict__ tok,
                                                     int32_t V, PassArgs a, unsigned long long* __restrict__ err,
-                                                    const int32_t* __restrict__ list) {
+                                                    const int32_t* __restrict__ list,
+                                                    const unsigned long long* __restrict__ count) {
     constexpr int SLOTS = 1 << LOG2_SLOTS;
     constexpr int TEAMS = kBlock / TEAM;
     extern __shared__ __align__(16) unsigned char smem[];
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     if (tid == 0) *nused = 0;
     team_sync<TEAM>();
 
-    const int64_t n_items = list ? (int64_t)__hip_atomic_load(err + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+    const int64_t n_items = list ? (int64_t)__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
                                  : n_docs;
     for (int64_t item = (int64_t)blockIdx.x * TEAMS + team; item < n_items; item += (int64_t)gridDim.x * TEAMS) {
         const int64_t d = list ? (int64_t)list[item] : item;
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
     }
 }
 
-// Long documents (listed by k_validate_offsets, count in err[2]): a [V]
+// Long documents (the last length class of k_validate_offsets): a [V]
 // uint32 count table per workgroup in global memory (all zero between
 // documents).
 template <int MODE>
@@ -374,7 +375,8 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
                                                        const int32_t* __restrict__ tok, PassArgs a,
                                                        uint32_t* __restrict__ tables,
                                                        unsigned long long* __restrict__ err,
-                                                       const int32_t* __restrict__ list) {
+                                                       const int32_t* __restrict__ list,
+                                                       const unsigned long long* __restrict__ count) {
     extern __shared__ __align__(16) unsigned char smem[];
     unsigned long long* bins = (unsigned long long*)smem;
     const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
@@ -385,7 +387,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
     if (pass_disabled(err)) return;
     for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
     __syncthreads();
-    const int64_t n_items = (int64_t)__hip_atomic_load(err + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int64_t n_items = (int64_t)__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
         const int64_t d = list[item];
         const int64_t o = off[d];
@@ -707,9 +709,7 @@ __global__ __launch_bounds__(256) void k_sign_counts(const int64_t* __restrict__
 // ------------------------------------------------------------------- driver
 
 constexpr int kShortTeam = 64, kShortLog2 = 10, kShortPer = kShortMax / 64;      // 1024 slots
-constexpr int kMidMax = 2048;                                                    // medium documents up to here:
 constexpr int kMidTeam = 256, kMidLog2 = 12, kMidPer = kMidMax / 256;            // 4096 slots, 4 workgroups per CU
-constexpr int kMedMax = 4096;
 constexpr int kMedTeam = 256, kMedLog2 = 13, kMedPer = kMedMax / 256;            // 8192 slots
 constexpr int kBigTeam = 256, kBigLog2 = 14, kBigPer = kMediumMax / 256;         // 16384 slots, 1 workgroup per CU
 static_assert((1 << kShortLog2) >= 2 * kShortMax, "short table load factor");
@@ -731,35 +731,36 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const Pass
     const int64_t n = docs->n_docs;
     unsigned long long* err = (unsigned long long*)ctx->d_flags;
     void* lists = nullptr;
-    if (n > 0) MRC_TRY(scratch(ctx, "doc_lists", (size_t)2 * (size_t)n * sizeof(int32_t), &lists));
+    if (n > 0) MRC_TRY(scratch(ctx, "doc_lists", (size_t)kClasses * (size_t)n * sizeof(int32_t), &lists));
     MRC_TRY(launch_validate_offsets(ctx, docs, s, (int32_t*)lists));
     if (n == 0) return MRC_OK;
-    const int32_t* med_list = (const int32_t*)lists;
-    const int32_t* long_list = med_list + n;
+    auto list = [&](int c) { return (const int32_t*)lists + (size_t)c * (size_t)n; };
+    auto count = [&](int c) { return (const unsigned long long*)err + kClassCount + c; };
     const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
     ScopedTimer tm(ctx, name, s);
     {
         const size_t lds = team_lds_bytes(kpad, 1 << kShortLog2) * (kBlock / kShortTeam);
         const int grid = grid_for(n, kBlock / kShortTeam, 256 * 8);
         hipLaunchKernelGGL((k_doc_lds<MODE, kShortTeam, kShortLog2, kShortPer>), dim3(grid), dim3(kBlock),
-                           lds, s, docs->offsets, n, 0, kShortMax, docs->tokens, V, a, err, nullptr);
+                           lds, s, docs->offsets, n, 0, kShortMax, docs->tokens, V, a, err, nullptr, nullptr);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
-        // the medium list in three passes by length: up to kMidMax tokens with
-        // 4096-slot tables (four workgroups per CU), up to kMedMax with 8192
-        // slots, up to kMediumMax with 16384 (147 KB: one workgroup per CU)
+        // the listed classes: up to kMidMax tokens with 4096-slot tables (four
+        // workgroups per CU), up to kMedMax with 8192 slots, up to kMediumMax
+        // with 16384 (147 KB: one workgroup per CU)
         const size_t lds_mid = team_lds_bytes(kpad, 1 << kMidLog2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kMidTeam, kMidLog2, kMidPer>), dim3(grid_for(n, 1, 256 * 4)), dim3(kBlock),
-                           lds_mid, s, docs->offsets, n, kShortMax, kMidMax, docs->tokens, V, a, err, med_list);
+                           lds_mid, s, docs->offsets, n, kShortMax, kMidMax, docs->tokens, V, a, err, list(0), count(0));
         MRC_HIP_TRY(ctx, hipGetLastError());
         const size_t lds = team_lds_bytes(kpad, 1 << kMedLog2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kMedTeam, kMedLog2, kMedPer>), dim3(grid_for(n, 1, 256 * 2)), dim3(kBlock),
-                           lds, s, docs->offsets, n, kMidMax, kMedMax, docs->tokens, V, a, err, med_list);
+                           lds, s, docs->offsets, n, kMidMax, kMedMax, docs->tokens, V, a, err, list(1), count(1));
         MRC_HIP_TRY(ctx, hipGetLastError());
         const size_t lds_big = team_lds_bytes(kpad, 1 << kBigLog2);
         hipLaunchKernelGGL((k_doc_lds<MODE, kBigTeam, kBigLog2, kBigPer>), dim3(grid_for(n, 1, 256)), dim3(kBlock),
-                           lds_big, s, docs->offsets, n, kMedMax, kMediumMax, docs->tokens, V, a, err, med_list);
+                           lds_big, s, docs->offsets, n, kMedMax, kMediumMax, docs->tokens, V, a, err, list(2),
+                           count(2));
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     {
@@ -771,7 +772,7 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const Pass
         if (fresh) MRC_HIP_TRY(ctx, hipMemsetAsync(tables, 0, ctx->scratch["long_tables"].second, s));
         const size_t lds = (size_t)kpad * 8 + 4 * sizeof(u128) + 16;
         hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets, V,
-                           docs->tokens, a, (uint32_t*)tables, err, long_list);
+                           docs->tokens, a, (uint32_t*)tables, err, list(3), count(3));
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     return MRC_OK;
@@ -788,7 +789,9 @@ mrc_status clear_words(mrc_ctx* ctx, int64_t* p, int n, hipStream_t s) {
 }
 
 mrc_status launch_validate_offsets(mrc_ctx* ctx, const mrc_docs* docs, hipStream_t s, int32_t* lists) {
-    MRC_TRY(clear_words(ctx, ctx->d_flags, 3, s));
+    // error word and, for the listed passes, the class counts (one launch:
+    // the words between them are free at this point of every caller)
+    MRC_TRY(clear_words(ctx, ctx->d_flags, lists ? kClassCount + kClasses : 1, s));
     const int64_t n = docs->n_docs;
     if (n == 0) return MRC_OK;
     hipLaunchKernelGGL(k_validate_offsets, dim3((unsigned)ceil_div(n + 1, 256)), dim3(256), 0, s, docs->offsets, n,
