@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--workload", default="plain_full", choices=["plain_full", "precision", "serving"],
                     help="plain_full: 20k docs, k=64 (default); precision: 200k docs, k=256; "
                          "serving: 1M-signature database, k=128, query stream")
+    ap.add_argument("--query-only", action="store_true",
+                    help="serving workload: build the database and time the mrc_query batches only")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
                     help="serving workload: length of each offered-load run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -535,6 +537,11 @@ def serving(a, mrc, synth, prec):
         batch[pname] = rows
         log(f"mrc_query {pname}: " + ", ".join(f"b={b} {r['ms']:.2f} ms" for b, r in rows.items()))
     out["query_batches"] = batch
+    if a.query_only:
+        b4 = batch[a.precision if a.precision in batch else "bf16"]["4096"]
+        out.update({"value": b4["pairs_per_s"], "unit": "pairs/s", "steps": 5, "warmup": 1, "ms_per_step": b4["ms"],
+                    "note": "value = query-row pairs/s of a 4096-query mrc_query batch (closed loop)"})
+        return out
     # serving loop: saturation (everything submitted at once), then Poisson arrivals
     srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=prec,
                               max_wait_us=500)
