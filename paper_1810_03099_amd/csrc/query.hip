@@ -200,23 +200,49 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
 #pragma unroll
             for (int x = 0; x < 4; ++x)
                 mx = fmaxf(mx, fmaxf(fmaxf(acc[g][x][0], acc[g][x][1]), fmaxf(acc[g][x][2], acc[g][x][3])));
-            const bool skip = MODE == MODE_TOP ? mx < ts[kTop - 1] : mx < thr[g];
-            if (skip || !qvalid[g]) continue;
+            if (MODE == MODE_TOP) {
+                if (mx < ts[kTop - 1] || !qvalid[g]) continue;
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
+                for (int x = 0; x < 4; ++x)
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int64_t row = row0 + 16 * x + 4 * lg + r;
-                    const float v = acc[g][x][r];
-                    const bool ok = row < a.rows;
-                    if (MODE == MODE_TOP) {
-                        if (ok && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1])) top_insert(ts, tid_, v, (int)row);
-                    } else if (ok && v >= thr[g]) {
-                        const int e = atomicAdd(&a.ccount[q[g]], 1);
-                        if (e < a.cap)
-                            a.cand[(int64_t)q[g] * a.cap + e] = ((int64_t)row << 32) | (int64_t)__float_as_uint(v);
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t row = row0 + 16 * x + 4 * lg + r;
+                        const float v = acc[g][x][r];
+                        if (row < a.rows && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1]))
+                            top_insert(ts, tid_, v, (int)row);
                     }
+            } else {
+                // candidates of this lane (bit 4x + r), counted per query over
+                // its 4 lanes (lane groups) so that one atomic reserves them all
+                uint32_t m = 0;
+                if (qvalid[g] && mx >= thr[g]) {
+#pragma unroll
+                    for (int x = 0; x < 4; ++x)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r)
+                            if (row0 + 16 * x + 4 * lg + r < a.rows && acc[g][x][r] >= thr[g]) m |= 1u << (4 * x + r);
                 }
+                if (__ballot(m != 0) == 0) continue;  // (wavefront-uniform)
+                const int cnt = __popc(m);
+                const int c0 = __shfl(cnt, li, 64), c1 = __shfl(cnt, li + 16, 64), c2 = __shfl(cnt, li + 32, 64),
+                          c3 = __shfl(cnt, li + 48, 64);
+                const int pre = (lg > 0 ? c0 : 0) + (lg > 1 ? c1 : 0) + (lg > 2 ? c2 : 0);
+                const int tot = c0 + c1 + c2 + c3;
+                int base = 0;
+                if (lg == 0 && tot > 0) base = atomicAdd(&a.ccount[q[g]], tot);
+                base = __shfl(base, li, 64) + pre;
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (m & (1u << (4 * x + r))) {
+                            if (base < a.cap)
+                                a.cand[(int64_t)q[g] * a.cap + base] =
+                                    ((int64_t)(row0 + 16 * x + 4 * lg + r) << 32) |
+                                    (int64_t)__float_as_uint(acc[g][x][r]);
+                            ++base;
+                        }
+            }
         }
     }
     if (MODE == MODE_COLLECT) return;
