@@ -367,6 +367,33 @@ __device__ __forceinline__ float chain_score(const float* __restrict__ qu, const
     return acc;
 }
 
+// The same chain with the query row in LDS and the database row read four
+// 16-component blocks per round trip (components in the same ascending order,
+// so the same bits as chain_score).
+__device__ __forceinline__ float chain_score_wide(const float* __restrict__ qu_lds, const float* __restrict__ dr,
+                                                  int k) {
+    float acc = 0.f;
+    for (int c0 = 0; c0 < k; c0 += 64) {
+        f32x4 blk[4][4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            if (c0 + 16 * b < k) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) blk[b][j] = *(const f32x4*)(dr + c0 + 16 * b + 4 * j);
+            }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int cb = c0 + 16 * b;
+            if (cb >= k) break;
+            const int m = min(16, k - cb);
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < m) acc = __builtin_fmaf(qu_lds[cb + c], blk[b][c & 3][c >> 2], acc);
+        }
+    }
+    return acc;
+}
+
 // E16[q]: the exact (chain) score of the 16th best of the query's 16 best rows
 // by the low-precision score (-inf with fewer than 16 rows). The exact 16th
 // best over all rows is at least this, so a row can only enter the exact
@@ -398,6 +425,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
     __shared__ float ss[4][kTop];
     __shared__ int si[4][kTop];
     __shared__ int shits;
+    __shared__ float qs[1024];  // the query's unit vector (k <= 1024)
     const int q = blockIdx.x;
     const int nc = ccount[q];
     if (nc > cap) {
@@ -405,6 +433,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
         return;
     }
     if (threadIdx.x == 0) shits = 0;
+    for (int c = threadIdx.x; c < k; c += 256) qs[c] = qunit[(int64_t)q * k + c];
     __syncthreads();
     float ts[kTop];
     int ti[kTop];
@@ -414,11 +443,10 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
         ti[p] = 0x7fffffff;
     }
     int hits = 0;
-    const float* qu = qunit + (int64_t)q * k;
     for (int e = threadIdx.x; e < nc; e += 256) {
         const int64_t pk = cand[(int64_t)q * cap + e];
         const int row = (int)(pk >> 32);
-        const float acc = chain_score(qu, db_umfma + (int64_t)row * kp, k);
+        const float acc = chain_score_wide(qs, db_umfma + (int64_t)row * kp, k);
         hits += acc >= tau ? 1 : 0;
         if (better(acc, row, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, acc, row);
     }
