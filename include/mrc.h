@@ -299,7 +299,8 @@ mrc_status mrc_db_load(mrc_ctx* ctx, const char* path, uint32_t precisions, mrc_
  * topk_out: device mrc_hit [n_queries][topk] (rows beyond the database size
  * get id -1); n_hits: device int32 [n_queries]. precision as in mrc_compare:
  * BF16/FP8 candidates are rescored in FP32 so results equal the FP32 ones.
- * The database snapshot is its size at call time. */
+ * The database snapshot is its size at call time. topk in [1, 16]; the
+ * database's k at most 512 (MRC_E_INVAL above, here and in mrc_serve_start). */
 mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, const mrc_docs* q,
                      int32_t topk, float tau, int32_t precision, mrc_hit* topk_out,
                      int32_t* n_hits, void* hip_stream);

@@ -380,6 +380,9 @@ constexpr int kMediumMax = 8192;  //   ... 16384-slot table; longer documents: g
 // counts in context words kClassCount + c.
 constexpr int kClasses = 4;
 constexpr int kClassCount = 9;
+// Largest signature length of queries against a database (the query scans are
+// instantiated up to 32 FP32 / 16 BF16 chunks).
+constexpr int kQueryMaxK = 512;
 constexpr int kLongBlocks = 64;   // workgroups of the long-document pass (each owns a [V] table)
 constexpr int64_t kMaxDocLen = 1 << 22;  // longest document (exact 64/128-bit sums below this)
 

@@ -262,6 +262,7 @@ mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, con
     if (!db || !model || !q || !q->offsets) return fail(MRC_E_INVAL, "mrc_query: NULL argument");
     if (model->k != db->k) return fail(MRC_E_INVAL, "mrc_query: model and database differ in k");
     if (topk < 1 || topk > 16) return fail(MRC_E_INVAL, "mrc_query: topk must lie in [1, 16]");
+    if (db->k > kQueryMaxK) return fail(MRC_E_INVAL, "mrc_query: queries support k <= 512");
     if (precision < MRC_PREC_FP32 || precision > MRC_PREC_FP8) return fail(MRC_E_INVAL, "mrc_query: bad precision");
     if (q->n_docs < 0 || q->n_docs > (1 << 20)) return fail(MRC_E_INVAL, "mrc_query: n_docs outside [0, 2^20]");
     if (q->n_docs > 0 && (!topk_out || !n_hits)) return fail(MRC_E_INVAL, "mrc_query: NULL output");

@@ -180,6 +180,7 @@ mrc_status mrc_serve_start(mrc_ctx* ctx, mrc_db* db, const mrc_model* model, con
     if (!ctx || !db || !model || !opts || !out) return fail(MRC_E_INVAL, "mrc_serve_start: NULL argument");
     *out = nullptr;
     if (model->k != db->k) return fail(MRC_E_INVAL, "mrc_serve_start: model and database differ in k");
+    if (db->k > kQueryMaxK) return fail(MRC_E_INVAL, "mrc_serve_start: queries support k <= 512");
     if (opts->max_batch < 1 || opts->max_batch > 4096 || opts->n_streams < 1 || opts->n_streams > 4 ||
         opts->topk < 1 || opts->topk > 16 || opts->precision < MRC_PREC_FP32 || opts->precision > MRC_PREC_FP8 ||
         !(opts->hbm_frac > 0.0 && opts->hbm_frac <= 1.0) || opts->max_queue < 1 || opts->max_batch_tokens < 1 ||

@@ -96,6 +96,39 @@ def test_query_prefix_threshold_exact(lib, ctx, nq):
     flush(f"  nq={nq}: 20,000 rows, prefix threshold, all forms == exact chain; mean hits {whits.mean():.2f}")
 
 
+@pytest.mark.parametrize("k", [100, 512])
+def test_query_k_shapes(lib, ctx, k):
+    # k = 100: partial 16-component blocks in every layout; k = 512: the
+    # largest query length (32 FP32 chunks, 16 BF16, 4 FP8)
+    dbc = synth.generate(2, n_docs=2500)
+    qc = synth.generate_queries(synth.CONFIGS[2], 70, seed=9 + k, median=400, sigma=1.2, hi=6000, near_of=dbc,
+                                near_frac=0.4)
+    o, t = device_docs(dbc)
+    model = lib.mrc_build_vocab_idf(ctx, o, t, dbc.vocab, lib.ref_spec(k))
+    db = lib.mrc_db_create(ctx, dbc.n_docs, k)
+    lib.mrc_db_insert_docs(db, model, o, t)
+    qo, qt = device_docs(qc)
+    dbunit = lib.mrc_normalise(ctx, lib.mrc_sign(ctx, model, o, t))["unit"].cpu().numpy()
+    qunit = lib.mrc_normalise(ctx, lib.mrc_sign(ctx, model, qo, qt))["unit"].cpu().numpy()
+    wids, wsc, whits = chain_topk(qunit, dbunit, 16, TAU)
+    for p in (lib.PREC_FP32, lib.PREC_BF16, lib.PREC_FP8):
+        ids, sc, hits = lib.mrc_query(ctx, db, model, qo, qt, 16, TAU, p)
+        np.testing.assert_array_equal(ids.cpu().numpy(), wids)
+        np.testing.assert_array_equal(sc.cpu().numpy().view(np.uint32), wsc.view(np.uint32))
+        np.testing.assert_array_equal(hits.cpu().numpy(), whits)
+
+
+def test_query_k_above_limit_rejected(lib, ctx):
+    dbc = synth.generate(2, n_docs=300)
+    o, t = device_docs(dbc)
+    model = lib.mrc_build_vocab_idf(ctx, o, t, dbc.vocab, lib.ref_spec(600))
+    db = lib.mrc_db_create(ctx, 400, 600)
+    lib.mrc_db_insert_docs(db, model, o, t)
+    with pytest.raises(lib.MrcError) as e:
+        lib.mrc_query(ctx, db, model, o, t, 16, TAU)
+    assert e.value.status == lib.MRC_E_INVAL
+
+
 def test_query_vs_fp64_oracle(lib, ctx, setup):
     dbc, qc = setup["dbc"], setup["qc"]
     omodel = om.build_model(dbc.offsets, dbc.tokens, dbc.vocab, om.RefSpec(k=64))
