@@ -17,7 +17,7 @@ def require_gpu():
         pytest.skip("no GPU")
     from paper_1810_03099_amd import mrc
     if not os.path.exists(mrc.LIB_PATH):
-        # on a GPU machine the product must be there: fail loudly, never fall back
+        # with a GPU present the product must be there: fail loudly, never fall back
         raise RuntimeError(f"{mrc.LIB_PATH} missing: the HIP library must be built before GPU tests")
     return mrc
 
