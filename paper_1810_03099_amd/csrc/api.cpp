@@ -457,7 +457,9 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
         const float* err_p = (const float*)err + (prec == MRC_PREC_BF16 ? 0 : n_pad);
         float* d_lo = (float*)(ctx->d_flags + 22);
         if (n >= 2) {
-            MRC_TRY(launch_lowp_threshold(ctx, prec, err_p, n, opts->tau, opts->band, k, d_lo, s));
+            // (word 23: zeroed with the others above, the largest row error)
+            MRC_TRY(launch_lowp_threshold(ctx, prec, err_p, n, opts->tau, opts->band, k,
+                                          (unsigned int*)(ctx->d_flags + 23), d_lo, s));
             PairSink cs{(mrc_pair*)cand, cand_cap, (unsigned long long*)(ctx->d_flags + 16)};
             MRC_TRY(launch_compare_lowp(ctx, prec, (const uint8_t*)q, ldq * ebytes, (const float*)scale, n, k, d_lo,
                                         cs, s));

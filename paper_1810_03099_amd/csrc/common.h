@@ -229,7 +229,7 @@ mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q
                                PairSink cand, hipStream_t s);
 float lowp_acc_unit(int precision, int k);
 mrc_status launch_lowp_threshold(mrc_ctx* ctx, int precision, const float* err, int64_t n, float tau,
-                                 float nominal, int k, float* d_out, hipStream_t s);
+                                 float nominal, int k, unsigned int* d_emax, float* d_out, hipStream_t s);
 mrc_status launch_rescore2(mrc_ctx* ctx, int precision, const mrc_pair* cand, const unsigned long long* n_cand,
                            int64_t cand_cap, const float* unit, int32_t k, const float* err, float tau, float nominal,
                            PairSink out, unsigned long long* stats, hipStream_t s);

@@ -303,19 +303,21 @@ __device__ __forceinline__ float lowp_band(float ei, float ej, float nominal, fl
     return fmaxf(nominal, b);
 }
 
-__global__ __launch_bounds__(1024) void k_lowp_threshold(const float* __restrict__ err, int64_t n, float tau,
-                                                         float nominal, float acc_unit, float* __restrict__ out) {
-    __shared__ float red[16];
+// lo_thr in two steps: the largest row error (blocks over the rows, one
+// atomic max of the float bits per wavefront into a zeroed word), then the band.
+__global__ __launch_bounds__(256) void k_lowp_errmax(const float* __restrict__ err, int64_t n,
+                                                     unsigned int* __restrict__ emax) {
     float m = 0.f;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmaxf(m, err[i]);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        m = fmaxf(m, err[i]);
     m = mrc_dev::wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float e = 0.f;
-        for (int w = 0; w < 16; ++w) e = fmaxf(e, red[w]);
-        out[0] = tau - lowp_band(e, e, nominal, acc_unit);
-    }
+    if ((threadIdx.x & 63) == 0) atomicMax(emax, __float_as_uint(m));  // non-negative floats order like their bits
+}
+
+__global__ void k_lowp_threshold(const unsigned int* __restrict__ emax, float tau, float nominal, float acc_unit,
+                                 float* __restrict__ out) {
+    const float e = __uint_as_float(*emax);
+    out[0] = tau - lowp_band(e, e, nominal, acc_unit);
 }
 
 // Rescoring: every candidate with |s_lp - tau| <= band(e_i, e_j) gets the plain
@@ -514,8 +516,10 @@ float lowp_acc_unit(int precision, int k) {
 }
 
 mrc_status launch_lowp_threshold(mrc_ctx* ctx, int precision, const float* err, int64_t n, float tau,
-                                 float nominal, int k, float* d_out, hipStream_t s) {
-    hipLaunchKernelGGL(k_lowp_threshold, dim3(1), dim3(1024), 0, s, err, n, tau, nominal,
+                                 float nominal, int k, unsigned int* d_emax, float* d_out, hipStream_t s) {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n, 256), 1024));
+    hipLaunchKernelGGL(k_lowp_errmax, dim3((unsigned)blocks), dim3(256), 0, s, err, n, d_emax);
+    hipLaunchKernelGGL(k_lowp_threshold, dim3(1), dim3(1), 0, s, (const unsigned int*)d_emax, tau, nominal,
                        lowp_acc_unit(precision, k), d_out);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;

@@ -207,20 +207,31 @@ __global__ __launch_bounds__(256) void k_validate_offsets(const int64_t* __restr
     }
     if (bad) atomicOr(err, kErrOffsets);
     if (too_long) atomicOr(err, kErrDocLen);
-    if (lists == nullptr) return;
+    if (lists == nullptr) return;  // (kernel argument: the whole grid returns)
+    // a wavefront's members of each class take consecutive slots of the
+    // workgroup's share (LDS), which one global atomic per class reserves
+    __shared__ unsigned int wg_cnt[kClasses];
+    __shared__ unsigned long long wg_base[kClasses];
+    if (threadIdx.x < kClasses) wg_cnt[threadIdx.x] = 0u;
+    __syncthreads();
     const int lane = __lane_id();
     const unsigned long long below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    unsigned int off_c[kClasses];
 #pragma unroll
     for (int c = 0; c < kClasses; ++c) {
-        const bool f = cls == c;
-        const unsigned long long m = __ballot(f);
-        if (m == 0) continue;
-        const int leader = __ffsll((long long)m) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(err + kClassCount + c, (unsigned long long)__popcll(m));
-        base = __shfl(base, leader, 64);
-        if (f) lists[(int64_t)c * n + (int64_t)base + __popcll(m & below)] = (int32_t)d;
+        const unsigned long long m = __ballot(cls == c);
+        unsigned int o = 0u;
+        if (m != 0 && lane == __ffsll((long long)m) - 1) o = atomicAdd(&wg_cnt[c], (unsigned int)__popcll(m));
+        off_c[c] = m != 0 ? __shfl(o, __ffsll((long long)m) - 1, 64) + (unsigned int)__popcll(m & below) : 0u;
     }
+    __syncthreads();
+    if (threadIdx.x < kClasses)
+        wg_base[threadIdx.x] =
+            wg_cnt[threadIdx.x] ? atomicAdd(err + kClassCount + threadIdx.x, (unsigned long long)wg_cnt[threadIdx.x]) : 0ull;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < kClasses; ++c)
+        if (cls == c) lists[(int64_t)c * n + (int64_t)(wg_base[c] + off_c[c])] = (int32_t)d;
 }
 
 __global__ void k_clear_words(int64_t* __restrict__ p, int n) {
