@@ -326,7 +326,36 @@ __global__ void k_lowp_threshold(const unsigned int* __restrict__ emax, float ta
 // workgroup in LDS and reserved in the output with one atomic per workgroup.
 // stats: [0] rescored, [1] rescored within nominal, [2] flips outside nominal,
 // [3] max |s_lp - s32| (float bits), [4] sum |s_lp - s32| (double bits).
-constexpr int kRescoreChunk = 2048;
+constexpr int kRescoreChunk = 256;  // one candidate per thread and pass
+
+// The plain chain of two natural-order rows; `wide` (the caller's rows are
+// 16-byte aligned: k a multiple of 4 and an aligned base) reads 16 components
+// per round trip, in the same ascending order as the scalar loop.
+__device__ __forceinline__ float chain_rows(const float* __restrict__ a, const float* __restrict__ b, int k, bool wide) {
+    float acc = 0.f;
+    if (wide) {
+        for (int c0 = 0; c0 < k; c0 += 16) {
+            float4 va[4], vb[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c0 + 4 * j < k) {
+                    va[j] = *(const float4*)(a + c0 + 4 * j);
+                    vb[j] = *(const float4*)(b + c0 + 4 * j);
+                }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (c0 + 4 * j < k) {
+                    acc = __builtin_fmaf(va[j].x, vb[j].x, acc);
+                    acc = __builtin_fmaf(va[j].y, vb[j].y, acc);
+                    acc = __builtin_fmaf(va[j].z, vb[j].z, acc);
+                    acc = __builtin_fmaf(va[j].w, vb[j].w, acc);
+                }
+        }
+        return acc;
+    }
+    for (int cc = 0; cc < k; ++cc) acc = __builtin_fmaf(a[cc], b[cc], acc);
+    return acc;
+}
 
 __global__ __launch_bounds__(256) void k_rescore(const mrc_pair* __restrict__ cand,
                                                  const unsigned long long* __restrict__ n_cand_ptr,
@@ -360,10 +389,7 @@ __global__ __launch_bounds__(256) void k_rescore(const mrc_pair* __restrict__ ca
             } else if (p.s < tau - band) {
                 keep = false;
             } else {
-                const float* a = unit + (int64_t)p.i * k;
-                const float* b = unit + (int64_t)p.j * k;
-                float acc = 0.f;
-                for (int cc = 0; cc < k; ++cc) acc = __builtin_fmaf(a[cc], b[cc], acc);
+                const float acc = chain_rows(unit + (int64_t)p.i * k, unit + (int64_t)p.j * k, k, (k & 3) == 0);
                 keep = acc >= tau;
                 const float d = fabsf(p.s - acc);
                 atomicAdd(&s_nb, 1ull);
@@ -398,14 +424,10 @@ __global__ __launch_bounds__(256) void k_rescore(const mrc_pair* __restrict__ ca
 
 // Plain score of listed pairs (one thread per pair, same chain).
 __global__ void k_score_pairs(const float* __restrict__ u, int k, const int32_t* __restrict__ ii,
-                              const int32_t* __restrict__ jj, int64_t np, float* __restrict__ out) {
+                              const int32_t* __restrict__ jj, int64_t np, float* __restrict__ out, bool wide) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= np) return;
-    const float* a = u + (int64_t)ii[p] * k;
-    const float* b = u + (int64_t)jj[p] * k;
-    float acc = 0.f;
-    for (int c = 0; c < k; ++c) acc = __builtin_fmaf(a[c], b[c], acc);
-    out[p] = acc;
+    out[p] = chain_rows(u + (int64_t)ii[p] * k, u + (int64_t)jj[p] * k, k, wide);
 }
 
 }  // namespace
@@ -538,8 +560,9 @@ mrc_status launch_rescore2(mrc_ctx* ctx, int precision, const mrc_pair* cand, co
 mrc_status launch_score_pairs(mrc_ctx* ctx, const float* unit, int32_t k, const int32_t* ii,
                               const int32_t* jj, int64_t n_pairs, float* out, hipStream_t s) {
     if (n_pairs == 0) return MRC_OK;
+    const bool wide = (k & 3) == 0 && ((uintptr_t)unit & 15) == 0;
     hipLaunchKernelGGL(k_score_pairs, dim3((unsigned)ceil_div(n_pairs, 256)), dim3(256), 0, s, unit, k, ii, jj,
-                       n_pairs, out);
+                       n_pairs, out, wide);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }
