@@ -521,6 +521,164 @@ __global__ void k_max_err(const float* __restrict__ db_max, const float* __restr
     }
 }
 
+// Collection for large batches: the 4 wavefronts of a workgroup each hold G
+// query groups and read the same 64-row database tile from LDS, so a tile
+// comes from memory once per 64 G queries. Tiles are staged through
+// registers into a second LDS buffer while the current one is used; one
+// workgroup barrier per tile (every wavefront walks the same tiles).
+constexpr int kLdsRowMax = 1024;  // bytes per database row this kernel stages
+
+template <int PREC, int NK, int G>
+__global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
+    using T = QT<PREC>;
+    constexpr int ROW = NK * T::kChunkBytes;  // bytes per database row (= a.ld_db)
+    constexpr int LD = ROW + 16;              // padded LDS row
+    constexpr int PIECES = ROW / 16;          // 16-byte pieces per row
+    constexpr int PER = kTileRows * PIECES / 256;
+    static_assert(ROW <= kLdsRowMax && (kTileRows * PIECES) % 256 == 0, "tile staging shape");
+    __shared__ __align__(16) uint8_t buf[2][kTileRows * LD];
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    typename T::F qb[G][NK];
+    int q[G];
+    bool qvalid[G];
+    float qsc[G], thr[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        q[g] = ((blockIdx.y * 4 + wave) * G + g) * 16 + li;  // rows of the padded query arrays
+        qvalid[g] = q[g] < a.nq;
+        const uint8_t* pq = a.q + (int64_t)q[g] * a.ld_q + lg * T::kLaneBytes;
+#pragma unroll
+        for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
+        qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
+        thr[g] = qvalid[g] ? a.thr[q[g]] : 0.f;
+    }
+    const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
+    // staging: thread piece j is 16 bytes at (row, column) of the tile
+    i32x4 st[PER];
+    int64_t t = blockIdx.x;
+    if (t < n_tiles) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
+            st[j] = *(const i32x4*)(a.db + (t * kTileRows + r) * a.ld_db + c * 16);  // rows padded to 64
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
+            *(i32x4*)(&buf[0][r * LD + c * 16]) = st[j];
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    for (; t < n_tiles; t += gridDim.x) {
+        const int64_t tn = t + gridDim.x;
+        const bool more = tn < n_tiles;
+        // the next tile's loads overlap this tile's products (without a next
+        // tile: this one again, valid and unused, so that nothing branches
+        // around the staged values)
+        const int64_t tl = more ? tn : t;
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
+            st[j] = *(const i32x4*)(a.db + (tl * kTileRows + r) * a.ld_db + c * 16);
+        }
+        const int64_t row0 = t * kTileRows;
+        const uint8_t* pa = &buf[cur][li * LD + lg * T::kLaneBytes];
+        f32x4 acc[G][4];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int x = 0; x < 4; ++x) acc[g][x] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int c = 0; c < NK; ++c) {
+            typename T::F fa[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) fa[x] = T::load(pa + 16 * x * LD + c * T::kChunkBytes);
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int x = 0; x < 4; ++x) acc[g][x] = T::mma(fa[x], qb[g][c], acc[g][x]);
+        }
+        if (PREC == MRC_PREC_FP8) {
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const f32x4 sc = *(const f32x4*)(a.db_scale + row0 + 16 * x + 4 * lg);
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc[g][x][r] = acc[g][x][r] * sc[r] * qsc[g];
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            float mx = -INFINITY;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+                mx = fmaxf(mx, fmaxf(fmaxf(acc[g][x][0], acc[g][x][1]), fmaxf(acc[g][x][2], acc[g][x][3])));
+            uint32_t m = 0;
+            if (qvalid[g] && mx >= thr[g]) {
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (row0 + 16 * x + 4 * lg + r < a.rows && acc[g][x][r] >= thr[g]) m |= 1u << (4 * x + r);
+            }
+            if (__ballot(m != 0) == 0) continue;  // (wavefront-uniform)
+            const int cnt = __popc(m);
+            const int c0 = __shfl(cnt, li, 64), c1 = __shfl(cnt, li + 16, 64), c2 = __shfl(cnt, li + 32, 64),
+                      c3 = __shfl(cnt, li + 48, 64);
+            const int pre = (lg > 0 ? c0 : 0) + (lg > 1 ? c1 : 0) + (lg > 2 ? c2 : 0);
+            const int tot = c0 + c1 + c2 + c3;
+            int base = 0;
+            if (lg == 0 && tot > 0) base = atomicAdd(&a.ccount[q[g]], tot);
+            base = __shfl(base, li, 64) + pre;
+#pragma unroll
+            for (int x = 0; x < 4; ++x)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (m & (1u << (4 * x + r))) {
+                        if (base < a.cap)
+                            a.cand[(int64_t)q[g] * a.cap + base] = ((int64_t)(row0 + 16 * x + 4 * lg + r) << 32) |
+                                                                   (int64_t)__float_as_uint(acc[g][x][r]);
+                        ++base;
+                    }
+        }
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {  // (after the last tile: written, never read)
+            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
+            *(i32x4*)(&buf[cur ^ 1][r * LD + c * 16]) = st[j];
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+}
+
+template <int PREC, int G, int NK>
+bool launch_collect_lds_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
+    if constexpr (NK * QT<PREC>::kChunkBytes <= kLdsRowMax && G * NK * QT<PREC>::kLaneBytes / 4 <= 128) {
+        hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G>), grid, dim3(256), 0, s, a);
+        return true;
+    } else {
+        return false;
+    }
+}
+
+// false: no instantiation for this shape (the caller uses k_query_scan)
+template <int PREC, int G>
+bool launch_collect_lds(int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+#define MRC_Q(c) case c: return launch_collect_lds_nk<PREC, G, c>(a, grid, s);
+    if constexpr (PREC == MRC_PREC_FP32) {
+        switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) default: return false; }
+    } else if constexpr (PREC == MRC_PREC_BF16) {
+        switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(10) MRC_Q(12) MRC_Q(16) default: return false; }
+    } else {
+        switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) default: return false; }
+    }
+#undef MRC_Q
+}
+
 // G query groups per wavefront when their fragments fit in 128 registers.
 template <int PREC, int MODE, int G, int NK>
 bool launch_scan_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
@@ -575,7 +733,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     const int64_t nq = qd->n_docs;
     const int k = db->k;
     const DbLayout L = db_layout(k);
-    const int64_t nq_pad = ceil_div(nq > 0 ? nq : 1, 64) * 64;
+    const int64_t nq_pad = ceil_div(nq > 0 ? nq : 1, 256) * 256;  // whole query blocks of every scan
     // sign and normalise the queries into every layout the scan needs
     void *sig, *unit, *umf, *qb, *q8, *qsc, *qerr;
     MRC_TRY(scratch(ctx, "q_sig", (size_t)nq_pad * k * 4, &sig));
@@ -665,7 +823,34 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     int g = nq <= 16 ? 1 : nq <= 48 ? 2 : 4;
     while (g > 1 && g * nk * lane_regs > 128) g /= 2;
     a.rows = rows;
-    const dim3 g2 = grid_for_rows(rows, ceil_div(nq, 16 * g));
+    // batches above 64 queries: the LDS-shared form (64 g queries per
+    // workgroup, all four wavefronts on the same tiles) where it is built
+    const bool lds_form = nq > 64;
+    dim3 g2 = grid_for_rows(rows, ceil_div(nq, 16 * g));
+    if (lds_form) {
+        const int64_t tiles = std::max<int64_t>(1, ceil_div(rows, kTileRows));
+        const int64_t groups = ceil_div(nq, 64 * g);
+        g2 = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), tiles)), (unsigned)groups);
+    }
+    auto collect = [&]() -> mrc_status {
+        if (lds_form) {
+            bool ok;
+            if (fp32) ok = g == 4 ? launch_collect_lds<MRC_PREC_FP32, 4>(nk, a, g2, s)
+                         : g == 2 ? launch_collect_lds<MRC_PREC_FP32, 2>(nk, a, g2, s)
+                                  : launch_collect_lds<MRC_PREC_FP32, 1>(nk, a, g2, s);
+            else if (bf) ok = g == 4 ? launch_collect_lds<MRC_PREC_BF16, 4>(nk, a, g2, s)
+                            : g == 2 ? launch_collect_lds<MRC_PREC_BF16, 2>(nk, a, g2, s)
+                                     : launch_collect_lds<MRC_PREC_BF16, 1>(nk, a, g2, s);
+            else ok = g == 4 ? launch_collect_lds<MRC_PREC_FP8, 4>(nk, a, g2, s)
+                    : g == 2 ? launch_collect_lds<MRC_PREC_FP8, 2>(nk, a, g2, s)
+                             : launch_collect_lds<MRC_PREC_FP8, 1>(nk, a, g2, s);
+            if (ok) {
+                MRC_HIP_TRY(ctx, hipGetLastError());
+                return MRC_OK;
+            }
+        }
+        return scan(MODE_COLLECT, g, grid_for_rows(rows, ceil_div(nq, 16 * g)));
+    };
     int cap = 2048;
     auto it = ctx->scratch.find("q_cand");
     if (it != ctx->scratch.end()) cap = std::max<int64_t>(cap, (int64_t)(it->second.second / 8 / nq));
@@ -678,7 +863,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         a.cand = (int64_t*)cand;
         a.ccount = (int32_t*)cc;
         a.cap = cap;
-        MRC_TRY(scan(MODE_COLLECT, g, g2));
+        MRC_TRY(collect());
         hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)cand,
                            (const int32_t*)cc, cap, (const float*)unit, k, db->d_unit, L.kp, tau, topk, topk_out,
                            n_hits, fp32 ? 0 : 1, (unsigned long long*)ctx->d_flags);
