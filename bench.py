@@ -56,9 +56,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16", "fp8"])
-    ap.add_argument("--workload", default="plain_full", choices=["plain_full", "precision", "serving"],
+    ap.add_argument("--workload", default="plain_full", choices=["plain_full", "precision", "serving", "sweep"],
                     help="plain_full: 20k docs, k=64 (default); precision: 200k docs, k=256; "
-                         "serving: 1M-signature database, k=128, query stream")
+                         "serving: 1M-signature database, k=128, query stream; sweep: reference "
+                         "selection x k on the 20k-document corpus (accuracy and time curves)")
     ap.add_argument("--query-only", action="store_true",
                     help="serving workload: build the database and time the mrc_query batches only")
     ap.add_argument("--serve-seconds", type=float, default=4.0,
@@ -152,6 +153,9 @@ def main():
     prec = {"fp32": mrc.PREC_FP32, "bf16": mrc.PREC_BF16, "fp8": mrc.PREC_FP8}[a.precision]
     if a.workload == "serving":
         print(json.dumps(serving(a, mrc, synth, prec)))
+        return
+    if a.workload == "sweep":
+        print(json.dumps(sweep(mrc, synth)))
         return
     spec_idx = 1 if a.workload == "plain_full" else 2
     cs = synth.CONFIGS[spec_idx]
@@ -271,6 +275,107 @@ def main():
         out["extras"] = extras(mrc, ctx, c, off, tok, sig, state["model"], k, tau, cap, sign_ms,
                                ktimes.get("sign_counts", {}).get("avg_ms"))
     print(json.dumps(out))
+
+
+SWEEP_KS = (8, 16, 32, 64, 128, 256, 512, 1024)
+
+
+def count_flagged(mrc, ctx, sig, tau):
+    """Number of FP32-flagged pairs, from the two-call protocol's count alone."""
+    import ctypes
+    import torch
+    n, k = sig.shape
+    opts = mrc.MrcCompareOpts(float(tau), mrc.PREC_FP32, 0.02, 0)
+    found = ctypes.c_int64()
+    st = mrc.lib().mrc_compare(ctx, ctypes.c_void_p(sig.data_ptr()), int(n), int(k), ctypes.byref(opts), None, 0,
+                               ctypes.byref(found), None,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    if st not in (mrc.MRC_OK, mrc.MRC_E_OVERFLOW):
+        raise RuntimeError("mrc_compare: " + mrc.lib().mrc_last_error().decode(errors="replace"))
+    return int(found.value)
+
+
+def sweep(mrc, synth):
+    """Reference selection x k (the paper's experiments over reference regions and
+    partition counts, Sections 4-5) on the 20,000-document corpus: for each
+    selection and k, the time of model build + signing and of the FP32 all-pairs
+    comparison, the flagged count, recall and precision against exact TF-IDF
+    cosine at tau, and MAE / variance (Eqs. 2-3, as read: mean |MRC - cos| and
+    the variance of MRC - cos) over all pairs of the first 2,000 documents.
+
+    Flagged sets are never materialised: the comparison reports its count, and
+    the true positives are the exact-cosine pairs whose MRC score (the same
+    float32 chain the comparison decides with) reaches tau."""
+    import torch
+    cs = synth.CONFIGS[1]
+    tau = cs.tau
+    c = synth.generate(1)
+    n = c.n_docs
+    torch.cuda.set_device(0)
+    off = torch.from_numpy(c.offsets).cuda()
+    tok = torch.from_numpy(c.tokens).cuda()
+    sub = c.subset(np.arange(2000))
+    so = torch.from_numpy(sub.offsets).cuda()
+    st_ = torch.from_numpy(sub.tokens).cuda()
+    ctx = mrc.mrc_ctx_create(0)
+    log("sweep: exact cosine")
+    # idf does not depend on the selection: one model serves the exact comparator
+    m0, _ = mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(8, mode=mrc.SEL_ALL))
+    v_listed = mrc.mrc_model_info(m0)["n_listed"]
+    ep = mrc.mrc_exact_cosine(ctx, m0, off, tok, tau, capacity=4 * 1024 * 1024)
+    ei = ep[:, 0].contiguous()
+    ej = ep[:, 1].contiguous()
+    n_exact = int(ep.shape[0])
+    sp = mrc.mrc_exact_cosine(ctx, m0, so, st_, -2.0, capacity=2000 * 1999 // 2 + 16)
+    si = sp[:, 0].contiguous()
+    sj = sp[:, 1].contiguous()
+    scos = sp[:, 2].cpu().numpy().view(np.float32).astype(np.float64)
+    del m0
+    sels = [("all", dict(mode=mrc.SEL_ALL)),
+            ("drop_top_5pct", dict(mode=mrc.SEL_DROP_TOP)),
+            ("frequent_half", dict(mode=mrc.SEL_REGION, lo=0, hi=v_listed // 2)),
+            ("rare_half", dict(mode=mrc.SEL_REGION, lo=v_listed // 2, hi=v_listed)),
+            ("rarest_10pct", dict(mode=mrc.SEL_RAREST, m=v_listed // 10))]
+    rows = []
+    for name, kw in sels:
+        for k in SWEEP_KS:
+            spec = mrc.ref_spec(k, **kw)
+            sig = torch.empty((n, k), dtype=torch.float32, device="cuda")
+            mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, spec, sig_out=sig)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                model, _ = mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, spec, sig_out=sig)
+            torch.cuda.synchronize()
+            sign_ms = (time.perf_counter() - t0) / 3 * 1e3
+            info = mrc.mrc_model_info(model)
+            flagged = count_flagged(mrc, ctx, sig, tau)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                count_flagged(mrc, ctx, sig, tau)
+            torch.cuda.synchronize()
+            cmp_ms = (time.perf_counter() - t0) / 3 * 1e3
+            unit = mrc.mrc_normalise(ctx, sig)["unit"]
+            tp = int((mrc.mrc_score_pairs(ctx, unit, ei, ej) >= tau).sum().item()) if n_exact else 0
+            usub = unit[:2000].contiguous()
+            e = mrc.mrc_score_pairs(ctx, usub, si, sj).double().cpu().numpy() - scos
+            zero = int((sig.abs().sum(dim=1) == 0).sum().item())
+            rows.append({"selection": name, "k": k, "m": int(info["hi"] - info["lo"]), "sign_ms": sign_ms,
+                         "compare_ms": cmp_ms, "flagged": flagged,
+                         "recall": tp / n_exact if n_exact else 1.0,
+                         "precision": tp / flagged if flagged else 1.0,
+                         "mae": float(np.abs(e).mean()), "variance": float(((e - e.mean()) ** 2).mean()),
+                         "zero_signatures": zero})
+            r = rows[-1]
+            log(f"sweep {name:14s} k={k:5d} m={r['m']:7d} sign {sign_ms:7.3f} ms  compare {cmp_ms:7.3f} ms  "
+                f"flagged {flagged:10d}  recall {r['recall']:.4f}  precision {r['precision']:.4f}  "
+                f"mae {r['mae']:.4f}  var {r['variance']:.5f}")
+            del model, sig, unit, usub
+    return {"workload": "sweep", "data": "synthetic",
+            "config": {"workload": cs.name, "docs": n, "vocab": c.vocab, "listed_terms": int(v_listed), "tau": tau,
+                       "ks": list(SWEEP_KS), "mae_sample": "all pairs of the first 2,000 documents"},
+            "exact_cosine_flagged": n_exact, "rows": rows}
 
 
 def fp64_unit(sig):

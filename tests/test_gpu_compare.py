@@ -73,6 +73,41 @@ def test_fp32_decisions_equal_the_chain_and_the_oracle(lib, ctx, cfg, n_docs, k)
     flush(f"    flagged={gi.size} near-ties excluded={int((~far).sum())}")
 
 
+@pytest.mark.parametrize("mode,k", [("all", 8), ("frequent_half", 512), ("rare_half", 1024), ("rarest", 1024),
+                                    ("drop_top", 32)])
+def test_fp32_decisions_across_selections_and_k(lib, ctx, mode, k):
+    """The selection x k shapes of the sweep: the comparison's flagged set and
+    its bare count (no output buffer) equal the chain's set on the same unit
+    signatures, from 8 parts (most pairs flagged) to 1,024 parts."""
+    import torch
+    c = synth.generate(1, n_docs=400)
+    o, t = device_docs(c)
+    listed = lib.mrc_model_info(lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(8, mode=lib.SEL_ALL)))[
+        "n_listed"]
+    kw = {"all": dict(mode=lib.SEL_ALL), "drop_top": dict(mode=lib.SEL_DROP_TOP),
+          "frequent_half": dict(mode=lib.SEL_REGION, lo=0, hi=listed // 2),
+          "rare_half": dict(mode=lib.SEL_REGION, lo=listed // 2, hi=listed),
+          "rarest": dict(mode=lib.SEL_RAREST, m=listed // 10)}[mode]
+    gm = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, lib.ref_spec(k, **kw))
+    sig = lib.mrc_sign(ctx, gm, o, t)
+    flush(f"  compare fp32 selection={mode} k={k} listed={listed}")
+    pairs, stats = lib.mrc_compare(ctx, sig, TAU, lib.PREC_FP32)
+    gi, gj, gs, _ = lib.pairs_to_numpy(pairs)
+    unit = lib.mrc_normalise(ctx, sig)["unit"].cpu().numpy()
+    iu, ju, s32 = all_pairs_score32(unit)
+    want = s32 >= np.float32(TAU)
+    assert set(zip(gi.tolist(), gj.tolist())) == set(zip(iu[want].tolist(), ju[want].tolist()))
+    order = np.lexsort((gj, gi))
+    np.testing.assert_array_equal(gs[order].view(np.uint32), om.score32_pairs(unit, gi[order], gj[order]).view(np.uint32))
+    n = ctypes.c_int64()
+    opts = lib.MrcCompareOpts(TAU, lib.PREC_FP32, 0.02, 0)
+    st = lib.lib().mrc_compare(ctx, ctypes.c_void_p(sig.data_ptr()), sig.shape[0], sig.shape[1], ctypes.byref(opts),
+                               None, 0, ctypes.byref(n), None,
+                               ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == (lib.MRC_E_OVERFLOW if gi.size else lib.MRC_OK) and n.value == gi.size
+    flush(f"    flagged={gi.size} of {iu.size}")
+
+
 def test_fp32_overflow_protocol_and_tiny_inputs(lib, ctx):
     import torch
     c, sig = _signed(lib, ctx, 0, None, 16)
