@@ -297,7 +297,7 @@ def count_flagged(mrc, ctx, sig, tau):
 
 def sweep(mrc, synth):
     """Reference selection x k (the paper's experiments over reference regions and
-    partition counts, Sections 4-5) on the 20,000-document corpus: for each
+    partition counts, Section 4, Figs. 1-18) on the 20,000-document corpus: for each
     selection and k, the time of model build + signing and of the FP32 all-pairs
     comparison, the flagged count, recall and precision against exact TF-IDF
     cosine at tau, and MAE / variance (Eqs. 2-3, as read: mean |MRC - cos| and
