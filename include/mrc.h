@@ -249,6 +249,27 @@ mrc_status mrc_score_pairs(mrc_ctx* ctx, const float* unit, int64_t n, int32_t k
                            const int32_t* ii, const int32_t* jj, int64_t n_pairs, float* out,
                            void* hip_stream);
 
+/* ------------------------------------------------------------------ text front end */
+
+/* Character 3-grams of raw text (Sections 3-4: documents and the reference
+ * are vectors over character 3-grams), as token ids for the other calls.
+ * Case-folded ASCII letters are symbols 0-25; every other byte is the
+ * separator symbol 26. Each window of three consecutive bytes of a document
+ * gives id 729 s0 + 27 s1 + s2 in [0, 19683), in text order: a document of L
+ * bytes gives max(L - 2, 0) ids (vocab_size 19683 for the model calls).
+ *   text:            device bytes [n_bytes].
+ *   text_offsets:    device int64 [n_docs + 1], nondecreasing, first 0, last n_bytes.
+ *   tok_offsets_out: device int64 [n_docs + 1], written: the ids' CSR offsets.
+ *   tokens_out:      device int32 [capacity]; may be NULL when capacity is 0.
+ *   n_tokens:        host; receives the total number of ids.
+ * Two-call protocol: if the total exceeds capacity the call writes the
+ * offsets and *n_tokens, writes no ids and returns MRC_E_OVERFLOW. Malformed
+ * offsets: MRC_E_INVAL, nothing usable written. The caller owns every buffer;
+ * the ids are ready when the stream reaches the end of the call's work. */
+mrc_status mrc_trigrams(mrc_ctx* ctx, const uint8_t* text, const int64_t* text_offsets, int64_t n_docs,
+                        int64_t n_bytes, int64_t* tok_offsets_out, int32_t* tokens_out, int64_t capacity,
+                        int64_t* n_tokens, void* hip_stream);
+
 /* ------------------------------------------------------------------ comparators */
 
 /* Simhash-64 of each document (Section 3): term t hashes to the first 8 bytes

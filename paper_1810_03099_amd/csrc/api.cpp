@@ -512,6 +512,26 @@ mrc_status mrc_term_hashes(mrc_ctx* ctx, const mrc_model* model, uint64_t* out, 
     return MRC_OK;
 }
 
+mrc_status mrc_trigrams(mrc_ctx* ctx, const uint8_t* text, const int64_t* text_offsets, int64_t n_docs,
+                        int64_t n_bytes, int64_t* tok_offsets_out, int32_t* tokens_out, int64_t capacity,
+                        int64_t* n_tokens, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_trigrams"));
+    if (!n_tokens || n_docs < 0 || n_bytes < 0 || capacity < 0 || (capacity > 0 && !tokens_out) ||
+        !text_offsets || !tok_offsets_out || (n_bytes > 0 && !text) || (n_docs == 0 && n_bytes != 0))
+        return fail(MRC_E_INVAL, "mrc_trigrams: bad argument");
+    hipStream_t s = (hipStream_t)hip_stream;
+    *n_tokens = 0;
+    if (n_docs == 0) {
+        MRC_TRY(clear_words(ctx, tok_offsets_out, 1, s));
+        return MRC_OK;
+    }
+    MRC_TRY(launch_trigram_offsets(ctx, text_offsets, n_docs, n_bytes, tok_offsets_out, s));
+    MRC_TRY(sync_flags(ctx, s, 2, "mrc_trigrams"));
+    *n_tokens = ctx->h_flags[1];
+    if (*n_tokens > capacity) return fail(MRC_E_OVERFLOW, "mrc_trigrams: more ids than capacity");
+    return launch_trigrams(ctx, text, text_offsets, n_docs, tok_offsets_out, tokens_out, s);
+}
+
 mrc_status mrc_simhash(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, uint64_t* out, void* hip_stream) {
     MRC_TRY(check_ctx(ctx, "mrc_simhash"));
     MRC_TRY(check_docs(docs, "mrc_simhash"));

@@ -35,7 +35,7 @@ EXPORTS = (
     "mrc_ctx_create", "mrc_ctx_destroy", "mrc_ctx_memory", "mrc_ctx_set_timing", "mrc_ctx_kernel_time",
     "mrc_last_error", "mrc_build_vocab_idf", "mrc_build_and_sign", "mrc_model_destroy", "mrc_model_info", "mrc_model_get",
     "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_compare", "mrc_normalise", "mrc_score_pairs",
-    "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
+    "mrc_trigrams", "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
     "mrc_db_destroy", "mrc_db_insert", "mrc_db_insert_docs", "mrc_db_size", "mrc_db_save", "mrc_db_load",
     "mrc_query", "mrc_serve_start", "mrc_serve_submit", "mrc_serve_submit_many", "mrc_serve_poll", "mrc_serve_stop",
 )
@@ -116,6 +116,7 @@ _SIGS = {
                     C.POINTER(C.c_int64), C.POINTER(MrcCompareStats), _P],
     "mrc_normalise": [_P, _P, C.c_int64, C.c_int32, _P, _P, _P, _P, _P, _P],
     "mrc_score_pairs": [_P, _P, C.c_int64, C.c_int32, _P, _P, C.c_int64, _P, _P],
+    "mrc_trigrams": [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P],
     "mrc_simhash": [_P, _P, C.POINTER(MrcDocs), _P, _P],
     "mrc_term_hashes": [_P, _P, _P, _P],
     "mrc_hamming_pairs": [_P, _P, C.c_int64, C.c_int32, _P, C.c_int64, C.POINTER(C.c_int64), _P],
@@ -392,6 +393,37 @@ def mrc_score_pairs(ctx, unit, ii, jj, stream=None):
                                  _dptr(jj, torch.int32), int(ii.numel()), _dptr(out), _stream(stream)),
            "mrc_score_pairs")
     return out
+
+
+# ------------------------------------------------------------------ text front end
+
+TRIGRAM_VOCAB = 27 ** 3
+
+
+def mrc_trigrams(ctx, text, text_offsets, capacity=None, stream=None):
+    """Character 3-gram ids of raw text. text: device uint8 [n_bytes];
+    text_offsets: device int64 [n_docs + 1]. Returns (offsets int64 [n_docs + 1],
+    ids int32 [total]) on the device, with the two-call protocol handled here."""
+    n = int(text_offsets.numel()) - 1
+    if n < 0:
+        raise MrcError(MRC_E_INVAL, "mrc_trigrams: text_offsets is empty")
+    nb = int(text.numel())
+    dev = text_offsets.device
+    tok_off = torch.empty((n + 1,), dtype=torch.int64, device=dev)
+    tp = _dptr(text, torch.uint8, "text") if nb > 0 else None
+    op = _dptr(text_offsets, torch.int64, "text_offsets")
+    s = _stream(stream)
+    cap = int(capacity) if capacity is not None else max(nb, 1)
+    while True:
+        ids = torch.empty((max(cap, 1),), dtype=torch.int32, device=dev)
+        total = C.c_int64()
+        st = lib().mrc_trigrams(ctx, tp, op, n, nb, _dptr(tok_off), _dptr(ids) if cap > 0 else None, cap,
+                                C.byref(total), s)
+        if st == MRC_E_OVERFLOW:
+            cap = int(total.value)
+            continue
+        _check(st, "mrc_trigrams")
+        return tok_off, ids[: total.value]
 
 
 # ------------------------------------------------------------------ comparators
