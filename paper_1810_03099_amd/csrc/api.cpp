@@ -529,7 +529,7 @@ mrc_status mrc_trigrams(mrc_ctx* ctx, const uint8_t* text, const int64_t* text_o
     MRC_TRY(sync_flags(ctx, s, 2, "mrc_trigrams"));
     *n_tokens = ctx->h_flags[1];
     if (*n_tokens > capacity) return fail(MRC_E_OVERFLOW, "mrc_trigrams: more ids than capacity");
-    return launch_trigrams(ctx, text, text_offsets, n_docs, tok_offsets_out, tokens_out, s);
+    return launch_trigrams(ctx, text, n_bytes, text_offsets, n_docs, tok_offsets_out, tokens_out, s);
 }
 
 mrc_status mrc_simhash(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, uint64_t* out, void* hip_stream) {

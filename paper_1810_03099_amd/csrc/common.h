@@ -275,8 +275,8 @@ mrc_status launch_exact_cosine(mrc_ctx* ctx, const mrc_model* m, const mrc_docs*
 // then the ids themselves.
 mrc_status launch_trigram_offsets(mrc_ctx* ctx, const int64_t* off, int64_t n, int64_t n_bytes, int64_t* tok_off,
                                   hipStream_t s);
-mrc_status launch_trigrams(mrc_ctx* ctx, const uint8_t* text, const int64_t* off, int64_t n, const int64_t* tok_off,
-                           int32_t* out, hipStream_t s);
+mrc_status launch_trigrams(mrc_ctx* ctx, const uint8_t* text, int64_t n_bytes, const int64_t* off, int64_t n,
+                           const int64_t* tok_off, int32_t* out, hipStream_t s);
 
 // Leading dimensions (elements) of the database / query layouts for k.
 struct DbLayout {

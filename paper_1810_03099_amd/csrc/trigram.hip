@@ -11,8 +11,8 @@
 // Passes: per-document id counts with a block total (also checks the
 // offsets), an exclusive scan of the block totals (one workgroup), the
 // output offsets; then the map itself, one wavefront per document, each lane
-// writing consecutive ids so that every load and store instruction of a
-// wavefront covers 64 consecutive bytes / ids.
+// loading one aligned word of text per round and writing the four ids that
+// start in it.
 #include "common.h"
 
 using namespace mrc;
@@ -108,26 +108,48 @@ __global__ __launch_bounds__(kTriBlock) void k_tri_offsets(const int64_t* __rest
     }
 }
 
-// One wavefront per document (grid-stride); lane l of a round writes ids
-// r + 64 j + l, j = 0..3, each from three byte loads inside the document.
-__global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restrict__ text,
+// Four bytes at the 4-byte-aligned address x, as a little-endian word; a word
+// that reaches outside [lo, hi) is assembled from its bytes inside it (zero
+// elsewhere), so no access leaves the caller's buffer.
+__device__ __forceinline__ uint32_t tri_word(uintptr_t x, uintptr_t lo, uintptr_t hi) {
+    if (x >= lo && x + 4 <= hi) return *(const uint32_t*)x;
+    uint32_t w = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        if (x + i >= lo && x + i < hi) w |= (uint32_t)(*(const uint8_t*)(x + i)) << (8 * i);
+    return w;
+}
+
+// One wavefront per document (grid-stride). A round covers 256 window starts
+// from a 4-byte-aligned address: lane l loads the aligned word at 4 l, takes
+// the following word from lane l + 1 (lane 63 loads it), and writes the ids
+// of the windows that start at its four bytes and lie inside the document.
+__global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restrict__ text, int64_t n_bytes,
                                                        const int64_t* __restrict__ off, int64_t n,
                                                        const int64_t* __restrict__ tok_off,
                                                        int32_t* __restrict__ out) {
     const int lane = __lane_id();
     const int64_t waves = (int64_t)gridDim.x * (kTriBlock / 64);
+    const uintptr_t lo = (uintptr_t)text, hi = lo + (uintptr_t)n_bytes;
     for (int64_t d = (int64_t)blockIdx.x * (kTriBlock / 64) + (threadIdx.x >> 6); d < n; d += waves) {
-        const int64_t a = off[d];
-        const int64_t m = off[d + 1] - a - 2;  // ids of this document (<= 0: none)
-        const uint8_t* t = text + a;
-        int32_t* o = out + tok_off[d];
-        for (int64_t r = 0; r < m; r += 256) {
+        const int64_t a = off[d], e = off[d + 1];
+        if (e - a < 3) continue;
+        const uintptr_t pa = lo + (uintptr_t)a, plast = lo + (uintptr_t)(e - 3);  // first / last window start
+        int32_t* __restrict__ o = out + tok_off[d];
+        for (uintptr_t r = pa & ~(uintptr_t)3; r <= plast; r += 256) {
+            const uintptr_t x = r + 4 * (uintptr_t)lane;
+            const uint32_t w = tri_word(x, lo, hi);
+            uint32_t nx = __shfl_down(w, 1, 64);
+            if (lane == 63) nx = tri_word(x + 4, lo, hi);
+            const uint64_t b = (uint64_t)w | ((uint64_t)nx << 32);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t p = r + 64 * j + lane;
-                if (p < m) {
-                    const int s0 = tri_sym(t[p]), s1 = tri_sym(t[p + 1]), s2 = tri_sym(t[p + 2]);
-                    o[p] = s0 * 729 + s1 * 27 + s2;
+            for (int k = 0; k < 4; ++k) {
+                const uintptr_t q = x + k;
+                if (q >= pa && q <= plast) {
+                    const int s0 = tri_sym((unsigned)(b >> (8 * k)) & 0xffu);
+                    const int s1 = tri_sym((unsigned)(b >> (8 * k + 8)) & 0xffu);
+                    const int s2 = tri_sym((unsigned)(b >> (8 * k + 16)) & 0xffu);
+                    o[q - pa] = s0 * 729 + s1 * 27 + s2;
                 }
             }
         }
@@ -156,12 +178,12 @@ mrc_status launch_trigram_offsets(mrc_ctx* ctx, const int64_t* off, int64_t n, i
     return MRC_OK;
 }
 
-mrc_status launch_trigrams(mrc_ctx* ctx, const uint8_t* text, const int64_t* off, int64_t n, const int64_t* tok_off,
-                           int32_t* out, hipStream_t s) {
+mrc_status launch_trigrams(mrc_ctx* ctx, const uint8_t* text, int64_t n_bytes, const int64_t* off, int64_t n,
+                           const int64_t* tok_off, int32_t* out, hipStream_t s) {
     if (n == 0) return MRC_OK;
     ScopedTimer tm(ctx, "trigrams", s);
     const int64_t grid = std::min<int64_t>(ceil_div(n, kTriBlock / 64), 16384);
-    hipLaunchKernelGGL(k_trigrams, dim3((unsigned)grid), dim3(kTriBlock), 0, s, text, off, n, tok_off, out);
+    hipLaunchKernelGGL(k_trigrams, dim3((unsigned)grid), dim3(kTriBlock), 0, s, text, n_bytes, off, n, tok_off, out);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }

@@ -60,6 +60,26 @@ def test_random_bytes_ragged(lib, ctx, seed):
     _check(lib, ctx, text, off, f"random bytes seed {seed}")
 
 
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_text_pointer_not_word_aligned(lib, ctx, shift):
+    """The caller's text may start at any byte address: the map reads whole
+    aligned words only where they lie inside the buffer."""
+    import torch
+    rng = np.random.default_rng(20 + shift)
+    lens = rng.integers(0, 300, 500)
+    lens[:4] = [5, 0, 3, 1]
+    text = rng.integers(0, 256, int(lens.sum()), dtype=np.uint8)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    pad = torch.from_numpy(np.concatenate([np.full(shift, 65, np.uint8), text, np.full(7, 66, np.uint8)])).cuda()
+    t = pad[shift:shift + text.size]
+    assert t.is_contiguous() and t.data_ptr() % 4 == shift % 4
+    flush(f"  trigrams text at byte offset {shift}")
+    tok_off, ids = lib.mrc_trigrams(ctx, t, torch.from_numpy(off).cuda())
+    want_off, want = ot.trigram_csr(text, off)
+    np.testing.assert_array_equal(tok_off.cpu().numpy(), want_off)
+    np.testing.assert_array_equal(ids.cpu().numpy(), want)
+
+
 def test_many_documents_and_one_long(lib, ctx):
     rng = np.random.default_rng(11)
     # 600,000 documents: 293 offset blocks of 2,048, more than one round of the block scan
