@@ -11,8 +11,8 @@
 // Passes: per-document id counts with a block total (also checks the
 // offsets), an exclusive scan of the block totals (one workgroup), the
 // output offsets; then the map itself, one wavefront per document, each lane
-// loading one aligned word of text per round and writing the four ids that
-// start in it.
+// loading four aligned words of text per round and writing the ids that
+// start in them.
 #include "common.h"
 
 using namespace mrc;
@@ -120,10 +120,13 @@ __device__ __forceinline__ uint32_t tri_word(uintptr_t x, uintptr_t lo, uintptr_
     return w;
 }
 
-// One wavefront per document (grid-stride). A round covers 256 window starts
-// from a 4-byte-aligned address: lane l loads the aligned word at 4 l, takes
-// the following word from lane l + 1 (lane 63 loads it), and writes the ids
-// of the windows that start at its four bytes and lie inside the document.
+// One wavefront per document (grid-stride). A round covers 1,024 window
+// starts from a 4-byte-aligned address r: lane l loads the aligned words at
+// r + 256 j + 4 l, j = 0..3, all four before any is used (so that a wavefront
+// keeps 4 KB of text in flight), takes each following word from lane l + 1
+// (lane 63 from lane 0 of the next quarter, or its own load past the round),
+// and writes the ids of the windows that start at its bytes inside the
+// document. A word is loaded only if it holds a byte some window needs.
 __global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restrict__ text, int64_t n_bytes,
                                                        const int64_t* __restrict__ off, int64_t n,
                                                        const int64_t* __restrict__ tok_off,
@@ -135,21 +138,32 @@ __global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restric
         const int64_t a = off[d], e = off[d + 1];
         if (e - a < 3) continue;
         const uintptr_t pa = lo + (uintptr_t)a, plast = lo + (uintptr_t)(e - 3);  // first / last window start
+        const uintptr_t pend = plast + 2;                                            // last byte any window reads
         int32_t* __restrict__ o = out + tok_off[d];
-        for (uintptr_t r = pa & ~(uintptr_t)3; r <= plast; r += 256) {
-            const uintptr_t x = r + 4 * (uintptr_t)lane;
-            const uint32_t w = tri_word(x, lo, hi);
-            uint32_t nx = __shfl_down(w, 1, 64);
-            if (lane == 63) nx = tri_word(x + 4, lo, hi);
-            const uint64_t b = (uint64_t)w | ((uint64_t)nx << 32);
+        for (uintptr_t r = pa & ~(uintptr_t)3; r <= plast; r += 1024) {
+            uint32_t w[4];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                const uintptr_t q = x + k;
-                if (q >= pa && q <= plast) {
-                    const int s0 = tri_sym((unsigned)(b >> (8 * k)) & 0xffu);
-                    const int s1 = tri_sym((unsigned)(b >> (8 * k + 8)) & 0xffu);
-                    const int s2 = tri_sym((unsigned)(b >> (8 * k + 16)) & 0xffu);
-                    o[q - pa] = s0 * 729 + s1 * 27 + s2;
+            for (int j = 0; j < 4; ++j) {
+                const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
+                w[j] = x <= pend ? tri_word(x, lo, hi) : 0u;
+            }
+            const uint32_t tail = (lane == 63 && r + 1024 <= pend) ? tri_word(r + 1024, lo, hi) : 0u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
+                uint32_t nx = __shfl_down(w[j], 1, 64);
+                const uint32_t first_next = j < 3 ? __shfl(w[j < 3 ? j + 1 : 3], 0, 64) : tail;
+                if (lane == 63) nx = first_next;
+                const uint64_t b = (uint64_t)w[j] | ((uint64_t)nx << 32);
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uintptr_t q = x + k;
+                    if (q >= pa && q <= plast) {
+                        const int s0 = tri_sym((unsigned)(b >> (8 * k)) & 0xffu);
+                        const int s1 = tri_sym((unsigned)(b >> (8 * k + 8)) & 0xffu);
+                        const int s2 = tri_sym((unsigned)(b >> (8 * k + 16)) & 0xffu);
+                        o[q - pa] = s0 * 729 + s1 * 27 + s2;
+                    }
                 }
             }
         }
