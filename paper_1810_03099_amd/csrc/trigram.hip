@@ -11,7 +11,7 @@
 // Passes: per-document id counts with a block total (also checks the
 // offsets), an exclusive scan of the block totals (one workgroup), the
 // output offsets; then the map itself, one wavefront per document, each lane
-// loading four aligned words of text per round and writing the ids that
+// loading eight aligned words of text per round and writing the ids that
 // start in them.
 #include "common.h"
 
@@ -120,13 +120,16 @@ __device__ __forceinline__ uint32_t tri_word(uintptr_t x, uintptr_t lo, uintptr_
     return w;
 }
 
-// One wavefront per document (grid-stride). A round covers 1,024 window
-// starts from a 4-byte-aligned address r: lane l loads the aligned words at
-// r + 256 j + 4 l, j = 0..3, all four before any is used (so that a wavefront
-// keeps 4 KB of text in flight), takes each following word from lane l + 1
-// (lane 63 from lane 0 of the next quarter, or its own load past the round),
-// and writes the ids of the windows that start at its bytes inside the
-// document. A word is loaded only if it holds a byte some window needs.
+// One wavefront per document (grid-stride). A round covers 256 kTriWords
+// window starts from a 4-byte-aligned address r: lane l loads the aligned
+// words at r + 256 j + 4 l, j < kTriWords, all before any is used (so that a
+// wavefront keeps 256 kTriWords bytes of text in flight), takes each following
+// word from lane l + 1 (lane 63 from lane 0 of the next quarter, or its own
+// load past the round), and writes the ids of the windows that start at its
+// bytes inside the document. A word is loaded only if it holds a byte some
+// window needs. The next document's offsets are loaded before this one's text.
+constexpr int kTriWords = 8;
+
 __global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restrict__ text, int64_t n_bytes,
                                                        const int64_t* __restrict__ off, int64_t n,
                                                        const int64_t* __restrict__ tok_off,
@@ -134,39 +137,58 @@ __global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restric
     const int lane = __lane_id();
     const int64_t waves = (int64_t)gridDim.x * (kTriBlock / 64);
     const uintptr_t lo = (uintptr_t)text, hi = lo + (uintptr_t)n_bytes;
-    for (int64_t d = (int64_t)blockIdx.x * (kTriBlock / 64) + (threadIdx.x >> 6); d < n; d += waves) {
-        const int64_t a = off[d], e = off[d + 1];
-        if (e - a < 3) continue;
-        const uintptr_t pa = lo + (uintptr_t)a, plast = lo + (uintptr_t)(e - 3);  // first / last window start
-        const uintptr_t pend = plast + 2;                                            // last byte any window reads
-        int32_t* __restrict__ o = out + tok_off[d];
-        for (uintptr_t r = pa & ~(uintptr_t)3; r <= plast; r += 1024) {
-            uint32_t w[4];
+    int64_t d = (int64_t)blockIdx.x * (kTriBlock / 64) + (threadIdx.x >> 6);
+    int64_t a = 0, e = 0, t0 = 0;
+    if (d < n) {
+        a = off[d];
+        e = off[d + 1];
+        t0 = tok_off[d];
+    }
+    for (; d < n; d += waves) {
+        const int64_t dn = d + waves;
+        int64_t an = 0, en = 0, tn = 0;
+        if (dn < n) {
+            an = off[dn];
+            en = off[dn + 1];
+            tn = tok_off[dn];
+        }
+        if (e - a >= 3) {
+            const uintptr_t pa = lo + (uintptr_t)a, plast = lo + (uintptr_t)(e - 3);  // first / last window start
+            const uintptr_t pend = plast + 2;                                            // last byte any window reads
+            int32_t* __restrict__ o = out + t0;
+            for (uintptr_t r = pa & ~(uintptr_t)3; r <= plast; r += 256 * kTriWords) {
+                uint32_t w[kTriWords];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
-                w[j] = x <= pend ? tri_word(x, lo, hi) : 0u;
-            }
-            const uint32_t tail = (lane == 63 && r + 1024 <= pend) ? tri_word(r + 1024, lo, hi) : 0u;
+                for (int j = 0; j < kTriWords; ++j) {
+                    const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
+                    w[j] = x <= pend ? tri_word(x, lo, hi) : 0u;
+                }
+                const uintptr_t xt = r + 256 * kTriWords;
+                const uint32_t tail = (lane == 63 && xt <= pend) ? tri_word(xt, lo, hi) : 0u;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
-                uint32_t nx = __shfl_down(w[j], 1, 64);
-                const uint32_t first_next = j < 3 ? __shfl(w[j < 3 ? j + 1 : 3], 0, 64) : tail;
-                if (lane == 63) nx = first_next;
-                const uint64_t b = (uint64_t)w[j] | ((uint64_t)nx << 32);
+                for (int j = 0; j < kTriWords; ++j) {
+                    const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
+                    uint32_t nx = __shfl_down(w[j], 1, 64);
+                    const uint32_t first_next =
+                        j < kTriWords - 1 ? __shfl(w[j < kTriWords - 1 ? j + 1 : j], 0, 64) : tail;
+                    if (lane == 63) nx = first_next;
+                    const uint64_t b = (uint64_t)w[j] | ((uint64_t)nx << 32);
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    const uintptr_t q = x + k;
-                    if (q >= pa && q <= plast) {
-                        const int s0 = tri_sym((unsigned)(b >> (8 * k)) & 0xffu);
-                        const int s1 = tri_sym((unsigned)(b >> (8 * k + 8)) & 0xffu);
-                        const int s2 = tri_sym((unsigned)(b >> (8 * k + 16)) & 0xffu);
-                        o[q - pa] = s0 * 729 + s1 * 27 + s2;
+                    for (int k = 0; k < 4; ++k) {
+                        const uintptr_t q = x + k;
+                        if (q >= pa && q <= plast) {
+                            const int s0 = tri_sym((unsigned)(b >> (8 * k)) & 0xffu);
+                            const int s1 = tri_sym((unsigned)(b >> (8 * k + 8)) & 0xffu);
+                            const int s2 = tri_sym((unsigned)(b >> (8 * k + 16)) & 0xffu);
+                            o[q - pa] = s0 * 729 + s1 * 27 + s2;
+                        }
                     }
                 }
             }
         }
+        a = an;
+        e = en;
+        t0 = tn;
     }
 }
 
