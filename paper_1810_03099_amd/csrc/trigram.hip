@@ -123,10 +123,12 @@ __device__ __forceinline__ uint32_t tri_word(uintptr_t x, uintptr_t lo, uintptr_
 // One wavefront per document (grid-stride). A round covers 256 kTriWords
 // window starts from a 4-byte-aligned address r: lane l loads the aligned
 // words at r + 256 j + 4 l, j < kTriWords, all before any is used (so that a
-// wavefront keeps 256 kTriWords bytes of text in flight), takes each following
-// word from lane l + 1 (lane 63 from lane 0 of the next quarter, or its own
-// load past the round), and writes the ids of the windows that start at its
-// bytes inside the document. A word is loaded only if it holds a byte some
+// wavefront keeps 256 kTriWords bytes of text in flight). The ids are formed
+// in store order: for each group of 256 window starts, store k has lane l
+// write the window at 64 k + l, whose bytes it takes by shuffle from the two
+// words that hold them (the last word's successor is the next group's first
+// word, or lane 63's load past the round), so that every store instruction
+// writes 256 contiguous bytes. A word is loaded only if it holds a byte some
 // window needs. The next document's offsets are loaded before this one's text.
 constexpr int kTriWords = 8;
 
@@ -165,21 +167,26 @@ __global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restric
                 }
                 const uintptr_t xt = r + 256 * kTriWords;
                 const uint32_t tail = (lane == 63 && xt <= pend) ? tri_word(xt, lo, hi) : 0u;
+                const uint32_t tail_all = __shfl(tail, 63, 64);
 #pragma unroll
                 for (int j = 0; j < kTriWords; ++j) {
-                    const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
-                    uint32_t nx = __shfl_down(w[j], 1, 64);
-                    const uint32_t first_next =
-                        j < kTriWords - 1 ? __shfl(w[j < kTriWords - 1 ? j + 1 : j], 0, 64) : tail;
-                    if (lane == 63) nx = first_next;
-                    const uint64_t b = (uint64_t)w[j] | ((uint64_t)nx << 32);
+                    // the word after this quarter's last one, on every lane
+                    const uint32_t next_first =
+                        j < kTriWords - 1 ? __shfl(w[j < kTriWords - 1 ? j + 1 : j], 0, 64) : tail_all;
+                    // store instruction k writes window starts r + 256 j + 64 k + lane: the
+                    // window's first byte is byte (lane mod 4) of lane 16 k + lane / 4's word
 #pragma unroll
                     for (int k = 0; k < 4; ++k) {
-                        const uintptr_t q = x + k;
+                        const int src = 16 * k + (lane >> 2);
+                        const uint32_t wa = __shfl(w[j], src, 64);
+                        const uint32_t wb0 = __shfl(w[j], (src + 1) & 63, 64);
+                        const uint32_t wb = src == 63 ? next_first : wb0;
+                        const uint64_t b = ((uint64_t)wa | ((uint64_t)wb << 32)) >> (8 * (lane & 3));
+                        const uintptr_t q = r + 256 * j + 64 * k + (uintptr_t)lane;
                         if (q >= pa && q <= plast) {
-                            const int s0 = tri_sym((unsigned)(b >> (8 * k)) & 0xffu);
-                            const int s1 = tri_sym((unsigned)(b >> (8 * k + 8)) & 0xffu);
-                            const int s2 = tri_sym((unsigned)(b >> (8 * k + 16)) & 0xffu);
+                            const int s0 = tri_sym((unsigned)b & 0xffu);
+                            const int s1 = tri_sym((unsigned)(b >> 8) & 0xffu);
+                            const int s2 = tri_sym((unsigned)(b >> 16) & 0xffu);
                             o[q - pa] = s0 * 729 + s1 * 27 + s2;
                         }
                     }
