@@ -13,6 +13,7 @@ Modules
   comparators  exact TF-IDF cosine (the ground truth), Simhash-64 and Hamming
                distance, MAE/variance and recall/precision
   brute        pure-Python loops for tiny corpora, used to check `mrc`
+  trigram      character 3-gram ids of raw text (the front end before counting)
   fma_chain.c  the FP32 multiply-add chain that defines the plain FP32 score
 
 Every function names the passage of the paper it follows. Where the paper is
