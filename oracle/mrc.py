@@ -205,6 +205,39 @@ def sign(offsets, tokens, model: Model):
     return sig, norm
 
 
+# --------------------------------------------------------------------------- general references
+
+def reference_matrix(model: Model):
+    """The k reference vectors of a model as the columns of a dense V x k
+    matrix: R[t, part_of[t]] = rho_t (Section 4's parts; every term in at most
+    one column)."""
+    R = np.zeros((model.vocab, model.k), dtype=np.float64)
+    sel = np.nonzero(model.part_of >= 0)[0]
+    R[sel, model.part_of[sel]] = model.rho[sel]
+    return R
+
+
+def sign_matrix(offsets, tokens, model: Model, R):
+    """Signature against k general reference vectors, the columns of a V x k
+    matrix R whose entries may weight their terms and whose columns may share
+    terms (Section 4's construction with Section 6's weighted vector-space
+    models): sig[d][j] = w_d . r_j / (|w_d| |r_j|), Eq. (1) between the
+    document's TF-IDF vector (the model's idf) and column j; 0 when either norm
+    is 0. The model's own parts play no role. Returns (sig [N][k], norm [N])."""
+    import scipy.sparse as sp
+    R = np.asarray(R, dtype=np.float64)
+    if R.ndim != 2 or R.shape[0] != model.vocab:
+        raise ValueError("R must be vocab x k")
+    doc, term, w, norm = tfidf(offsets, tokens, model)
+    n = int(len(offsets) - 1)
+    W = sp.csr_matrix((w, (doc, term)), shape=(n, model.vocab))
+    num = np.asarray(W @ R)
+    rnorm = np.sqrt((R * R).sum(axis=0))
+    den = norm[:, None] * rnorm[None, :]
+    sig = np.divide(num, den, out=np.zeros_like(num), where=den > 0)
+    return sig, norm
+
+
 # --------------------------------------------------------------------------- comparison
 
 def normalise(sig):

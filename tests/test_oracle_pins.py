@@ -98,7 +98,134 @@ def test_compare_pairs_matches_brute_all_pairs(seed):
     assert np.all(i < j)
 
 
+def test_pair_scores_match_brute_cosine():
+    """MRC(i, j) of listed pairs (Eq. (1) on the signatures) against the
+    pure-Python cosine of the raw signatures: ordered pairs in both directions,
+    i == j, zero rows and a scaled copy."""
+    rng = np.random.default_rng(7)
+    n, k = 30, 6
+    sig = rng.random((n, k)) ** 2
+    sig[[6, 11]] = 0.0
+    sig[4] = sig[1] * 3.0
+    shat = mrc.normalise(sig)
+    i = rng.integers(0, n, 300)
+    j = rng.integers(0, n, 300)
+    i[:6] = [1, 4, 2, 6, 6, 0]
+    j[:6] = [4, 1, 2, 3, 11, 29]
+    got = mrc.pair_scores(shat, i, j)
+    for a, b, g in zip(i.tolist(), j.tolist(), got):
+        assert abs(g - brute.cosine(sig[a], sig[b])) <= 1e-12
+    assert abs(got[0] - 1.0) <= 1e-15 and abs(got[2] - 1.0) <= 1e-15   # scaled copy, self
+    assert got[3] == 0.0 and got[4] == 0.0                                # zero rows
+    np.testing.assert_array_equal(mrc.pair_scores(shat, j, i), got)       # symmetric
+
+
+# --------------------------------------------------------------------------- general references
+
+@pytest.mark.parametrize("seed", range(20))
+def test_sign_matrix_matches_brute_force(seed):
+    """Dense reference columns with arbitrary weights (negative ones, shared
+    terms, a zero column) against the pure-Python Eq. (1) between the dense
+    TF-IDF vector and each column."""
+    rng = np.random.default_rng(500 + seed)
+    vocab = int(rng.integers(4, 40))
+    c = _tiny_corpus(rng, int(rng.integers(1, 20)), vocab, 20)
+    docs = [c.doc(d) for d in range(c.n_docs)]
+    listed = len({int(t) for t in c.tokens})
+    if listed == 0:
+        return
+    spec = mrc.RefSpec(k=1, mode=mrc.SEL_ALL, idf_mode=int(rng.integers(0, 2)))
+    mdl = mrc.build_model(c.offsets, c.tokens, vocab, spec)
+    k = int(rng.integers(1, 9))
+    R = rng.standard_normal((vocab, k)) * (rng.random((vocab, k)) < 0.5)
+    R[:, 0] = 0.0 if k > 1 and seed % 3 == 0 else R[:, 0]
+    sig, norm = mrc.sign_matrix(c.offsets, c.tokens, mdl, R)
+    b = brute.model(docs, vocab, 1, lambda n: (0, n), idf_smooth=spec.idf_mode == mrc.IDF_SMOOTH)
+    for d, doc in enumerate(docs):
+        tf = brute.counts(doc)
+        w = [tf.get(t, 0) * b["idf"][t] for t in range(vocab)]
+        for j in range(k):
+            assert abs(sig[d, j] - brute.cosine(w, R[:, j].tolist())) <= 1e-12
+        assert abs(norm[d] - math.sqrt(sum(x * x for x in w))) <= 1e-12 * max(1.0, norm[d])
+
+
+@pytest.mark.parametrize("ref_weight", [0, 1])
+def test_sign_matrix_of_the_parts_is_the_mrc_signature(ref_weight):
+    """With the model's own parts as columns (indicator or idf weights), the
+    general signature is Section 4's signature."""
+    c = synth.generate(0, n_docs=300)
+    for spec in (mrc.RefSpec(k=16, ref_weight=ref_weight),
+                 mrc.RefSpec(k=7, mode=mrc.SEL_REGION, lo=10, hi=500, ref_weight=ref_weight)):
+        mdl = mrc.build_model(c.offsets, c.tokens, c.vocab, spec)
+        a, na = mrc.sign(c.offsets, c.tokens, mdl)
+        b, nb = mrc.sign_matrix(c.offsets, c.tokens, mdl, mrc.reference_matrix(mdl))
+        np.testing.assert_allclose(b, a, rtol=0, atol=1e-13)
+        np.testing.assert_array_equal(na, nb)
+
+
+def test_sign_matrix_closed_forms():
+    """Columns that are documents' own TF-IDF vectors give the exact cosine
+    (sklearn); a column that is the union of two disjoint parts combines their
+    indicator signatures as (s_a sqrt|P_a| + s_b sqrt|P_b|) / sqrt(|P_a| + |P_b|);
+    a column of one term gives that term's share of the unit TF-IDF vector."""
+    from sklearn.feature_extraction.text import TfidfTransformer
+    from sklearn.metrics.pairwise import cosine_similarity
+    import scipy.sparse as sp
+    c = synth.generate(0, n_docs=250)
+    mdl = mrc.build_model(c.offsets, c.tokens, c.vocab, mrc.RefSpec(k=16))
+    doc, term, tf = mrc.term_counts(c.offsets, c.tokens, c.vocab)
+    TF = sp.csr_matrix((tf, (doc, term)), shape=(c.n_docs, c.vocab))
+    W = TfidfTransformer(norm=None, smooth_idf=True).fit_transform(TF)
+    cols = [3, 17, 100, 249]
+    R = np.asarray(W[cols].todense()).T
+    sig, _ = mrc.sign_matrix(c.offsets, c.tokens, mdl, R)
+    np.testing.assert_allclose(sig, cosine_similarity(W, W[cols]), rtol=0, atol=1e-12)
+    # union of parts 2 and 5
+    P = mrc.reference_matrix(mdl)
+    s_ind, _ = mrc.sign(c.offsets, c.tokens, mdl)
+    na, nb = (mdl.part_of == 2).sum(), (mdl.part_of == 5).sum()
+    su, _ = mrc.sign_matrix(c.offsets, c.tokens, mdl, (P[:, 2] + P[:, 5])[:, None])
+    want = (s_ind[:, 2] * math.sqrt(na) + s_ind[:, 5] * math.sqrt(nb)) / math.sqrt(na + nb)
+    np.testing.assert_allclose(su[:, 0], want, rtol=0, atol=1e-13)
+    # one term per column
+    t = int(mdl.order[40])
+    e = np.zeros((c.vocab, 1))
+    e[t, 0] = 2.5
+    s1, norm = mrc.sign_matrix(c.offsets, c.tokens, mdl, e)
+    d2, t2, w2, _ = mrc.tfidf(c.offsets, c.tokens, mdl)
+    want = np.zeros(c.n_docs)
+    want[d2[t2 == t]] = w2[t2 == t] / norm[d2[t2 == t]]
+    np.testing.assert_allclose(s1[:, 0], want, rtol=0, atol=1e-14)
+
+
 # --------------------------------------------------------------------------- library routines
+
+def test_exact_cosine_scores_match_sklearn_at_listed_pairs():
+    """exact_cosine_scores (Eq. (1) on the TF-IDF vectors, and on raw counts
+    with idf NONE) at listed pairs against sklearn's cosine_similarity of the
+    same vectors."""
+    from sklearn.feature_extraction.text import TfidfTransformer
+    from sklearn.metrics.pairwise import cosine_similarity
+    import scipy.sparse as sp
+    c = synth.generate(0, n_docs=300)
+    doc, term, tf = mrc.term_counts(c.offsets, c.tokens, c.vocab)
+    TF = sp.csr_matrix((tf, (doc, term)), shape=(c.n_docs, c.vocab))
+    rng = np.random.default_rng(3)
+    i = rng.integers(0, c.n_docs, 2000)
+    j = rng.integers(0, c.n_docs, 2000)
+    dup = np.nonzero(c.source >= 0)[0]
+    i = np.concatenate([i, dup, np.arange(5)])
+    j = np.concatenate([j, c.source[dup], np.arange(5)])
+    for idf_mode, W in [(mrc.IDF_SMOOTH, TfidfTransformer(norm=None, smooth_idf=True).fit_transform(TF)),
+                        (mrc.IDF_NONE, TF.astype(np.float64))]:
+        mdl = mrc.build_model(c.offsets, c.tokens, c.vocab, mrc.RefSpec(k=16, idf_mode=idf_mode))
+        G = cosine_similarity(W)
+        got = cmpo.exact_cosine_scores(c.offsets, c.tokens, mdl, i, j)
+        np.testing.assert_allclose(got, G[i, j], rtol=0, atol=1e-12)
+        np.testing.assert_allclose(got[-5:], 1.0, atol=1e-12)
+        assert np.all(got[2000:2000 + dup.size] > 0.5)      # near duplicates and copies
+
+
 
 def test_smooth_idf_and_tfidf_match_sklearn():
     from sklearn.feature_extraction.text import TfidfTransformer
@@ -385,6 +512,26 @@ def test_fma_chain_matches_exact_rounding(seed):
     assert mrc.score32_pairs(a, [1], [0])[0] == got
 
 
+def test_fp32_rounding_bound_covers_the_chain():
+    """The bound the GPU parity tests use to excuse near-ties (tests/fp_bounds.py)
+    covers the float32 chain of rounded unit vectors against the float64 score,
+    on random rows and on rows built to cancel (large products of both signs)."""
+    from tests.fp_bounds import pair_bound
+    rng = np.random.default_rng(12)
+    for k in (7, 64, 256):
+        x = rng.random((200, k)) ** 3
+        x[100:] = rng.standard_normal((100, k)) * np.exp(rng.standard_normal((100, k)) * 4)
+        shat = mrc.normalise(x)
+        u32 = shat.astype(np.float32)
+        i = rng.integers(0, 200, 3000)
+        j = rng.integers(0, 200, 3000)
+        c = mrc.score32_pairs(u32, i, j).astype(np.float64)
+        s64 = mrc.pair_scores(shat, i, j)
+        b = pair_bound(u32, shat, i, j)
+        assert np.all(np.abs(c - s64) <= b)
+        assert b.max() < 1e-4 and np.median(b) < 1e-5
+
+
 def test_lowp_band_covers_quantisation_error():
     rng = np.random.default_rng(5)
     for k in (64, 128, 256):
@@ -474,3 +621,17 @@ def test_mae_variance_closed_form():
     assert abs(var - sum((x - m) ** 2 for x in e) / 3) < 1e-15
     r, p = cmpo.recall_precision([0, 1], [2, 3], [0, 5], [2, 6])
     assert r == 0.5 and p == 0.5
+    # Eq. (2) as printed: the signed pair sum over the number of documents
+    # (errors of opposite sign cancel, unlike the MAE)
+    assert abs(cmpo.mae_paper_literal(approx, truth, 3) - (0.1 - 0.2 + 0.0) / 3) < 1e-15
+    assert abs(cmpo.mae_paper_literal(approx, truth, 10) - (0.1 - 0.2) / 10) < 1e-15
+    assert cmpo.mae_paper_literal([0.3], [0.3], 2) == 0.0
+
+
+def test_simhash_similarity_closed_form():
+    np.testing.assert_array_equal(cmpo.simhash_similarity([0, 3, 32, 64]), [1.0, 61 / 64, 0.5, 0.0])
+    x = np.array([0x0123456789ABCDEF], np.uint64)
+    assert cmpo.simhash_similarity(cmpo.hamming(x, x))[0] == 1.0
+    assert cmpo.simhash_similarity(cmpo.hamming(x, ~x))[0] == 0.0
+    y = x ^ np.uint64(0b10110)
+    assert cmpo.simhash_similarity(cmpo.hamming(x, y))[0] == 1.0 - 3 / 64
