@@ -64,7 +64,8 @@ typedef int32_t mrc_status;
 #define MRC_REF_ONE 0       /* reference part = indicator vector of its terms */
 #define MRC_REF_IDF 1       /* reference part carries its terms' idf */
 
-#define MRC_PREC_FP32 0     /* plain path: float32 multiply-add chain on the vector ALUs */
+#define MRC_PREC_FP32 0     /* plain path: float32 multiply-add chain in ascending component order,
+                               run on the FP32 matrix cores (16x16x4 steps keep that order) */
 #define MRC_PREC_BF16 1     /* bfloat16 matrix cores, FP32 accumulate, band rescored in FP32 */
 #define MRC_PREC_FP8 2      /* float8 e4m3fn with per-row FP32 scale, band rescored in FP32 */
 
@@ -203,6 +204,23 @@ mrc_status mrc_model_load(mrc_ctx* ctx, const char* path, mrc_model** out);
 mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float* sig_out,
                     float* norm_out, void* hip_stream);
 
+/* Signatures against k general reference vectors (Section 4's construction
+ * with the weighted vector-space models of Section 6): the columns of a dense
+ * matrix R, whose entries may weight their terms and whose columns may share
+ * terms. sig[d][j] = (sum over the document's terms t of w_dt R[t][j]) /
+ * (|w_d| |r_j|), with w_dt = tf * idf_t under `model` (its idf and frequency
+ * order only; its own parts play no role) and |r_j| the Euclidean norm of
+ * column j; 0 when either norm is 0. The model's parts as columns (R[t][part
+ * of t] = rho_t) give mrc_sign's signature.
+ * R: device float [V][k] row-major (row t = term t's weight in every
+ * reference), V = the model's vocabulary; caller-owned, read only. k in
+ * [1, 1024]. sig_out: device float [n_docs][k]; norm_out as mrc_sign (the
+ * same exact |w_d|). The numerators are float64 sums in the order of each
+ * document's distinct-term list, rounded once to float. Errors: those of
+ * mrc_sign; MRC_E_INVAL for k outside [1, 1024] or a NULL R. */
+mrc_status mrc_sign_matrix(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, const float* R,
+                           int32_t k, float* sig_out, float* norm_out, void* hip_stream);
+
 /* Build the model of a corpus and sign that corpus (Sections 1 and 4: the
  * signature database of a collection) in one call, reusing the per-document
  * term counts of the build. Same result as mrc_build_vocab_idf followed by
@@ -236,8 +254,9 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k,
  * unit_out: device float [n][k] (may be NULL); bf16_out: device uint16 [n][k]
  * (bfloat16 bits, round to nearest even; may be NULL); fp8_out: device uint8
  * [n][k] (float8 e4m3fn bits of u / scale, round to nearest even; may be
- * NULL); scale_out: device float [n] with scale = max_c |u_c| / 448 (may be
- * NULL); err_out: device float [2][n]: per-row |u - dequantised|_2 bounds for
+ * NULL); scale_out: device float [n] with scale = the smallest power of two
+ * >= max_c |u_c| / 448 (the quotient in float32; an E8M0 operand scale of the
+ * matrix cores; may be NULL); err_out: device float [2][n]: per-row |u - dequantised|_2 bounds for
  * bf16 then fp8 (may be NULL). */
 mrc_status mrc_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit_out,
                          uint16_t* bf16_out, uint8_t* fp8_out, float* scale_out, float* err_out,

@@ -120,15 +120,15 @@ __global__ __launch_bounds__(256, 1) void k_compare_f32w(const float* __restrict
 namespace mrc {
 
 mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau, PairSink sink,
-                              hipStream_t s) {
+                              hipStream_t s, int64_t* table) {
     if (n < 2) return MRC_OK;
     const int nc = mfma_chunks(k);
     // short signatures: the flag walk outweighs the short products (64x64 tiles,
     // two wavefronts per SIMD); very long ones: too many registers for 128x128
-    if (nc <= 4 || nc > 32) return launch_compare_f32_small(ctx, umfma, n, k, tau, sink, s);
+    if (nc <= 4 || nc > 32) return launch_compare_f32_small(ctx, umfma, n, k, tau, sink, s, table);
     TileOrder ord;
     int64_t grid = 0;
-    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kTW), 4, &ord, &grid, s));
+    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kTW), 4, &ord, &grid, s, table));
     ScopedTimer tm(ctx, "compare_f32", s);
     switch (nc) {
 #define MRC_NC(c)                                                                                          \

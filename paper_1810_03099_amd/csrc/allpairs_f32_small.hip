@@ -104,11 +104,11 @@ __global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u
 namespace mrc {
 
 mrc_status launch_compare_f32_small(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
-                                    PairSink sink, hipStream_t s) {
+                                    PairSink sink, hipStream_t s, int64_t* table) {
     if (n < 2) return MRC_OK;
     TileOrder ord;
     int64_t grid = 0;
-    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s));
+    MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s, table));
     const int nc = mfma_chunks(k);
     ScopedTimer tm(ctx, "compare_f32", s);
     switch (nc) {

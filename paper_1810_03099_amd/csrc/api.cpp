@@ -372,6 +372,20 @@ mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, 
     return sync_flags(ctx, s, 1, "mrc_sign");
 }
 
+mrc_status mrc_sign_matrix(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, const float* R, int32_t k,
+                           float* sig_out, float* norm_out, void* hip_stream) {
+    MRC_TRY(check_ctx(ctx, "mrc_sign_matrix"));
+    MRC_TRY(check_docs(docs, "mrc_sign_matrix"));
+    if (!model) return fail(MRC_E_INVAL, "mrc_sign_matrix: model is NULL");
+    if (model->ctx->device != ctx->device) return fail(MRC_E_INVAL, "mrc_sign_matrix: model lives on another device");
+    if (k < 1 || k > 1024) return fail(MRC_E_INVAL, "mrc_sign_matrix: k must lie in [1, 1024]");
+    if (!R) return fail(MRC_E_INVAL, "mrc_sign_matrix: R is NULL");
+    if (docs->n_docs > 0 && !sig_out) return fail(MRC_E_INVAL, "mrc_sign_matrix: sig_out is NULL");
+    hipStream_t s = (hipStream_t)hip_stream;
+    MRC_TRY(launch_sign_matrix(ctx, model, docs, R, k, sig_out, norm_out, s));
+    return sync_flags(ctx, s, 1, "mrc_sign_matrix");
+}
+
 // ------------------------------------------------------------------ comparison
 
 mrc_status mrc_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit_out,

@@ -176,6 +176,14 @@ mrc_status count_scratch(mrc_ctx* ctx, const mrc_docs* docs, CountLists* c);
 mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, uint32_t* d_df, const CountLists& c,
                      hipStream_t s);
 
+// The count pass alone: the distinct terms of each document with their counts
+// (also checks offsets and token ids, error bits in ctx->d_flags[0]).
+mrc_status launch_counts(mrc_ctx* ctx, const mrc_docs* docs, int32_t vocab, const CountLists& c, hipStream_t s);
+
+// Signatures against the k columns of a dense [V][k] reference matrix R.
+mrc_status launch_sign_matrix(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const float* R, int32_t k,
+                              float* sig_out, float* norm_out, hipStream_t s);
+
 // Signatures of the corpus whose count lists `c` holds (bit-identical to
 // launch_sign on the same documents).
 mrc_status launch_sign_counts(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, const CountLists& c,
@@ -215,11 +223,13 @@ struct PairSink {
     unsigned long long* counter;  // device: number of pairs found
 };
 
+// `table` (optional): device words for the tile order's band table (at least
+// n / 64 / TileOrder::kBand + 2 of them), else the context's scratch holds it.
 mrc_status launch_compare_f32(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
-                              PairSink sink, hipStream_t s);
+                              PairSink sink, hipStream_t s, int64_t* table = nullptr);
 // 64x64-tile form of the same (allpairs_f32_small.hip; k <= 64 or k > 512).
 mrc_status launch_compare_f32_small(mrc_ctx* ctx, const float* umfma, int64_t n, int32_t k, float tau,
-                                    PairSink sink, hipStream_t s);
+                                    PairSink sink, hipStream_t s, int64_t* table = nullptr);
 
 // Even number of 16x16 matrix-core steps (32 BF16 or 128 FP8 components)
 // covering k: the column padding of the query kernels' code layouts.
@@ -357,7 +367,10 @@ struct TileOrder {
     }
 };
 
-mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s);
+// The band table goes to `table` (device, n_bands + 1 words) when given, else
+// to context scratch (kept for the next call with the same tile count).
+mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s,
+                           int64_t* table = nullptr);
 // Low-precision candidate kernels (lds_allpairs.hip, LDS-tiled 256x256 blocks),
 // called by launch_compare_lowp. The codes need ceil(n / 256) * 256 rows of
 // ldq_bytes = 128 * lowp_lds_chunks(precision, k) bytes, zero padded; the FP8
@@ -395,6 +408,9 @@ constexpr int64_t kMaxDocLen = 1 << 22;  // longest document (exact 64/128-bit s
 // Error bits of ctx->d_flags[0], set by kernels and decoded after the call.
 constexpr unsigned long long kErrOffsets = 1, kErrToken = 2, kErrSelection = 4, kErrTailCap = 8,
                              kErrQueryCap = 16, kErrDocLen = 32;
+// Context word of the query collection's capacity signal (kErrQueryCap): kept
+// apart from word 0, whose input-error bits the query's signing pass sets.
+constexpr int kQueryCapWord = 40;
 
 }  // namespace mrc
 

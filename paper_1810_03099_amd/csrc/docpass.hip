@@ -29,8 +29,10 @@
 #include <type_traits>
 
 #include "common.h"
+#include "exact_sums.h"
 
 using namespace mrc;
+using namespace mrc_exact;
 
 namespace {
 
@@ -38,50 +40,6 @@ constexpr int kBlock = 256;
 constexpr int kEmpty = -1;
 constexpr int kHistSlice = 65536;  // vocabulary ids per LDS histogram slice (16-bit counters)
 constexpr int kHistMaxSlices = 8;  // above this, df is counted with global atomics instead
-
-typedef unsigned __int128 u128;
-
-// --------------------------------------------------------------- exact sums
-
-// tf * idf^2 * 2^46 (the contribution of one occurrence of a term with count tf)
-__device__ __forceinline__ u128 occ_sq_fixed(uint32_t tf, float idf) {
-    const uint32_t b = __float_as_uint(idf);
-    const int E = (int)(b >> 23) - 127;  // 0 <= E <= 4 for idf in [1, 32)
-    const uint64_t m = (b & 0x7FFFFFu) | 0x800000u;
-    return ((u128)(m * m) * tf) << (2 * E);
-}
-
-// (tf * idf)^2 * 2^46 (the contribution of a distinct term with count tf)
-__device__ __forceinline__ u128 term_sq_fixed(uint32_t tf, float idf) {
-    const uint32_t b = __float_as_uint(idf);
-    const int E = (int)(b >> 23) - 127;
-    const uint64_t m = (b & 0x7FFFFFu) | 0x800000u;
-    const uint64_t a = (uint64_t)tf * m;
-    return ((u128)a * a) << (2 * E);
-}
-
-// Correctly rounded u128 -> double: the leading 64 bits with a sticky bit for
-// the rest (below the rounding position), converted once.
-__device__ __forceinline__ double u128_to_double(u128 v) {
-    const uint64_t hi = (uint64_t)(v >> 64), lo = (uint64_t)v;
-    if (hi == 0) return (double)lo;
-    const int lz = __clzll((long long)hi);
-    const uint64_t top = lz ? (hi << lz) | (lo >> (64 - lz)) : hi;
-    const uint64_t rest = lz ? (lo << lz) : lo;
-    return ldexp((double)(top | (rest != 0 ? 1ull : 0ull)), 64 - lz);
-}
-
-__device__ __forceinline__ double norm_from_fixed(u128 s) { return sqrt(u128_to_double(s) * 0x1p-46); }
-
-__device__ __forceinline__ u128 wave_sum_u128(u128 v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint64_t lo = __shfl_xor((unsigned long long)(uint64_t)v, off, 64);
-        const uint64_t hi = __shfl_xor((unsigned long long)(uint64_t)(v >> 64), off, 64);
-        v += ((u128)hi << 64) | lo;
-    }
-    return v;
-}
 
 // ------------------------------------------------------------------ helpers
 
@@ -583,12 +541,6 @@ __global__ __launch_bounds__(256) void k_df_atomic(const int64_t* __restrict__ o
 
 // One wavefront per document over its distinct-term list (same exact sums as
 // the hash passes, so the same signature bits).
-// mantissa(x) << exponent(x) for a float 1 <= x < 32: x * 2^23, an integer
-// below 2^28.
-__device__ __forceinline__ uint32_t idf_scaled(float x) {
-    const uint32_t b = __float_as_uint(x);
-    return ((b & 0x7FFFFFu) | 0x800000u) << ((b >> 23) - 127u);
-}
 
 // c * 2^32 for a float 1 <= c < 2^24 (the value mrc_dev::fixed32 gives, from
 // the bits alone).
@@ -821,6 +773,14 @@ mrc_status count_scratch(mrc_ctx* ctx, const mrc_docs* docs, CountLists* c) {
     c->tf = (int32_t*)pf;
     c->nnz = (int32_t*)pn;
     return MRC_OK;
+}
+
+mrc_status launch_counts(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const CountLists& c, hipStream_t s) {
+    PassArgs a{};
+    a.cnt_term = c.term;
+    a.cnt_tf = c.tf;
+    a.cnt_nnz = c.nnz;
+    return run_docpass<MODE_COUNT>(ctx, docs, V, a, s, "counts");
 }
 
 mrc_status launch_df(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, uint32_t* d_df, const CountLists& c,

@@ -858,7 +858,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         MRC_TRY(scratch(ctx, "q_cand", (size_t)nq * cap * 8, &cand));
         MRC_TRY(scratch(ctx, "q_ccount", (size_t)nq * 4, &cc));
         MRC_HIP_TRY(ctx, hipMemsetAsync(cc, 0, (size_t)nq * 4, s));
-        MRC_TRY(clear_words(ctx, ctx->d_flags, 1, s));
+        MRC_TRY(clear_words(ctx, ctx->d_flags + kQueryCapWord, 1, s));
         a.thr = (const float*)thr;
         a.cand = (int64_t*)cand;
         a.ccount = (int32_t*)cc;
@@ -866,12 +866,17 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         MRC_TRY(collect());
         hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)cand,
                            (const int32_t*)cc, cap, (const float*)unit, k, db->d_unit, L.kp, tau, topk, topk_out,
-                           n_hits, fp32 ? 0 : 1, (unsigned long long*)ctx->d_flags);
+                           n_hits, fp32 ? 0 : 1, (unsigned long long*)(ctx->d_flags + kQueryCapWord));
         MRC_HIP_TRY(ctx, hipGetLastError());
-        int64_t flag = 0;
-        MRC_HIP_TRY(ctx, hipMemcpyAsync(&flag, ctx->d_flags, 8, hipMemcpyDeviceToHost, s));
+        // word 0 holds the signing pass's input errors (the scans ran on
+        // whatever the early-returning document kernels left, in bounds);
+        // the capacity signal has a word of its own
+        MRC_HIP_TRY(ctx, hipMemcpyAsync(ctx->h_flags, ctx->d_flags, (kQueryCapWord + 1) * sizeof(int64_t),
+                                        hipMemcpyDeviceToHost, s));
         MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
-        if (!(flag & 16)) return MRC_OK;
+        if (ctx->h_flags[0] & (kErrOffsets | kErrToken | kErrDocLen))
+            return fail(MRC_E_INVAL, "mrc_query: malformed offsets, token ids or document lengths");
+        if (!(ctx->h_flags[kQueryCapWord] & kErrQueryCap)) return MRC_OK;
         std::vector<int32_t> counts(nq);
         MRC_HIP_TRY(ctx, hipMemcpy(counts.data(), cc, (size_t)nq * 4, hipMemcpyDeviceToHost));
         cap = std::max(cap, *std::max_element(counts.begin(), counts.end()));

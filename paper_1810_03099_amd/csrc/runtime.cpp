@@ -123,25 +123,45 @@ void timer_collect(mrc_ctx* ctx) {
     ctx->pending.clear();
 }
 
-mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s) {
+// start[b] = first tile index of band b (b = 0 .. n_bands): one thread per band
+// sums the sizes of the bands before it.
+__global__ void k_band_starts(int nb, int n_bands, int64_t* __restrict__ start) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b > n_bands) return;
+    const int B = TileOrder::kBand;
+    int64_t t = 0;
+    for (int x = 0; x < b; ++x) {
+        const int r0 = x * B, h = min(B, nb - r0);
+        t += (int64_t)h * (h + 1) / 2 + (int64_t)h * (nb - r0 - h);
+    }
+    start[b] = t;
+}
+
+mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s,
+                           int64_t* table) {
     const int B = TileOrder::kBand;
     const int n_bands = (nb + B - 1) / B;
-    std::vector<int64_t> start(n_bands + 1);
     int64_t t = 0;
     for (int b = 0; b < n_bands; ++b) {
-        start[b] = t;
         const int r0 = b * B, h = std::min(B, nb - r0);
         t += (int64_t)h * (h + 1) / 2 + (int64_t)h * (nb - r0 - h);
     }
-    start[n_bands] = t;
-    void* d = nullptr;
-    auto it = ctx->scratch.find("tile_order");
-    const bool cached = ctx->tile_order_nb == nb && it != ctx->scratch.end();
-    MRC_TRY(scratch(ctx, "tile_order", (size_t)(n_bands + 1) * sizeof(int64_t), &d));
-    if (!cached) {
-        MRC_HIP_TRY(ctx, hipMemcpyAsync(d, start.data(), (n_bands + 1) * sizeof(int64_t), hipMemcpyHostToDevice, s));
-        MRC_HIP_TRY(ctx, hipStreamSynchronize(s));  // the host vector must outlive the copy
-        ctx->tile_order_nb = nb;
+    void* d = table;
+    if (!table) {
+        // the context keeps the table of the last tile count it was made for
+        auto it = ctx->scratch.find("tile_order");
+        const bool cached = ctx->tile_order_nb == nb && it != ctx->scratch.end();
+        MRC_TRY(scratch(ctx, "tile_order", (size_t)(n_bands + 1) * sizeof(int64_t), &d));
+        if (!cached) {
+            hipLaunchKernelGGL(k_band_starts, dim3((unsigned)ceil_div(n_bands + 1, 256)), dim3(256), 0, s, nb,
+                               n_bands, (int64_t*)d);
+            MRC_HIP_TRY(ctx, hipGetLastError());
+            ctx->tile_order_nb = nb;
+        }
+    } else {
+        hipLaunchKernelGGL(k_band_starts, dim3((unsigned)ceil_div(n_bands + 1, 256)), dim3(256), 0, s, nb, n_bands,
+                           table);
+        MRC_HIP_TRY(ctx, hipGetLastError());
     }
     ord->nb = nb;
     ord->n_bands = n_bands;

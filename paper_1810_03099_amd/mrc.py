@@ -34,7 +34,7 @@ REQ_QUERY, REQ_INSERT = 0, 1
 EXPORTS = (
     "mrc_ctx_create", "mrc_ctx_destroy", "mrc_ctx_memory", "mrc_ctx_set_timing", "mrc_ctx_kernel_time",
     "mrc_last_error", "mrc_build_vocab_idf", "mrc_build_and_sign", "mrc_model_destroy", "mrc_model_info", "mrc_model_get",
-    "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_compare", "mrc_normalise", "mrc_score_pairs",
+    "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_sign_matrix", "mrc_compare", "mrc_normalise", "mrc_score_pairs",
     "mrc_trigrams", "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
     "mrc_db_destroy", "mrc_db_insert", "mrc_db_insert_docs", "mrc_db_size", "mrc_db_save", "mrc_db_load",
     "mrc_query", "mrc_serve_start", "mrc_serve_submit", "mrc_serve_submit_many", "mrc_serve_poll", "mrc_serve_stop",
@@ -112,6 +112,7 @@ _SIGS = {
     "mrc_model_save": [_P, C.c_char_p],
     "mrc_model_load": [_P, C.c_char_p, C.POINTER(_P)],
     "mrc_sign": [_P, _P, C.POINTER(MrcDocs), _P, _P, _P],
+    "mrc_sign_matrix": [_P, _P, C.POINTER(MrcDocs), _P, C.c_int32, _P, _P, _P],
     "mrc_compare": [_P, _P, C.c_int64, C.c_int32, C.POINTER(MrcCompareOpts), _P, C.c_int64,
                     C.POINTER(C.c_int64), C.POINTER(MrcCompareStats), _P],
     "mrc_normalise": [_P, _P, C.c_int64, C.c_int32, _P, _P, _P, _P, _P, _P],
@@ -333,6 +334,22 @@ def mrc_sign(ctx, model, offsets, tokens, sig_out=None, norm_out=None, stream=No
         norm_out = torch.empty((d.n_docs,), dtype=torch.float32, device=offsets.device)
     _check(lib().mrc_sign(ctx, model, C.byref(d), _dptr(sig_out, torch.float32, "sig_out"),
                           _dptr(norm_out, torch.float32, "norm_out"), _stream(stream)), "mrc_sign")
+    return (sig_out, norm_out) if with_norm else sig_out
+
+
+def mrc_sign_matrix(ctx, model, offsets, tokens, R, sig_out=None, norm_out=None, stream=None, with_norm=False):
+    """Signatures against the columns of a dense [V][k] float32 device matrix R."""
+    d, _keep = _docs(offsets, tokens)
+    if R.dim() != 2:
+        raise ValueError("R must be a [V][k] matrix")
+    k = int(R.shape[1])
+    if sig_out is None:
+        sig_out = torch.empty((d.n_docs, k), dtype=torch.float32, device=offsets.device)
+    if norm_out is None and with_norm:
+        norm_out = torch.empty((d.n_docs,), dtype=torch.float32, device=offsets.device)
+    _check(lib().mrc_sign_matrix(ctx, model, C.byref(d), _dptr(R, torch.float32, "R"), k,
+                                 _dptr(sig_out, torch.float32, "sig_out"), _dptr(norm_out, torch.float32, "norm_out"),
+                                 _stream(stream)), "mrc_sign_matrix")
     return (sig_out, norm_out) if with_norm else sig_out
 
 

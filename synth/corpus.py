@@ -22,7 +22,9 @@ Seeds are 181003099 + the 0-based position of the configuration in `CONFIGS`.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass, field
+
 import numpy as np
 
 BASE_SEED = 181003099
@@ -115,13 +117,25 @@ class _Sampler:
     def draw(self, rng: np.random.Generator, topics: np.ndarray) -> np.ndarray:
         """One token per entry of `topics` (the topic of the document it belongs to)."""
         n = topics.shape[0]
-        u = rng.random(n) * self.cdf[-1]
-        r0 = np.searchsorted(self.cdf, u, side="right")
-        r0 = np.minimum(r0, self.vocab - 1)           # rank r0+1 -> index r0
+        u = rng.random(n)
         use_topic = rng.random(n) < self.topic_weight
-        out = r0.astype(np.int32)
-        out[use_topic] = self.perms[topics[use_topic], r0[use_topic]]
-        return out
+
+        def part(sl):
+            r0 = np.searchsorted(self.cdf, u[sl] * self.cdf[-1], side="right")
+            np.minimum(r0, self.vocab - 1, out=r0)      # rank r0+1 -> index r0
+            out = r0.astype(np.int32)
+            m = use_topic[sl]
+            out[m] = self.perms[topics[sl][m], r0[m]]
+            return out
+
+        if n < (1 << 22):
+            return part(slice(None))
+        # large draws: the same per-element steps over slices in threads (NumPy
+        # releases the GIL inside them)
+        from concurrent.futures import ThreadPoolExecutor
+        step = -(-n // 64)
+        with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+            return np.concatenate(list(ex.map(part, [slice(i, min(n, i + step)) for i in range(0, n, step)])))
 
 
 def _lengths(rng, n, median, sigma, lo, hi):
