@@ -340,8 +340,8 @@ def mrc_sign(ctx, model, offsets, tokens, sig_out=None, norm_out=None, stream=No
 def mrc_sign_matrix(ctx, model, offsets, tokens, R, sig_out=None, norm_out=None, stream=None, with_norm=False):
     """Signatures against the columns of a dense [V][k] float32 device matrix R."""
     d, _keep = _docs(offsets, tokens)
-    if R.dim() != 2:
-        raise ValueError("R must be a [V][k] matrix")
+    if R.dim() != 2 or int(R.shape[0]) != mrc_model_info(model)["vocab"]:
+        raise ValueError("R must be a [V][k] matrix, V = the model's vocabulary")
     k = int(R.shape[1])
     if sig_out is None:
         sig_out = torch.empty((d.n_docs, k), dtype=torch.float32, device=offsets.device)
