@@ -250,6 +250,30 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k,
                        const mrc_compare_opts* opts, mrc_pair* pairs_out, int64_t capacity,
                        int64_t* n_found, mrc_compare_stats* stats, void* hip_stream);
 
+/* For callers that cannot allocate device memory: code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc. The FP32 form
+ * of mrc_compare (same kernels, same pairs and scores, bit for bit) with its
+ * working memory (pair counter, tile-order table, unit signatures in the
+ * matrix-core layout) in a fixed device array of the library, one per GPU,
+ * held from the first mrc_ctx_create on that GPU until the process ends. The
+ * call allocates nothing; the caller passes inputs and outputs as for
+ * mrc_compare (sig device float [n][k]; pairs_out device mrc_pair [capacity];
+ * n_found host).
+ * Limit: ceil(n / 128) * 128 rows x 16 * mfma_chunks(k) columns x 4 bytes
+ * (columns = k rounded up to 32, 64, 96, 128, 192, 256, 384, 512, 768 or
+ * 1024) must not exceed MRC_NOALLOC_MAX_UNIT_BYTES (32 MiB), e.g.
+ * n <= 131,072 at k = 64 and n <= 32,768 at k = 256; larger inputs return
+ * MRC_E_INVAL before any device work. The array is that plus 8 KiB.
+ * Every call on one GPU uses that GPU's array, so calls that overlap on one
+ * GPU (several streams or threads) race; the array keeps the last call's
+ * contents (the call clears what must start at zero). Synchronises the stream
+ * (it returns the count). Errors: MRC_E_INVAL (sizes, NULL buffers, NaN tau),
+ * MRC_E_OVERFLOW (two-call protocol as mrc_compare), MRC_E_STATE (the array
+ * was not set up on this GPU), MRC_E_HIP. */
+#define MRC_NOALLOC_MAX_UNIT_BYTES ((size_t)32 << 20)
+mrc_status mrc_compare_f32_noalloc(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float tau,
+                                   mrc_pair* pairs_out, int64_t capacity, int64_t* n_found, void* hip_stream);
+
 /* Unit signatures and their low-precision forms, as mrc_compare uses them.
  * unit_out: device float [n][k] (may be NULL); bf16_out: device uint16 [n][k]
  * (bfloat16 bits, round to nearest even; may be NULL); fp8_out: device uint8

@@ -9,8 +9,7 @@
 
 using namespace mrc;
 
-namespace {
-
+namespace mrc {
 
 mrc_status check_ctx(mrc_ctx* ctx, const char* fn) {
     if (!ctx) return fail(MRC_E_INVAL, std::string(fn) + ": ctx is NULL");
@@ -23,6 +22,10 @@ mrc_status check_ctx(mrc_ctx* ctx, const char* fn) {
     (void)hipGetLastError();
     return MRC_OK;
 }
+
+}  // namespace mrc
+
+namespace {
 
 mrc_status check_docs(const mrc_docs* d, const char* fn) {
     if (!d) return fail(MRC_E_INVAL, std::string(fn) + ": docs is NULL");

@@ -113,6 +113,11 @@ struct mrc_db {
 namespace mrc {
 
 mrc_status hip_fail(mrc_ctx* ctx, hipError_t e, const char* what, const char* file, int line);
+// Entry-point check of a context: not NULL, not poisoned; makes its device current.
+mrc_status check_ctx(mrc_ctx* ctx, const char* fn);
+// Resolves the device address of the fixed scratch array of the no-allocation
+// comparison for `device` (current), once per device.
+mrc_status noalloc_setup(int device);
 
 // Context lifetime (see mrc_ctx::live): an object that holds the context
 // retains it when created and releases it when freed; the release that ends

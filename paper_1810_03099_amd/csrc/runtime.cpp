@@ -257,8 +257,9 @@ mrc_status mrc_ctx_create(mrc_ctx** out, int32_t device, size_t hbm_budget_bytes
     e = hipMalloc((void**)&ctx->d_flags, 64 * sizeof(int64_t));
     if (e == hipSuccess) e = hipHostMalloc((void**)&ctx->h_flags, 64 * sizeof(int64_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, 64 * sizeof(int64_t));
-    if (e != hipSuccess) {
-        mrc_status st = hip_fail(nullptr, e, "context flags", __FILE__, __LINE__);
+    mrc_status st = e != hipSuccess ? hip_fail(nullptr, e, "context flags", __FILE__, __LINE__) : MRC_OK;
+    if (st == MRC_OK) st = noalloc_setup(device);  // the no-allocation comparison's array on this device
+    if (st != MRC_OK) {
         if (ctx->d_flags) (void)hipFree(ctx->d_flags);
         if (ctx->h_flags) (void)hipHostFree(ctx->h_flags);
         delete ctx;

@@ -34,7 +34,7 @@ REQ_QUERY, REQ_INSERT = 0, 1
 EXPORTS = (
     "mrc_ctx_create", "mrc_ctx_destroy", "mrc_ctx_memory", "mrc_ctx_set_timing", "mrc_ctx_kernel_time",
     "mrc_last_error", "mrc_build_vocab_idf", "mrc_build_and_sign", "mrc_model_destroy", "mrc_model_info", "mrc_model_get",
-    "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_sign_matrix", "mrc_compare", "mrc_normalise", "mrc_score_pairs",
+    "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_sign_matrix", "mrc_compare", "mrc_compare_f32_noalloc", "mrc_normalise", "mrc_score_pairs",
     "mrc_trigrams", "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
     "mrc_db_destroy", "mrc_db_insert", "mrc_db_insert_docs", "mrc_db_size", "mrc_db_save", "mrc_db_load",
     "mrc_query", "mrc_serve_start", "mrc_serve_submit", "mrc_serve_submit_many", "mrc_serve_poll", "mrc_serve_stop",
@@ -115,6 +115,7 @@ _SIGS = {
     "mrc_sign_matrix": [_P, _P, C.POINTER(MrcDocs), _P, C.c_int32, _P, _P, _P],
     "mrc_compare": [_P, _P, C.c_int64, C.c_int32, C.POINTER(MrcCompareOpts), _P, C.c_int64,
                     C.POINTER(C.c_int64), C.POINTER(MrcCompareStats), _P],
+    "mrc_compare_f32_noalloc": [_P, _P, C.c_int64, C.c_int32, C.c_float, _P, C.c_int64, C.POINTER(C.c_int64), _P],
     "mrc_normalise": [_P, _P, C.c_int64, C.c_int32, _P, _P, _P, _P, _P, _P],
     "mrc_score_pairs": [_P, _P, C.c_int64, C.c_int32, _P, _P, C.c_int64, _P, _P],
     "mrc_trigrams": [_P, _P, _P, C.c_int64, C.c_int64, _P, _P, C.c_int64, C.POINTER(C.c_int64), _P],
@@ -382,6 +383,26 @@ def mrc_compare(ctx, sig, tau=0.9, precision=PREC_FP32, band=0.02, capacity=None
 
     pairs = _pairs_call("mrc_compare", call, capacity if capacity is not None else 4 * n + 1024, sig.device)
     return pairs, stats.as_dict()
+
+
+NOALLOC_MAX_UNIT_BYTES = 32 << 20
+
+
+def mrc_compare_f32_noalloc(ctx, sig, tau, pairs_out, stream=None):
+    """FP32 all-pairs comparison into the caller's pair buffer (int32 device
+    tensor [capacity, 4]); the library allocates nothing. Returns
+    (n_found, overflowed): on overflow the first `capacity` pairs are written
+    and n_found is the exact count."""
+    n, k = sig.shape
+    cap = int(pairs_out.shape[0])
+    nf = C.c_int64()
+    st = lib().mrc_compare_f32_noalloc(ctx, _dptr(sig, torch.float32, "sig"), int(n), int(k), float(tau),
+                                       _dptr(pairs_out, torch.int32, "pairs_out") if cap > 0 else None, cap,
+                                       C.byref(nf), _stream(stream))
+    if st == MRC_E_OVERFLOW:
+        return int(nf.value), True
+    _check(st, "mrc_compare_f32_noalloc")
+    return int(nf.value), False
 
 
 def pairs_to_numpy(pairs):
