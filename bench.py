@@ -16,8 +16,13 @@ Extras (same corpus, outside the timed steps): every precision form, the
 comparators (exact TF-IDF cosine, Simhash-64 + Hamming), recall / precision
 against exact cosine, each form's error against a float64 comparison of the
 same signatures, query latency against a database of the corpus, and the sign
-pass against HBM bandwidth. Only the CPU-baseline leg runs the FP64 oracle (its
-timed sample, and the check of the step's decisions and scores against it).
+pass against HBM bandwidth. Then two legs on the larger workloads
+(--no-scale-legs skips them): the precision form (200,000 documents, k = 256:
+the comparison kernels at FP32 / BF16 / FP8 against their matrix-core peaks)
+and the serving form (a 1,000,000-row k = 128 database: build rate, mrc_query
+batches, the serving loop's p50 / p99 under Poisson arrivals at half of its
+saturation). Only the CPU-baseline leg runs the FP64 oracle (its timed sample,
+and the check of the step's decisions and scores against it).
 
 Prints one JSON line.
 """
@@ -67,6 +72,8 @@ def parse():
                     help="serving workload: length of each offered-load run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--no-scale-legs", action="store_true",
+                    help="skip the precision-form (200k docs) and serving-form (1M-row database) legs of the extras")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy MIB MiB device-to-device 5 times (calibrates HBM byte counters) and exit")
     return ap.parse_args()
@@ -278,6 +285,13 @@ def main():
     if not a.no_extras:
         out["extras"] = extras(mrc, ctx, c, off, tok, sig, state["model"], k, tau, cap, sign_ms,
                                ktimes.get("sign_counts", {}).get("avg_ms"))
+        if not a.no_scale_legs:
+            # the precision and serving forms' workloads, measured in the same run
+            del off, tok, sig, state
+            torch.cuda.synchronize()
+            torch.cuda.empty_cache()
+            out["extras"]["precision_form"] = precision_leg(mrc, synth)
+            out["extras"]["serving_form"] = serving_leg(mrc, synth)
     print(json.dumps(out))
 
 
@@ -617,6 +631,125 @@ def extras(mrc, ctx, c, off, tok, sig, model, k, tau, cap, sign_ms, counts_ms):
     return ex
 
 
+def precision_leg(mrc, synth, tau=0.9):
+    """The precision form's workload (200,000 documents over a 262,144-term
+    vocabulary, median 400 tokens, k = 256): model build + signing, then the
+    all-pairs comparison kernels at FP32, BF16 and FP8 (+ FP32 rescoring of
+    the band), each timed with HIP events on its launch stream and set against
+    its form's dense matrix-core peak; decisions across the forms, and each
+    form's error against a float64 comparison on a 5,000-document subsample."""
+    import torch
+    cs = synth.CONFIGS[2]
+    k = cs.k
+    log(f"precision form: generating {cs.n_docs} docs")
+    c = synth.generate(2)
+    ctx = mrc.mrc_ctx_create(0)
+    off = torch.from_numpy(c.offsets).cuda()
+    tok = torch.from_numpy(c.tokens).cuda()
+    sig = torch.empty((c.n_docs, k), dtype=torch.float32, device="cuda")
+    mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(k), sig_out=sig)
+    torch.cuda.synchronize()
+    kms, wall, _ = timed(mrc, ctx, "sign_counts", lambda: mrc.mrc_build_and_sign(ctx, off, tok, c.vocab,
+                                                                               mrc.ref_spec(k), sig_out=sig), 3)
+    out = {"workload": f"precision: {c.n_docs} docs, vocab {cs.vocab}, k={k}, tau={tau}, band 0.02 (FP8: per-pair "
+                       f"bound, at least 0.02)", "tokens": int(c.tokens.size),
+           "build_and_sign_ms": wall, "docs_signed_per_s": c.n_docs / (wall / 1e3), "sign_counts_ms": kms,
+           "algorithmic_flops_per_compare_launch": c.n_docs * (c.n_docs - 1) / 2 * 2 * k}
+    del off, tok
+    out.update(precision_extras(mrc, ctx, c, sig, k, tau, 16 * 1024 * 1024))
+    for name in ("fp32", "bf16", "fp8"):
+        f = out["forms"][name]
+        f["achieved_TFLOPs"] = out["algorithmic_flops_per_compare_launch"] / (f["kernel_ms"] / 1e3) / 1e12
+    del sig, c
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+def serving_leg(mrc, synth, tau=0.9, n_queries=4096, seconds=3.0):
+    """The serving form's workload, short: a 1,000,000-signature database
+    (k = 128, FP32 + BF16 copies) built and signed on the GPU; closed-loop
+    mrc_query batches of 1, 256 and 4096 queries (FP32 and BF16); the serving
+    loop (2 streams, batches up to 4096) at saturation and under Poisson
+    arrivals at half of it, p50 / p99 submit-to-result latency."""
+    import torch
+    cs = synth.CONFIGS[3]
+    k = cs.k
+    log(f"serving form: generating the {cs.n_docs}-document database corpus")
+    c = synth.generate(3)
+    n = c.n_docs
+    ctx = mrc.mrc_ctx_create(0)
+    off = torch.from_numpy(c.offsets).cuda()
+    tok = torch.from_numpy(c.tokens).cuda()
+    sig = torch.empty((n, k), dtype=torch.float32, device="cuda")
+    model, _ = mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(k), sig_out=sig)
+    del model
+    torch.cuda.synchronize()
+    kms, wall, (model, _) = timed(mrc, ctx, "sign_counts",
+                                  lambda: mrc.mrc_build_and_sign(ctx, off, tok, c.vocab, mrc.ref_spec(k),
+                                                                 sig_out=sig), 3)
+    docid = np.repeat(np.arange(n, dtype=np.int64), np.diff(c.offsets))
+    nnz = int(np.unique(docid * c.vocab + c.tokens).size)
+    del docid
+    by = nnz * 8 + (n + 1) * 8 + n * k * 4
+    out = {"workload": f"serving: database {n} signatures x k={k} (FP32 + BF16) resident, queries lognormal median "
+                       f"400, sigma 1.2, 20-20,000 tokens, 20% near duplicates of database documents; top-16 + "
+                       f"tau={tau}",
+           "database_build": {"docs": n, "tokens": int(c.tokens.size), "build_and_sign_ms": wall,
+                              "docs_signed_per_s": n / (wall / 1e3),
+                              "sign_counts": {"bound": "hbm", "avg_ms": kms, "algorithmic_bytes": by, "nnz": nnz,
+                                              "achieved_GBps": by / (kms / 1e3) / 1e9,
+                                              "frac": by / (kms / 1e3) / 1e9 / PEAKS["hbm_GBps"]}}}
+    log(f"serving form: build + sign {wall:.1f} ms, sign_counts {kms:.2f} ms")
+    db = mrc.mrc_db_create(ctx, n + 65536, k, precisions=(mrc.PREC_BF16,))
+    mrc.mrc_db_insert(db, sig)
+    torch.cuda.synchronize()
+    del off, tok, sig
+    torch.cuda.empty_cache()
+    qc = synth.generate_queries(cs, n_queries, seed=31, median=400, sigma=1.2, hi=20000, near_of=c, near_frac=0.2)
+    del c
+    qo = torch.from_numpy(qc.offsets).cuda()
+    qt = torch.from_numpy(qc.tokens).cuda()
+    batch = {}
+    for pname, p in [("fp32", mrc.PREC_FP32), ("bf16", mrc.PREC_BF16)]:
+        rows = {}
+        for b in (1, 256, 4096):
+            o1 = (qo[:b + 1] - qo[0]).contiguous()
+            t1 = qt[int(qc.offsets[0]):int(qc.offsets[b])].contiguous()
+            mrc.mrc_query(ctx, db, model, o1, t1, 16, tau, p)
+            torch.cuda.synchronize()
+            reps = 10 if b < 256 else 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                mrc.mrc_query(ctx, db, model, o1, t1, 16, tau, p)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / reps
+            rows[str(b)] = {"ms": dt * 1e3, "queries_per_s": b / dt, "pairs_per_s": b * n / dt}
+        batch[pname] = rows
+        log(f"serving form mrc_query {pname}: " + ", ".join(f"b={b} {r['ms']:.2f} ms" for b, r in rows.items()))
+    out["query_batches"] = batch
+    docs = [qc.doc(i) for i in range(qc.n_docs)]
+    loop = {}
+    rng = np.random.default_rng(41)
+    for pname, p in [("bf16", mrc.PREC_BF16), ("fp32", mrc.PREC_FP32)]:
+        srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=p,
+                                  max_wait_us=500)
+        sat = serve_run(mrc, srv, [0.0] * 8192, docs)
+        lam = 0.5 * sat["docs_per_s"]
+        m = int(min(max(lam * seconds, 200), 40000))
+        half = serve_run(mrc, srv, rng.exponential(1.0 / lam, m).tolist(), docs)
+        half["offered_docs_per_s"] = lam
+        mrc.mrc_serve_stop(srv)
+        loop[pname] = {"saturation_queries_per_s": sat["docs_per_s"], "poisson_0.5": half}
+        log(f"serving form loop {pname}: saturation {sat['docs_per_s']:.0f}/s; at 0.5 load p50 "
+            f"{half['p50_ms']:.2f} ms, p99 {half['p99_ms']:.2f} ms")
+    out["serving_loop"] = loop
+    del db, model, qo, qt
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
 def serving_fp8(mrc, synth, ctx, c, qc, run, tau):
     """Serving with an FP8 database at scale: 4,000,000 rows x k = 256 (FP8 codes
     + row scales + the FP32 rescoring copy), built from four copies of the
@@ -658,6 +791,62 @@ def serving_fp8(mrc, synth, ctx, c, qc, run, tau):
             f"{half['query_p50_ms']:.2f} ms, p99 {half['query_p99_ms']:.2f} ms")
     res["database_rows_after"] = mrc.mrc_db_size(db)[0]
     return res
+
+
+def serve_run(mrc, srv, arrival_gaps, docs, mixed=False):
+    """Submit requests at the given arrival gaps (seconds; all zero = everything at
+    once): every request already due goes in one submit_many call (one per kind
+    when mixed: odd requests insert, even ones query), so the host loop keeps up
+    with the schedule (lag_ms = the largest delay of a submission behind its due
+    time). Latency is submit-to-result on the server's clock."""
+    n_req = len(arrival_gaps)
+    sel = [docs[i % len(docs)] for i in range(n_req)]
+    offs = np.zeros(n_req + 1, np.int64)
+    np.cumsum([d.size for d in sel], out=offs[1:])
+    toks = np.concatenate(sel).astype(np.int32)
+    tickets = []
+    lag = 0.0
+    t0 = time.perf_counter()
+    due = t0 + np.cumsum(np.asarray(arrival_gaps, np.float64))
+    i = 0
+    while i < n_req:
+        now = time.perf_counter()
+        if now < due[i]:
+            if due[i] - now > 2e-4:
+                time.sleep((due[i] - now) * 0.5)
+            continue
+        lag = max(lag, now - due[i])
+        j = max(int(np.searchsorted(due, now, side="right")), i + 1)
+        if not mixed:
+            got = mrc.mrc_serve_submit_many(srv, offs[i:j + 1] - offs[i], toks[offs[i]:offs[j]])
+            tickets += [(tk, mrc.REQ_QUERY) for tk in got]
+            tickets += [(None, mrc.REQ_QUERY)] * (j - i - len(got))
+        else:  # odd requests insert, even ones query; one call per kind, the earliest kind first
+            for par in (i % 2, 1 - i % 2):
+                ks = list(range(i + ((par - i) % 2), j, 2))
+                if not ks:
+                    continue
+                kind = mrc.REQ_INSERT if par else mrc.REQ_QUERY
+                o2 = np.zeros(len(ks) + 1, np.int64)
+                np.cumsum([sel[x].size for x in ks], out=o2[1:])
+                got = mrc.mrc_serve_submit_many(srv, o2, np.concatenate([sel[x] for x in ks]), kind)
+                tickets += [(tk, kind) for tk in got]
+                tickets += [(None, kind)] * (len(ks) - len(got))
+        i = j
+    res = [(mrc.mrc_serve_poll(srv, tk, wait_ms=120000), kind) for tk, kind in tickets if tk is not None]
+    wall = time.perf_counter() - t0
+    ok = [(r, kind) for r, kind in res if r is not None and r.status == 0]
+    lat = [r.t_done_ms - r.t_submit_ms for r, _ in ok]
+    latq = [r.t_done_ms - r.t_submit_ms for r, kind in ok if kind == mrc.REQ_QUERY]
+    first = min(r.t_submit_ms for r, _ in res)
+    last = max(r.t_done_ms for r, _ in res)
+    out = {"offered": n_req, "admitted": len(res), "completed": len(lat),
+           "p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
+           "docs_per_s": len(lat) / ((last - first) / 1e3), "wall_s": wall, "lag_ms": lag * 1e3}
+    if mixed:
+        out["query_p50_ms"] = percentile_ms(latq, 50)
+        out["query_p99_ms"] = percentile_ms(latq, 99)
+    return out
 
 
 def percentile_ms(x, q):
@@ -741,60 +930,7 @@ def serving(a, mrc, synth, prec):
     state = {"srv": srv}
 
     def run(arrival_gaps, srv=None, docs=docs, mixed=False):
-        """Submit requests at the given arrival gaps (seconds; all zero = everything at
-        once): every request already due goes in one submit_many call (one per kind
-        when mixed: odd requests insert, even ones query), so the host loop keeps up
-        with the schedule (lag_ms = the largest delay of a submission behind its due
-        time). Latency is submit-to-result on the server's clock."""
-        srv = srv if srv is not None else state["srv"]
-        n_req = len(arrival_gaps)
-        sel = [docs[i % len(docs)] for i in range(n_req)]
-        offs = np.zeros(n_req + 1, np.int64)
-        np.cumsum([d.size for d in sel], out=offs[1:])
-        toks = np.concatenate(sel).astype(np.int32)
-        tickets = []
-        lag = 0.0
-        t0 = time.perf_counter()
-        due = t0 + np.cumsum(np.asarray(arrival_gaps, np.float64))
-        i = 0
-        while i < n_req:
-            now = time.perf_counter()
-            if now < due[i]:
-                if due[i] - now > 2e-4:
-                    time.sleep((due[i] - now) * 0.5)
-                continue
-            lag = max(lag, now - due[i])
-            j = max(int(np.searchsorted(due, now, side="right")), i + 1)
-            if not mixed:
-                got = mrc.mrc_serve_submit_many(srv, offs[i:j + 1] - offs[i], toks[offs[i]:offs[j]])
-                tickets += [(tk, mrc.REQ_QUERY) for tk in got]
-                tickets += [(None, mrc.REQ_QUERY)] * (j - i - len(got))
-            else:  # odd requests insert, even ones query; one call per kind, the earliest kind first
-                for par in (i % 2, 1 - i % 2):
-                    ks = list(range(i + ((par - i) % 2), j, 2))
-                    if not ks:
-                        continue
-                    kind = mrc.REQ_INSERT if par else mrc.REQ_QUERY
-                    o2 = np.zeros(len(ks) + 1, np.int64)
-                    np.cumsum([sel[x].size for x in ks], out=o2[1:])
-                    got = mrc.mrc_serve_submit_many(srv, o2, np.concatenate([sel[x] for x in ks]), kind)
-                    tickets += [(tk, kind) for tk in got]
-                    tickets += [(None, kind)] * (len(ks) - len(got))
-            i = j
-        res = [(mrc.mrc_serve_poll(srv, tk, wait_ms=120000), kind) for tk, kind in tickets if tk is not None]
-        wall = time.perf_counter() - t0
-        ok = [(r, kind) for r, kind in res if r is not None and r.status == 0]
-        lat = [r.t_done_ms - r.t_submit_ms for r, _ in ok]
-        latq = [r.t_done_ms - r.t_submit_ms for r, kind in ok if kind == mrc.REQ_QUERY]
-        first = min(r.t_submit_ms for r, _ in res)
-        last = max(r.t_done_ms for r, _ in res)
-        out = {"offered": n_req, "admitted": len(res), "completed": len(lat),
-               "p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
-               "docs_per_s": len(lat) / ((last - first) / 1e3), "wall_s": wall, "lag_ms": lag * 1e3}
-        if mixed:
-            out["query_p50_ms"] = percentile_ms(latq, 50)
-            out["query_p99_ms"] = percentile_ms(latq, 99)
-        return out
+        return serve_run(mrc, srv if srv is not None else state["srv"], arrival_gaps, docs, mixed)
 
     sat = run([0.0] * 32768)
     sat_rate = sat["docs_per_s"]
