@@ -81,6 +81,7 @@ struct PassArgs {
     const TermInfo* tinfo;
     const double* rinv;
     int k;
+    int vocab;         // entries of tinfo
     int ref_idf;       // 1: rho_t = idf_t, so c_t = idf^2
     float* sig;
     float* norm;
@@ -549,122 +550,175 @@ __device__ __forceinline__ unsigned long long fixed32_ge1(float c) {
     return (unsigned long long)((b & 0x7FFFFFu) | 0x800000u) << ((b >> 23) - 127u + 9u);
 }
 
-// Entries per lane and pass of k_sign_counts (512 per wavefront pass: one
-// pass covers most documents).
+// Entries per lane and chunk of k_sign_counts (a list is signed 512 entries
+// at a time).
 constexpr int kSignPer = 8;
+constexpr int kSignChunk = 64 * kSignPer;
 
+// One chunk of a document's count list as this lane holds it (entry
+// 64 r + lane of the chunk) and the term information gathered for it.
+struct SignStage {
+    int t[kSignPer];
+    int f[kSignPer];
+    TermInfo ti[kSignPer];
+    int i;     // document index in the block (>= cnt: none)
+    int m;     // entries in this chunk
+    int last;  // the document's last chunk
+};
+
+// Each wavefront signs a contiguous block of documents (their offsets and
+// list lengths held one per lane, 64 at a time), chunk by chunk (512 list
+// entries), through a three-stage software pipeline: while chunk j is summed,
+// the term information of chunk j + 1 is being gathered and the entries of
+// chunk j + 2 are being loaded. The three stage buffers rotate by unrolling
+// (no register copies, which would wait for every load in flight); the loads
+// are buffer loads with a wavefront-uniform descriptor per chunk (lanes past
+// its entries read 0: term 0 with count 0), so no address registers are
+// formed per chunk and the waits the compiler places stay exact. Exact sums
+// as in every signing pass: per chunk, |w_d|^2 as three 64-bit partial sums
+// (at most 512 entries: each stays below 2^59) reduced over the wavefront
+// and added to the document's 128-bit total; the part sums in 64-bit fixed
+// point in LDS.
 __global__ __launch_bounds__(256) void k_sign_counts(const int64_t* __restrict__ off, int64_t n,
                                                      const int32_t* __restrict__ term,
                                                      const int32_t* __restrict__ tfv,
-                                                     const int32_t* __restrict__ nnz, PassArgs a,
+                                                     const int32_t* __restrict__ nnz, PassArgs a, int64_t per_wave,
                                                      const unsigned long long* __restrict__ err) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int R = kSignPer;
     const int kpad = (a.k + 1) & ~1;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const uint32_t lane4 = 4u * (uint32_t)lane;
     unsigned long long* bins = (unsigned long long*)smem + (size_t)wave * kpad;
     double* rinv = (double*)smem + (size_t)4 * kpad;  // 1 / |r_j|, staged once per workgroup
     if (pass_disabled(err)) return;
     for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
     for (int j = threadIdx.x; j < a.k; j += 256) rinv[j] = a.rinv[j];
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    const int64_t d0 = (int64_t)blockIdx.x * 4 + wave;
-    if (d0 >= n) return;
-    // Entries e0 .. e0 + 64 R - 1 of a document's count list, lane-interleaved
-    // (lanes past the end read the last entry, so the loads need no branches;
-    // which entries are real is decided where they are used).
-    const int64_t last = max(off[n] - 1, (int64_t)0);  // the lists hold max(T, 1) entries
-    auto load_chunk = [&](int64_t o, int m, int e0, int (&t)[R], int (&f)[R]) {
+    const int64_t first = ((int64_t)blockIdx.x * 4 + wave) * per_wave;
+    const int64_t end = min(first + per_wave, n);
+    // term table (ids < 2^24: byte offsets fit 32 bits)
+    const __amdgpu_buffer_rsrc_t tbl =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.tinfo, (short)0, (int)(8 * a.vocab), 0x00020000);
+
+    for (int64_t base = first; base < end; base += 64) {
+        const int cnt = (int)min((int64_t)64, end - base);
+        // this block's list offsets and lengths, one document per lane
+        const int64_t dl = base + min(lane, cnt - 1);
+        const int64_t o_l = off[dl];
+        const int m_l = lane < cnt ? nnz[dl] : 0;
+        auto o_at = [&](int i) {
+            const int ii = min(i, cnt - 1);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)o_l, ii);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)o_l >> 32), ii);
+            return (int64_t)(((uint64_t)hi << 32) | lo);
+        };
+        auto m_at = [&](int i) { return i < cnt ? __builtin_amdgcn_readlane(m_l, min(i, 63)) : 0; };
+        // issue the loads of chunk c of document i (i >= cnt: nothing to load)
+        auto load_chunk = [&](SignStage& b, int i, int c) {
+            const int m = m_at(i);
+            const int mc = i < cnt ? min(kSignChunk, m - kSignChunk * c) : 0;
+            b.i = i;
+            b.m = mc;
+            b.last = kSignChunk * (c + 1) >= m;
+            const int64_t o = (i < cnt ? o_at(i) : 0) + (int64_t)kSignChunk * c;
+            const __amdgpu_buffer_rsrc_t rt =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(term + o), (short)0, 4 * mc, 0x00020000);
+            const __amdgpu_buffer_rsrc_t rf =
+                __builtin_amdgcn_make_buffer_rsrc((void*)(tfv + o), (short)0, 4 * mc, 0x00020000);
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int64_t p = min(max(o + min(e0 + r * 64 + lane, m - 1), (int64_t)0), last);
-            t[r] = term[p];
-            f[r] = tfv[p];
-        }
-    };
-    auto gather = [&](const int (&t)[R], int m, int e0, TermInfo (&ti)[R]) {
+            for (int r = 0; r < R; ++r) {
+                b.t[r] = (int)__builtin_amdgcn_raw_buffer_load_b32(rt, (int)(lane4 + 256 * r), 0, 0);
+                b.f[r] = (int)__builtin_amdgcn_raw_buffer_load_b32(rf, (int)(lane4 + 256 * r), 0, 0);
+            }
+        };
+        auto gather = [&](SignStage& b) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) ti[r] = a.tinfo[e0 + r * 64 + lane < m ? t[r] : 0];
-    };
-    // (without a document that far ahead the loads re-read the last one: no
-    // branches, so every wait below is exact)
-    auto doc_at = [&](int64_t dd, int64_t& o, int& m) {
-        const int64_t dl = min(dd, n - 1);
-        o = off[dl];
-        m = dd < n ? nnz[dl] : 0;
-    };
-    // Software pipeline over this wavefront's documents d, d + stride, ...:
-    // iteration d holds d's tf and term info, d+1's list entries (loaded one
-    // iteration ago) and issues d+1's term-info gathers and d+2's list loads
-    // before it waits for anything, so both latencies overlap a document's sums,
-    // reduction and write.
-    int f_c[R], t_n[R], f_n[R], t_nn[R], f_nn[R];
-    TermInfo ti_c[R], ti_n[R];
-    int64_t o_c, o_n, o_nn;
-    int m_c, m_n, m_nn;
-    doc_at(d0, o_c, m_c);
-    doc_at(d0 + stride, o_n, m_n);
-    {
-        int t_c[R];
-        load_chunk(o_c, max(m_c, 1), 0, t_c, f_c);
-        load_chunk(o_n, max(m_n, 1), 0, t_n, f_n);
-        gather(t_c, m_c, 0, ti_c);
-    }
-    for (int64_t d = d0; d < n; d += stride) {
-        doc_at(d + 2 * stride, o_nn, m_nn);
-        gather(t_n, m_n, 0, ti_n);
-        load_chunk(o_nn, max(m_nn, 1), 0, t_nn, f_nn);
-        __builtin_amdgcn_sched_barrier(0);  // the requests above go out before any wait
-        // |w_d|^2 exactly: (tf idf)^2 = A^2 2^-46 with the integer
-        // A = tf (mantissa(idf) << exponent(idf)) < 2^50, split at bit 25
-        // into three partial products (< 2^51 each; a pass adds at most R)
-        u128 nacc = 0;
-        auto sums = [&](const int (&f_r)[R], const TermInfo (&ti_r)[R], int e0) {
+            for (int r = 0; r < R; ++r) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b64(tbl, (int)(8u * (uint32_t)b.t[r]), 0, 0);
+                b.ti[r].idf = __uint_as_float(v[0]);
+                b.ti[r].part = (int)v[1];
+            }
+        };
+        // the chunk after (i, c)
+        auto next = [&](int& i, int& c) {
+            if (kSignChunk * (c + 1) < m_at(i)) {
+                ++c;
+            } else {
+                ++i;
+                c = 0;
+            }
+        };
+        u128 total = 0;  // |w_d|^2 2^46 of the current document so far
+        auto sum_chunk = [&](const SignStage& b) {
+            // (tf idf)^2 = A^2 2^-46 with A = tf (mantissa(idf) << exponent(idf)) < 2^50, split at
+            // bit 25 into three partial products below 2^50
             uint64_t s2 = 0, s1 = 0, s0 = 0;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (e0 + r * 64 >= m_c) break;  // (wavefront-uniform) no entries left
-                const bool ok = e0 + r * 64 + lane < m_c;
-                const uint32_t f = ok ? (uint32_t)f_r[r] : 0u;
-                const uint64_t A = (uint64_t)f * idf_scaled(ti_r[r].idf);
+                const uint32_t f = (uint32_t)b.f[r];  // 0 past the chunk's entries
+                const uint64_t A = (uint64_t)f * idf_scaled(b.ti[r].idf);
                 const uint32_t hi = (uint32_t)(A >> 25), lo = (uint32_t)A & 0x1FFFFFFu;
                 s2 += (uint64_t)hi * hi;
                 s1 += (uint64_t)hi * lo;
                 s0 += (uint64_t)lo * lo;
-                if (ok && ti_r[r].part >= 0)
-                    atomicAdd(&bins[ti_r[r].part], (unsigned long long)f * fixed32_ge1(ref_coef(a, ti_r[r].idf)));
+                if (r * 64 + lane < b.m && b.ti[r].part >= 0)
+                    atomicAdd(&bins[b.ti[r].part], (unsigned long long)f * fixed32_ge1(ref_coef(a, b.ti[r].idf)));
             }
-            nacc += ((u128)s2 << 50) + ((u128)s1 << 26) + (u128)s0;
-        };
-        sums(f_c, ti_c, 0);
-        for (int e0 = 64 * R; e0 < m_c; e0 += 64 * R) {  // longer lists (rare): the rest, synchronously
-            int t_x[R], f_x[R];
-            TermInfo ti_x[R];
-            load_chunk(o_c, m_c, e0, t_x, f_x);
-            gather(t_x, m_c, e0, ti_x);
-            sums(f_x, ti_x, e0);
-        }
-        const double nrm = norm_from_fixed(wave_sum_u128(nacc));
-        // one wavefront owns `bins`, and LDS executes its operations in order:
-        // compiler-only fences (and no global loads here) keep the requests of
-        // the next documents in flight
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        float* out = a.sig + d * a.k;
-        for (int j = lane; j < a.k; j += 64)
-            out[j] = (float)(nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * rinv[j] / nrm : 0.0);
-        if (lane == 0 && a.norm) a.norm[d] = (float)nrm;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        // rotate the pipeline
-        o_c = o_n, m_c = m_n, o_n = o_nn, m_n = m_nn;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            f_c[r] = f_n[r];
-            ti_c[r] = ti_n[r];
-            t_n[r] = t_nn[r];
-            f_n[r] = f_nn[r];
+            for (int sh = 32; sh >= 1; sh >>= 1) {
+                s2 += __shfl_xor((unsigned long long)s2, sh, 64);
+                s1 += __shfl_xor((unsigned long long)s1, sh, 64);
+                s0 += __shfl_xor((unsigned long long)s0, sh, 64);
+            }
+            total += ((u128)s2 << 50) + ((u128)s1 << 26) + (u128)s0;
+            if (!b.last) return;
+            const int64_t d = base + b.i;
+            const double nrm = norm_from_fixed(total);
+            total = 0;
+            // one wavefront owns `bins`, and LDS executes its operations in
+            // order: compiler-only fences keep the next chunks' loads in flight
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            float* out = a.sig + d * a.k;
+            for (int j = lane; j < a.k; j += 64)
+                out[j] = (float)(nrm > 0.0 ? mrc_dev::unfixed32(bins[j]) * rinv[j] / nrm : 0.0);
+            if (lane == 0 && a.norm) a.norm[d] = (float)nrm;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            for (int j = lane; j < kpad; j += 64) bins[j] = 0ull;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        };
+
+        // the block's metadata is read here, before any list load is issued,
+        // so no wait inside the loop is for it
+        int i1 = 0, c1 = 0;
+        next(i1, c1);
+        int i2 = i1, c2 = c1;
+        next(i2, c2);
+        __builtin_amdgcn_sched_barrier(0);
+        SignStage b0, b1, b2;
+        load_chunk(b0, 0, 0);
+        load_chunk(b1, i1, c1);
+        gather(b0);
+        // (i2, c2): the chunk whose loads are issued next
+        while (true) {
+            load_chunk(b2, i2, c2);
+            next(i2, c2);
+            gather(b1);
+            __builtin_amdgcn_sched_barrier(0);  // the requests above go out before any wait
+            sum_chunk(b0);
+            if (b1.i >= cnt) break;
+            load_chunk(b0, i2, c2);
+            next(i2, c2);
+            gather(b2);
+            __builtin_amdgcn_sched_barrier(0);
+            sum_chunk(b1);
+            if (b2.i >= cnt) break;
+            load_chunk(b1, i2, c2);
+            next(i2, c2);
+            gather(b0);
+            __builtin_amdgcn_sched_barrier(0);
+            sum_chunk(b2);
+            if (b0.i >= cnt) break;
         }
     }
 }
@@ -827,16 +881,18 @@ mrc_status launch_sign_counts(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* 
     a.tinfo = m->d_tinfo;
     a.rinv = m->d_rinv;
     a.k = m->k;
+    a.vocab = m->vocab;
     a.ref_idf = m->spec.ref_weight == MRC_REF_IDF ? 1 : 0;
     a.sig = sig_out;
     a.norm = norm_out;
     const size_t lds = (size_t)5 * (size_t)((m->k + 1) & ~1) * 8;  // 4 wavefronts' bins + rinv
     ScopedTimer tm(ctx, "sign_counts", s);
-    // persistent: every wavefront walks its documents with the next one's
-    // loads in flight
+    // persistent: every wavefront signs a contiguous block of documents with
+    // the next two documents' loads in flight
     const int64_t grid = persistent_grid(ctx, (const void*)k_sign_counts, 256, ceil_div(n, 4));
+    const int64_t per_wave = ceil_div(n, grid * 4);
     hipLaunchKernelGGL(k_sign_counts, dim3((unsigned)grid), dim3(256), lds, s, docs->offsets, n, c.term, c.tf,
-                       c.nnz, a, (const unsigned long long*)ctx->d_flags);
+                       c.nnz, a, per_wave, (const unsigned long long*)ctx->d_flags);
     MRC_HIP_TRY(ctx, hipGetLastError());
     return MRC_OK;
 }
