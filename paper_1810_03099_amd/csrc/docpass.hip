@@ -424,6 +424,80 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
     }
 }
 
+// Long documents over a small vocabulary (V <= kDirectMaxV, e.g. the 27^3
+// character-3-gram space): one 1024-thread workgroup per document with a
+// direct [V] count array in LDS (no hashing, no global atomics). The tokens
+// are counted with LDS atomics (SIGN: the part sums per occurrence, as in
+// every pass); then one scan of the array visits each distinct term once
+// (its count, its norm term, its list entry), clearing it for the next
+// document.
+constexpr int kDirectThreads = 1024;
+constexpr int kDirectMaxV = 32768;  // 128 KB of counts
+
+template <int MODE>
+__global__ __launch_bounds__(kDirectThreads) void k_doc_direct(const int64_t* __restrict__ off, int32_t V,
+                                                               const int32_t* __restrict__ tok, PassArgs a,
+                                                               unsigned long long* __restrict__ err,
+                                                               const int32_t* __restrict__ list,
+                                                               const unsigned long long* __restrict__ count) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint32_t* cnt = (uint32_t*)smem;                                          // [V]
+    unsigned long long* bins = (unsigned long long*)(smem + (((size_t)V * 4 + 15) & ~(size_t)15));
+    const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
+    u128* red = (u128*)(bins + kpad);                                         // [16]
+    int* tcount = (int*)(red + kDirectThreads / 64);
+    const int tid = threadIdx.x;
+    if (pass_disabled(err)) return;
+    for (int t = tid; t < V; t += kDirectThreads) cnt[t] = 0u;
+    for (int j = tid; j < kpad; j += kDirectThreads) bins[j] = 0ull;
+    __syncthreads();
+    const int64_t n_items = (int64_t)__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+        const int64_t d = list[item];
+        const int64_t o = off[d];
+        const int64_t L = off[d + 1] - o;
+        for (int64_t p = tid; p < L; p += kDirectThreads) {
+            const int t = tok[o + p];
+            if ((unsigned)t >= (unsigned)V) {
+                atomicOr(err, kErrToken);
+                continue;
+            }
+            atomicAdd(&cnt[t], 1u);
+            if constexpr (MODE == MODE_SIGN) {
+                const TermInfo ti = a.tinfo[t];
+                if (ti.part >= 0) atomicAdd(&bins[ti.part], mrc_dev::fixed32(ref_coef(a, ti.idf)));
+            }
+        }
+        if (tid == 0) *tcount = 0;
+        __syncthreads();
+        double nrm = 0.0;
+        if constexpr (MODE != MODE_COUNT) {
+            u128 acc = 0;
+            for (int t = tid; t < V; t += kDirectThreads) {
+                const uint32_t c = cnt[t];
+                if (c) acc += term_sq_fixed(c, a.tinfo[t].idf);
+            }
+            nrm = norm_from_fixed(team_sum<kDirectThreads>(acc, red));
+        }
+        if constexpr (MODE == MODE_SIGN) write_signature(a, d, bins, nrm, tid, kDirectThreads);
+        for (int t = tid; t < V; t += kDirectThreads) {
+            const uint32_t c = cnt[t];
+            if (c == 0u) continue;
+            if constexpr (MODE == MODE_COUNT) emit_term<MODE_COUNT>(a, d, o, t, c, 0.0, atomicAdd(tcount, 1), nullptr);
+            else if constexpr (MODE == MODE_CSR) emit_term<MODE_CSR>(a, d, o, t, c, nrm, 0, tcount);
+            cnt[t] = 0u;
+        }
+        __syncthreads();
+        if constexpr (MODE == MODE_COUNT) {
+            if (tid == 0) a.cnt_nnz[d] = *tcount;
+        } else if constexpr (MODE == MODE_CSR) {
+            if (tid == 0) a.nnz_tail[d] = *tcount;
+        }
+        for (int j = tid; j < kpad; j += kDirectThreads) bins[j] = 0ull;
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------------ df from counts
 
 // One workgroup per (vocabulary slice, document range): the distinct terms of
@@ -780,7 +854,14 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const Pass
                            count(2));
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
-    {
+    if (V <= kDirectMaxV) {
+        // small vocabulary: counts directly in LDS, one workgroup per long document
+        const size_t lds = (((size_t)V * 4 + 15) & ~(size_t)15) + (size_t)kpad * 8 +
+                           (kDirectThreads / 64) * sizeof(u128) + 16;
+        hipLaunchKernelGGL((k_doc_direct<MODE>), dim3(256), dim3(kDirectThreads), lds, s, docs->offsets, V,
+                           docs->tokens, a, err, list(3), count(3));
+        MRC_HIP_TRY(ctx, hipGetLastError());
+    } else {
         const size_t table_bytes = (size_t)kLongBlocks * (size_t)V * sizeof(uint32_t);
         auto it = ctx->scratch.find("long_tables");
         const bool fresh = it == ctx->scratch.end() || it->second.second < table_bytes;

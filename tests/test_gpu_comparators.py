@@ -108,17 +108,34 @@ def test_exact_cosine_matches_oracle(lib, ctx, cfg, n_docs, tau):
     flush(f"  exact cosine n={c.n_docs} tau={tau}: {gi.size} pairs, {len(diff)} near-tie differences")
 
 
-def test_exact_cosine_edge_documents(lib, ctx):
+@pytest.mark.parametrize("V", [3000, 40000])
+def test_exact_cosine_edge_documents(lib, ctx, V):
+    """Duplicates, permutations, empty and one-token documents, and documents
+    above 8,192 tokens (a direct LDS count array for V <= 32,768, global tables
+    above); the whole flagged set against the oracle at a lower threshold."""
     rng = np.random.default_rng(8)
-    V = 3000
     base = rng.integers(0, V, 300)
+    long_doc = rng.integers(0, V, 9000)
     docs = [np.zeros(0, np.int32), base, base.copy(), rng.permutation(base), np.array([5]), np.array([5]),
-            rng.integers(0, V, 6000), rng.integers(0, V, 50)]
+            rng.integers(0, V, 6000), rng.integers(0, V, 50), long_doc, rng.permutation(long_doc),
+            np.concatenate([long_doc, rng.integers(0, V, 3000)])]
     c = synth.from_docs(docs, V)
     o, t = device_docs(c)
     gm = lib.mrc_build_vocab_idf(ctx, o, t, V, lib.ref_spec(4))
     got = lib.mrc_exact_cosine(ctx, gm, o, t, 0.999)
     gi, gj, gs, _ = lib.pairs_to_numpy(got)
     pairs = set(zip(gi.tolist(), gj.tolist()))
-    assert {(1, 2), (1, 3), (2, 3), (4, 5)} <= pairs
+    assert {(1, 2), (1, 3), (2, 3), (4, 5), (8, 9)} <= pairs
     assert not any(0 in p for p in pairs)            # empty document pairs with nothing
+    # every pair at tau = 0.2 (the long documents with each other and the rest) against the oracle
+    omodel = om.build_model(c.offsets, c.tokens, V, om.RefSpec(k=4))
+    got = lib.mrc_exact_cosine(ctx, gm, o, t, 0.2)
+    gi, gj, gs, _ = lib.pairs_to_numpy(got)
+    oi, oj, _ = oc.exact_cosine_pairs(c.offsets, c.tokens, omodel, 0.2)
+    assert set(zip(gi.tolist(), gj.tolist())) == set(zip(oi.tolist(), oj.tolist()))
+    # FP32 accumulation over the terms a pair shares: |error| <= ~2 n u (u = 2^-24) for n shared
+    # terms (the long documents share thousands), plus the 1e-5 budget of short documents
+    terms = [set(np.asarray(d).tolist()) for d in docs]
+    shared = np.array([len(terms[i] & terms[j]) for i, j in zip(gi.tolist(), gj.tolist())])
+    s64 = oc.exact_cosine_scores(c.offsets, c.tokens, omodel, gi, gj)
+    assert np.all(np.abs(gs - s64) <= 1e-5 + 2.0 * shared * 2.0 ** -24)

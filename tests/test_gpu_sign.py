@@ -98,13 +98,14 @@ def test_reference_modes(lib, ctx, mode, kw):
     assert np.abs(sig - osig).max() <= SIG_TOL
 
 
-def test_edge_documents(lib, ctx):
+@pytest.mark.parametrize("V", [4096, 65536])
+def test_edge_documents(lib, ctx, V):
     """Empty documents, one-token documents, the largest id, documents on both
     sides of every length-class boundary (LDS wavefront up to 512 tokens; LDS
     workgroup tables of 4096, 8192 and 16384 slots up to 2048, 4096 and 8192;
-    global tables beyond), 50,000 repeats of one id."""
+    beyond: a direct LDS count array when V <= 32768, global tables above),
+    50,000 repeats of one id."""
     rng = np.random.default_rng(4)
-    V = 4096
     docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
     for L in (1, 63, 64, 65, 511, 512, 513, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 9999, 10001, 30000):
         docs.append(rng.zipf(1.3, L).astype(np.int64) % V)
@@ -119,9 +120,8 @@ def test_edge_documents(lib, ctx):
     assert np.all(sig[0] == 0) and norm[0] == 0
 
 
-def _edge_corpus():
+def _edge_corpus(V=4096):
     rng = np.random.default_rng(4)
-    V = 4096
     docs = [np.zeros(0, np.int32), np.array([V - 1], np.int32), np.array([0], np.int32)]
     for L in (1, 63, 64, 65, 511, 512, 513, 2047, 2048, 2049, 4095, 4096, 4097, 8191, 8192, 8193, 9999, 10001, 30000):
         docs.append(rng.zipf(1.3, L).astype(np.int64) % V)
@@ -130,12 +130,12 @@ def _edge_corpus():
     return synth.from_docs(docs, V)
 
 
-@pytest.mark.parametrize("which", ["small", "full3000", "edge"])
+@pytest.mark.parametrize("which", ["small", "full3000", "edge", "edge_bigv"])
 def test_build_and_sign_equals_build_then_sign(lib, ctx, which):
     """The fused call signs the model corpus from the build's count lists; it
     must give the same model and the same signature and norm bits."""
-    if which == "edge":
-        c, k, mode = _edge_corpus(), 8, om.SEL_ALL
+    if which.startswith("edge"):
+        c, k, mode = _edge_corpus(4096 if which == "edge" else 65536), 8, om.SEL_ALL
     else:
         c = synth.generate(0) if which == "small" else synth.generate(1, n_docs=3000)
         k, mode = (16, om.SEL_DROP_TOP) if which == "small" else (64, om.SEL_DROP_TOP)
