@@ -798,7 +798,12 @@ def serving_fp8(mrc, synth, ctx, run, tau):
            "stream": "alternating insert / query, lengths lognormal median 400, sigma 1.2, 20-50,000 tokens, 20% "
                      "of the documents near duplicates of database documents"}
     rng = np.random.default_rng(43)
-    for pname, p in [("fp8", mrc.PREC_FP8), ("fp32", mrc.PREC_FP32)]:
+    # the persistent collection (work items from a device counter, as many
+    # workgroups as are resident) for both precisions; FP8 also on the
+    # grid-strided collection
+    for pname, p, form in [("fp8", mrc.PREC_FP8, mrc.SCAN_PERSISTENT), ("fp32", mrc.PREC_FP32, mrc.SCAN_PERSISTENT),
+                           ("fp8_grid_scan", mrc.PREC_FP8, mrc.SCAN_GRID)]:
+        mrc.mrc_ctx_set_scan(ctx, form)
         srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=p,
                                   max_wait_us=500, hbm_frac=0.8)
         sat = run([0.0] * 4096, srv=srv, docs=docs, mixed=True)
@@ -807,9 +812,11 @@ def serving_fp8(mrc, synth, ctx, run, tau):
                    mixed=True)
         half["offered_docs_per_s"] = lam
         mrc.mrc_serve_stop(srv)
-        res[pname] = {"saturation": sat, "poisson_0.5": half}
+        res[pname] = {"saturation": sat, "poisson_0.5": half,
+                      "collection": "persistent" if form == mrc.SCAN_PERSISTENT else "grid"}
         log(f"FP8-scale serving {pname}: saturation {sat['docs_per_s']:.0f} docs/s; at 0.5 load query p50 "
             f"{half['query_p50_ms']:.2f} ms, p99 {half['query_p99_ms']:.2f} ms")
+    mrc.mrc_ctx_set_scan(ctx, mrc.SCAN_GRID)
     res["database_rows_after"] = mrc.mrc_db_size(db)[0]
     return res
 

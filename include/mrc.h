@@ -158,6 +158,17 @@ mrc_status mrc_ctx_set_timing(mrc_ctx* ctx, int32_t enabled);
 mrc_status mrc_ctx_kernel_time(mrc_ctx* ctx, const char* kernel, double* total_ms,
                                int64_t* launches, int32_t reset);
 
+/* Form of the query collection pass (Section 1: each new document against
+ * the whole signature database) used by mrc_query and by servers started on
+ * this context afterwards. MRC_SCAN_GRID (default): each workgroup strides
+ * over the database tiles of one query block. MRC_SCAN_PERSISTENT: as many
+ * workgroups as are resident at once take (query block, 16-tile range) items
+ * in order from a device work counter until none is left. Both give the same
+ * results. Errors: MRC_E_INVAL for another form. */
+#define MRC_SCAN_GRID 0
+#define MRC_SCAN_PERSISTENT 1
+mrc_status mrc_ctx_set_scan(mrc_ctx* ctx, int32_t form);
+
 /* Thread-local message of the last failed call on this thread. */
 const char* mrc_last_error(void);
 

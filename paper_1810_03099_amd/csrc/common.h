@@ -62,6 +62,7 @@ struct mrc_ctx {
     std::vector<hipEvent_t> event_pool;
     std::mutex mu;               // guards `used` (databases may be touched by server threads)
     int tile_order_nb = -1;      // the band table in scratch "tile_order" is for this many tile rows
+    int scan_form = 0;           // MRC_SCAN_GRID or MRC_SCAN_PERSISTENT (query collection)
     void* model_spare = nullptr; // table block of the last destroyed model, kept for the next build
     size_t model_spare_bytes = 0;
     // Models and databases hold their context: destroyed while any of them

@@ -113,7 +113,15 @@ struct ScanArgs {
     int64_t* cand;            // [nq][cap] packed (id << 32 | float bits)
     int32_t* ccount;          // [nq]
     int cap;
+    // persistent collection: items (query block, kPersistTiles tiles) taken in
+    // order from a zeroed device counter
+    unsigned long long* work;
+    int64_t n_items;          // query blocks x tile ranges
+    int64_t tile_ranges;      // tile ranges per query block
 };
+
+// Tiles per work item of the persistent collection.
+constexpr int kPersistTiles = 16;
 
 enum { MODE_TOP = 0, MODE_COLLECT = 1 };
 
@@ -121,10 +129,11 @@ enum { MODE_TOP = 0, MODE_COLLECT = 1 };
 // wavefronts take turns over the share's 64-row tiles, and each wavefront
 // holds the G query groups' fragments, so every database fragment it loads
 // feeds G products (G > 1: collection only, where a lane keeps no lists).
-template <int PREC, int NK, int MODE, int G>
+template <int PREC, int NK, int MODE, int G, bool PERS = false>
 __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     using T = QT<PREC>;
     static_assert(MODE == MODE_COLLECT || G == 1, "top lists for one query group per wavefront");
+    static_assert(!PERS || MODE == MODE_COLLECT, "the persistent form collects");
     __shared__ float ls[256][kTop];    // 16 lists per query: 4 wavefronts x 4 lane groups
     __shared__ int lid[256][kTop];
     const int lane = threadIdx.x & 63;
@@ -136,16 +145,21 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     int q[G];
     bool qvalid[G];
     float qsc[G], thr[G];
+    // the query fragments of block y (PERS: the block of the current item)
+    auto load_queries = [&](int64_t y) {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        q[g] = (blockIdx.y * G + g) * 16 + li;
-        qvalid[g] = q[g] < a.nq;
-        const uint8_t* pq = a.q + (int64_t)q[g] * a.ld_q + lg * T::kLaneBytes;
+        for (int g = 0; g < G; ++g) {
+            q[g] = (int)((y * G + g) * 16 + li);
+            qvalid[g] = q[g] < a.nq;
+            const uint8_t* pq = a.q + (int64_t)q[g] * a.ld_q + lg * T::kLaneBytes;
 #pragma unroll
-        for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
-        qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
-        thr[g] = (MODE == MODE_COLLECT && qvalid[g]) ? a.thr[q[g]] : 0.f;
-    }
+            for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
+            qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
+            thr[g] = (MODE == MODE_COLLECT && qvalid[g]) ? a.thr[q[g]] : 0.f;
+        }
+    };
+    int64_t cur_y = PERS ? -1 : (int64_t)blockIdx.y;
+    if (!PERS) load_queries(cur_y);
     float ts[kTop];
     int tid_[kTop];
 #pragma unroll
@@ -154,8 +168,28 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
         tid_[p] = 0x7fffffff;
     }
     const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
-    const int64_t stride = (int64_t)gridDim.x * 4;
-    for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < n_tiles; t += stride) {
+    // grid form: this wavefront's tiles t0, t0 + stride, ...; persistent form:
+    // each wavefront takes items (query block, kPersistTiles tiles) from the
+    // work counter until it passes the item count (every wavefront ends
+    // there), starting from an empty range so that the first pass takes an
+    // item and loads its query block before any tile is scanned
+    int64_t t = PERS ? 0 : (int64_t)blockIdx.x * 4 + wave, t_end = PERS ? 0 : n_tiles;
+    const int64_t stride = PERS ? 1 : (int64_t)gridDim.x * 4;
+    while (true) {
+        if (PERS && t >= t_end) {
+            unsigned long long it = 0;
+            if (lane == 0) it = atomicAdd(a.work, 1ull);
+            const int64_t item = (int64_t)__shfl(it, 0, 64);
+            if (item >= a.n_items) break;
+            const int64_t y = item / a.tile_ranges, rg = item % a.tile_ranges;
+            if (y != cur_y) {
+                cur_y = y;
+                load_queries(y);
+            }
+            t = rg * kPersistTiles;
+            t_end = min(n_tiles, t + kPersistTiles);
+        }
+        if (!PERS && t >= n_tiles) break;
         const int64_t row0 = t * kTileRows;
         const uint8_t* pa = a.db + (row0 + li) * a.ld_db + lg * T::kLaneBytes;
         f32x4 acc[G][4];
@@ -244,6 +278,7 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
                         }
             }
         }
+        t += stride;
     }
     if (MODE == MODE_COLLECT) return;
     // workgroup merge: 16 lists (4 wavefronts x 4 lane groups) per query
@@ -528,7 +563,7 @@ __global__ void k_max_err(const float* __restrict__ db_max, const float* __restr
 // workgroup barrier per tile (every wavefront walks the same tiles).
 constexpr int kLdsRowMax = 1024;  // bytes per database row this kernel stages
 
-template <int PREC, int NK, int G>
+template <int PREC, int NK, int G, bool PERS = false>
 __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
     using T = QT<PREC>;
     constexpr int ROW = NK * T::kChunkBytes;  // bytes per database row (= a.ld_db)
@@ -537,6 +572,7 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
     constexpr int PER = kTileRows * PIECES / 256;
     static_assert(ROW <= kLdsRowMax && (kTileRows * PIECES) % 256 == 0, "tile staging shape");
     __shared__ __align__(16) uint8_t buf[2][kTileRows * LD];
+    __shared__ int64_t s_item;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
@@ -544,21 +580,51 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
     int q[G];
     bool qvalid[G];
     float qsc[G], thr[G];
+    // the fragments of query block y (rows of the padded query arrays)
+    auto load_queries = [&](int64_t y) {
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-        q[g] = ((blockIdx.y * 4 + wave) * G + g) * 16 + li;  // rows of the padded query arrays
-        qvalid[g] = q[g] < a.nq;
-        const uint8_t* pq = a.q + (int64_t)q[g] * a.ld_q + lg * T::kLaneBytes;
+        for (int g = 0; g < G; ++g) {
+            q[g] = (int)(((y * 4 + wave) * G + g) * 16 + li);
+            qvalid[g] = q[g] < a.nq;
+            const uint8_t* pq = a.q + (int64_t)q[g] * a.ld_q + lg * T::kLaneBytes;
 #pragma unroll
-        for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
-        qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
-        thr[g] = qvalid[g] ? a.thr[q[g]] : 0.f;
-    }
+            for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
+            qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
+            thr[g] = qvalid[g] ? a.thr[q[g]] : 0.f;
+        }
+    };
     const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
     // staging: thread piece j is 16 bytes at (row, column) of the tile
     i32x4 st[PER];
-    int64_t t = blockIdx.x;
-    if (t < n_tiles) {
+    int cur = 0;
+    int64_t cur_y = -1;
+    // grid form: one pass over tiles blockIdx.x, + gridDim.x, ... of query
+    // block blockIdx.y; persistent form: items (query block, kPersistTiles
+    // tiles) taken by the workgroup from the work counter until it passes the
+    // item count (the same value for every wavefront: all leave together)
+    while (true) {
+        int64_t t, t_end, step;
+        if (PERS) {
+            if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(a.work, 1ull);
+            __syncthreads();
+            const int64_t item = s_item;
+            __syncthreads();
+            if (item >= a.n_items) break;
+            const int64_t y = item / a.tile_ranges, rg = item % a.tile_ranges;
+            if (y != cur_y) {
+                cur_y = y;
+                load_queries(y);
+            }
+            t = rg * kPersistTiles;
+            t_end = min(n_tiles, t + kPersistTiles);
+            step = 1;
+        } else {
+            load_queries(blockIdx.y);
+            t = blockIdx.x;
+            t_end = n_tiles;
+            step = gridDim.x;
+        }
+    if (t < t_end) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
@@ -567,14 +633,13 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
-            *(i32x4*)(&buf[0][r * LD + c * 16]) = st[j];
+            *(i32x4*)(&buf[cur][r * LD + c * 16]) = st[j];
         }
     }
     __syncthreads();
-    int cur = 0;
-    for (; t < n_tiles; t += gridDim.x) {
-        const int64_t tn = t + gridDim.x;
-        const bool more = tn < n_tiles;
+    for (; t < t_end; t += step) {
+        const int64_t tn = t + step;
+        const bool more = tn < t_end;
         // the next tile's loads overlap this tile's products (without a next
         // tile: this one again, valid and unused, so that nothing branches
         // around the staged values)
@@ -653,12 +718,22 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
         __syncthreads();
         cur ^= 1;
     }
+        if (!PERS) break;
+    }
 }
 
+// pers: the persistent form (grid = the workgroups resident at once, at most
+// a.n_items), else `grid`
 template <int PREC, int G, int NK>
-bool launch_collect_lds_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
+bool launch_collect_lds_nk(mrc_ctx* ctx, bool pers, const ScanArgs& a, dim3 grid, hipStream_t s) {
     if constexpr (NK * QT<PREC>::kChunkBytes <= kLdsRowMax && G * NK * QT<PREC>::kLaneBytes / 4 <= 128) {
-        hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G>), grid, dim3(256), 0, s, a);
+        if (pers) {
+            const void* kf = (const void*)k_query_collect_lds<PREC, NK, G, true>;
+            const int64_t pg = persistent_grid(ctx, kf, 256, a.n_items);
+            hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G, true>), dim3((unsigned)pg), dim3(256), 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G>), grid, dim3(256), 0, s, a);
+        }
         return true;
     } else {
         return false;
@@ -667,8 +742,8 @@ bool launch_collect_lds_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
 
 // false: no instantiation for this shape (the caller uses k_query_scan)
 template <int PREC, int G>
-bool launch_collect_lds(int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
-#define MRC_Q(c) case c: return launch_collect_lds_nk<PREC, G, c>(a, grid, s);
+bool launch_collect_lds(mrc_ctx* ctx, bool pers, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+#define MRC_Q(c) case c: return launch_collect_lds_nk<PREC, G, c>(ctx, pers, a, grid, s);
     if constexpr (PREC == MRC_PREC_FP32) {
         switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) default: return false; }
     } else if constexpr (PREC == MRC_PREC_BF16) {
@@ -680,9 +755,18 @@ bool launch_collect_lds(int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
 }
 
 // G query groups per wavefront when their fragments fit in 128 registers.
+// pers (collection only): the persistent form, items per wavefront.
 template <int PREC, int MODE, int G, int NK>
-bool launch_scan_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
+bool launch_scan_nk(mrc_ctx* ctx, bool pers, const ScanArgs& a, dim3 grid, hipStream_t s) {
     if constexpr (G == 1 || G * NK * QT<PREC>::kLaneBytes / 4 <= 128) {
+        if constexpr (MODE == MODE_COLLECT) {
+            if (pers) {
+                const void* kf = (const void*)k_query_scan<PREC, NK, MODE, G, true>;
+                const int64_t pg = persistent_grid(ctx, kf, 256, ceil_div(a.n_items, 4));
+                hipLaunchKernelGGL((k_query_scan<PREC, NK, MODE, G, true>), dim3((unsigned)pg), dim3(256), 0, s, a);
+                return true;
+            }
+        }
         hipLaunchKernelGGL((k_query_scan<PREC, NK, MODE, G>), grid, dim3(256), 0, s, a);
         return true;
     } else {
@@ -691,9 +775,9 @@ bool launch_scan_nk(const ScanArgs& a, dim3 grid, hipStream_t s) {
 }
 
 template <int PREC, int MODE, int G>
-mrc_status launch_scan(mrc_ctx* ctx, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+mrc_status launch_scan(mrc_ctx* ctx, int nk, const ScanArgs& a, dim3 grid, hipStream_t s, bool pers = false) {
     bool ok = false;
-#define MRC_Q(c) case c: ok = launch_scan_nk<PREC, MODE, G, c>(a, grid, s); break;
+#define MRC_Q(c) case c: ok = launch_scan_nk<PREC, MODE, G, c>(ctx, pers, a, grid, s); break;
     if constexpr (PREC == MRC_PREC_FP32) {
         switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) MRC_Q(24) MRC_Q(32) default: break; }
     } else if constexpr (PREC == MRC_PREC_BF16) {
@@ -708,11 +792,12 @@ mrc_status launch_scan(mrc_ctx* ctx, int nk, const ScanArgs& a, dim3 grid, hipSt
 }
 
 template <int PREC>
-mrc_status launch_scan_any(mrc_ctx* ctx, int mode, int g, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
+mrc_status launch_scan_any(mrc_ctx* ctx, int mode, int g, int nk, const ScanArgs& a, dim3 grid, hipStream_t s,
+                           bool pers = false) {
     if (mode == MODE_TOP) return launch_scan<PREC, MODE_TOP, 1>(ctx, nk, a, grid, s);
-    if (g == 4) return launch_scan<PREC, MODE_COLLECT, 4>(ctx, nk, a, grid, s);
-    if (g == 2) return launch_scan<PREC, MODE_COLLECT, 2>(ctx, nk, a, grid, s);
-    return launch_scan<PREC, MODE_COLLECT, 1>(ctx, nk, a, grid, s);
+    if (g == 4) return launch_scan<PREC, MODE_COLLECT, 4>(ctx, nk, a, grid, s, pers);
+    if (g == 2) return launch_scan<PREC, MODE_COLLECT, 2>(ctx, nk, a, grid, s, pers);
+    return launch_scan<PREC, MODE_COLLECT, 1>(ctx, nk, a, grid, s, pers);
 }
 
 }  // namespace
@@ -771,10 +856,10 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         lane_regs = bf ? 4 : 8;
     }
     a.ld_q = a.ld_db;
-    auto scan = [&](int mode, int g, dim3 grid) {
-        if (fp32) return launch_scan_any<MRC_PREC_FP32>(ctx, mode, g, nk, a, grid, s);
-        if (bf) return launch_scan_any<MRC_PREC_BF16>(ctx, mode, g, nk, a, grid, s);
-        return launch_scan_any<MRC_PREC_FP8>(ctx, mode, g, nk, a, grid, s);
+    auto scan = [&](int mode, int g, dim3 grid, bool pers = false) {
+        if (fp32) return launch_scan_any<MRC_PREC_FP32>(ctx, mode, g, nk, a, grid, s, pers);
+        if (bf) return launch_scan_any<MRC_PREC_BF16>(ctx, mode, g, nk, a, grid, s, pers);
+        return launch_scan_any<MRC_PREC_FP8>(ctx, mode, g, nk, a, grid, s, pers);
     };
     auto grid_for_rows = [&](int64_t r, int64_t groups) {
         const int64_t tiles = std::max<int64_t>(1, ceil_div(r, kTileRows));
@@ -832,24 +917,34 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         const int64_t groups = ceil_div(nq, 64 * g);
         g2 = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), tiles)), (unsigned)groups);
     }
+    // persistent form: items of kPersistTiles tiles per query block, taken
+    // from a counter in context scratch (cleared by a fill kernel per launch)
+    const bool pers = ctx->scan_form == MRC_SCAN_PERSISTENT;
+    void* work = nullptr;
+    if (pers) MRC_TRY(scratch(ctx, "q_work", 256, &work));
+    a.work = (unsigned long long*)work;
+    a.tile_ranges = ceil_div(std::max<int64_t>(1, ceil_div(rows, kTileRows)), kPersistTiles);
     auto collect = [&]() -> mrc_status {
+        if (pers) MRC_TRY(clear_words(ctx, (int64_t*)work, 1, s));
         if (lds_form) {
+            a.n_items = ceil_div(nq, 64 * g) * a.tile_ranges;
             bool ok;
-            if (fp32) ok = g == 4 ? launch_collect_lds<MRC_PREC_FP32, 4>(nk, a, g2, s)
-                         : g == 2 ? launch_collect_lds<MRC_PREC_FP32, 2>(nk, a, g2, s)
-                                  : launch_collect_lds<MRC_PREC_FP32, 1>(nk, a, g2, s);
-            else if (bf) ok = g == 4 ? launch_collect_lds<MRC_PREC_BF16, 4>(nk, a, g2, s)
-                            : g == 2 ? launch_collect_lds<MRC_PREC_BF16, 2>(nk, a, g2, s)
-                                     : launch_collect_lds<MRC_PREC_BF16, 1>(nk, a, g2, s);
-            else ok = g == 4 ? launch_collect_lds<MRC_PREC_FP8, 4>(nk, a, g2, s)
-                    : g == 2 ? launch_collect_lds<MRC_PREC_FP8, 2>(nk, a, g2, s)
-                             : launch_collect_lds<MRC_PREC_FP8, 1>(nk, a, g2, s);
+            if (fp32) ok = g == 4 ? launch_collect_lds<MRC_PREC_FP32, 4>(ctx, pers, nk, a, g2, s)
+                         : g == 2 ? launch_collect_lds<MRC_PREC_FP32, 2>(ctx, pers, nk, a, g2, s)
+                                  : launch_collect_lds<MRC_PREC_FP32, 1>(ctx, pers, nk, a, g2, s);
+            else if (bf) ok = g == 4 ? launch_collect_lds<MRC_PREC_BF16, 4>(ctx, pers, nk, a, g2, s)
+                            : g == 2 ? launch_collect_lds<MRC_PREC_BF16, 2>(ctx, pers, nk, a, g2, s)
+                                     : launch_collect_lds<MRC_PREC_BF16, 1>(ctx, pers, nk, a, g2, s);
+            else ok = g == 4 ? launch_collect_lds<MRC_PREC_FP8, 4>(ctx, pers, nk, a, g2, s)
+                    : g == 2 ? launch_collect_lds<MRC_PREC_FP8, 2>(ctx, pers, nk, a, g2, s)
+                             : launch_collect_lds<MRC_PREC_FP8, 1>(ctx, pers, nk, a, g2, s);
             if (ok) {
                 MRC_HIP_TRY(ctx, hipGetLastError());
                 return MRC_OK;
             }
         }
-        return scan(MODE_COLLECT, g, grid_for_rows(rows, ceil_div(nq, 16 * g)));
+        a.n_items = ceil_div(nq, 16 * g) * a.tile_ranges;
+        return scan(MODE_COLLECT, g, grid_for_rows(rows, ceil_div(nq, 16 * g)), pers);
     };
     int cap = 2048;
     auto it = ctx->scratch.find("q_cand");

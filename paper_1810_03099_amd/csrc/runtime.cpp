@@ -294,6 +294,13 @@ mrc_status mrc_ctx_set_timing(mrc_ctx* ctx, int32_t enabled) {
     return MRC_OK;
 }
 
+mrc_status mrc_ctx_set_scan(mrc_ctx* ctx, int32_t form) {
+    if (!ctx) return fail(MRC_E_INVAL, "mrc_ctx_set_scan: ctx is NULL");
+    if (form != MRC_SCAN_GRID && form != MRC_SCAN_PERSISTENT) return fail(MRC_E_INVAL, "mrc_ctx_set_scan: bad form");
+    ctx->scan_form = form;
+    return MRC_OK;
+}
+
 mrc_status mrc_ctx_kernel_time(mrc_ctx* ctx, const char* kernel, double* total_ms,
                                int64_t* launches, int32_t reset) {
     if (!ctx || !kernel) return fail(MRC_E_INVAL, "mrc_ctx_kernel_time: NULL argument");

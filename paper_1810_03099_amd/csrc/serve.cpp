@@ -52,6 +52,7 @@ class GpuExecutor : public mrc_serve::Executor {
         slots_.resize(n);
         for (auto& sl : slots_) {
             MRC_TRY(mrc_ctx_create(&sl.ctx, main->device, main->budget));
+            sl.ctx->scan_form = main->scan_form;
             MRC_HIP_TRY(main, hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking));
         }
         return MRC_OK;

@@ -28,11 +28,12 @@ SEL_ALL, SEL_REGION, SEL_RAREST, SEL_DROP_TOP = 0, 1, 2, 3
 IDF_SMOOTH, IDF_NONE = 0, 1
 REF_ONE, REF_IDF = 0, 1
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+SCAN_GRID, SCAN_PERSISTENT = 0, 1
 REQ_QUERY, REQ_INSERT = 0, 1
 
 # names of the exported C functions (checked against include/mrc.h by the tests)
 EXPORTS = (
-    "mrc_ctx_create", "mrc_ctx_destroy", "mrc_ctx_memory", "mrc_ctx_set_timing", "mrc_ctx_kernel_time",
+    "mrc_ctx_create", "mrc_ctx_destroy", "mrc_ctx_memory", "mrc_ctx_set_timing", "mrc_ctx_set_scan", "mrc_ctx_kernel_time",
     "mrc_last_error", "mrc_build_vocab_idf", "mrc_build_and_sign", "mrc_model_destroy", "mrc_model_info", "mrc_model_get",
     "mrc_model_save", "mrc_model_load", "mrc_sign", "mrc_sign_matrix", "mrc_compare", "mrc_compare_f32_noalloc", "mrc_normalise", "mrc_score_pairs",
     "mrc_trigrams", "mrc_simhash", "mrc_term_hashes", "mrc_hamming_pairs", "mrc_exact_cosine", "mrc_db_create",
@@ -102,6 +103,7 @@ _SIGS = {
     "mrc_ctx_destroy": [_P],
     "mrc_ctx_memory": [_P, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)],
     "mrc_ctx_set_timing": [_P, C.c_int32],
+    "mrc_ctx_set_scan": [_P, C.c_int32],
     "mrc_ctx_kernel_time": [_P, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int32],
     "mrc_build_vocab_idf": [_P, C.POINTER(MrcDocs), C.c_int32, C.POINTER(MrcRefSpec), C.POINTER(_P), _P],
     "mrc_build_and_sign": [_P, C.POINTER(MrcDocs), C.c_int32, C.POINTER(MrcRefSpec), C.POINTER(_P), _P, _P, _P],
@@ -256,6 +258,11 @@ def mrc_ctx_memory(ctx):
 
 def mrc_ctx_set_timing(ctx, enabled=True):
     _check(lib().mrc_ctx_set_timing(ctx, 1 if enabled else 0), "mrc_ctx_set_timing")
+
+
+def mrc_ctx_set_scan(ctx, form):
+    """Query collection form: SCAN_GRID (default) or SCAN_PERSISTENT."""
+    _check(lib().mrc_ctx_set_scan(ctx, int(form)), "mrc_ctx_set_scan")
 
 
 def mrc_ctx_kernel_time(ctx, kernel, reset=False):

@@ -75,11 +75,15 @@ def test_query_equals_exact_chain(lib, ctx, setup, prec):
     flush(f"  {prec}: mean hits {hits.mean():.2f}, queries with a hit {int((hits > 0).sum())}")
 
 
+@pytest.mark.parametrize("form", ["grid", "persistent"])
 @pytest.mark.parametrize("nq", [10, 40, 200])
-def test_query_prefix_threshold_exact(lib, ctx, nq):
+def test_query_prefix_threshold_exact(lib, nq, form):
     # 20,000 rows: the first pass sees a 16,384-row prefix, whose 16th best is
     # only a lower bound; batches of 10, 40 and 200 queries run the collection
     # with 1, 2 and 4 query groups per wavefront
+    # (both collection forms: grid-strided and persistent work items)
+    ctx = lib.mrc_ctx_create(0)
+    lib.mrc_ctx_set_scan(ctx, lib.SCAN_PERSISTENT if form == "persistent" else lib.SCAN_GRID)
     dbc = synth.generate(1)
     qc = synth.generate_queries(synth.CONFIGS[1], nq, seed=101 + nq, median=300, sigma=1.2, hi=6000, near_of=dbc,
                                 near_frac=0.4)
@@ -96,13 +100,17 @@ def test_query_prefix_threshold_exact(lib, ctx, nq):
         np.testing.assert_array_equal(ids.cpu().numpy(), wids)
         np.testing.assert_array_equal(sc.cpu().numpy().view(np.uint32), wsc.view(np.uint32))
         np.testing.assert_array_equal(hits.cpu().numpy(), whits)
-    flush(f"  nq={nq}: 20,000 rows, prefix threshold, all forms == exact chain; mean hits {whits.mean():.2f}")
+    flush(f"  nq={nq} {form}: 20,000 rows, prefix threshold, all precisions == exact chain; mean hits "
+          f"{whits.mean():.2f}")
 
 
+@pytest.mark.parametrize("form", ["grid", "persistent"])
 @pytest.mark.parametrize("k", [100, 512])
-def test_query_k_shapes(lib, ctx, k):
+def test_query_k_shapes(lib, k, form):
     # k = 100: partial 16-component blocks in every layout; k = 512: the
     # largest query length (32 FP32 chunks, 16 BF16, 4 FP8)
+    ctx = lib.mrc_ctx_create(0)
+    lib.mrc_ctx_set_scan(ctx, lib.SCAN_PERSISTENT if form == "persistent" else lib.SCAN_GRID)
     dbc = synth.generate(2, n_docs=2500)
     qc = synth.generate_queries(synth.CONFIGS[2], 70, seed=9 + k, median=400, sigma=1.2, hi=6000, near_of=dbc,
                                 near_frac=0.4)
@@ -218,7 +226,8 @@ def test_query_rejects_malformed_input(lib, ctx, setup):
     np.testing.assert_array_equal(hits.cpu().numpy(), whits)
 
 
-def test_query_candidate_capacity_grows(lib):
+@pytest.mark.parametrize("form", ["grid", "persistent"])
+def test_query_candidate_capacity_grows(lib, form):
     """More than 2,048 rows at or above tau for one query: the collection's
     first per-query capacity (2,048 candidates on a fresh context) overflows,
     the call grows it and runs again, and the results still equal the exact
@@ -240,6 +249,7 @@ def test_query_candidate_capacity_grows(lib):
     qc = synth.from_docs([base, docs[700], docs[5]], c0.vocab)
     for prec in (lib.PREC_FP8, lib.PREC_BF16, lib.PREC_FP32):
         fresh = lib.mrc_ctx_create(0)
+        lib.mrc_ctx_set_scan(fresh, lib.SCAN_PERSISTENT if form == "persistent" else lib.SCAN_GRID)
         model = lib.mrc_build_vocab_idf(fresh, *device_docs(c0), c0.vocab, lib.ref_spec(64))
         o, t = device_docs(dbc)
         db = lib.mrc_db_create(fresh, dbc.n_docs, 64)

@@ -42,14 +42,20 @@ def alone(lib, env, doc, prec):
     return ids.cpu().numpy()[0], sc.cpu().numpy()[0], int(hits.cpu().numpy()[0])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16", "fp8"])
-def test_alone_equals_mixed(lib, env, prec):
+@pytest.mark.parametrize("prec,form", [("fp32", "grid"), ("bf16", "grid"), ("fp8", "grid"), ("fp8", "persistent"),
+                                       ("fp32", "persistent")])
+def test_alone_equals_mixed(lib, env, prec, form):
     p = {"fp32": lib.PREC_FP32, "bf16": lib.PREC_BF16, "fp8": lib.PREC_FP8}[prec]
     qc = env["qc"]
     docs = [qc.doc(i) for i in range(qc.n_docs)]
     ref = [alone(lib, env, d, lib.PREC_FP32) for d in docs]
-    srv = lib.mrc_serve_start(env["ctx"], env["db"], env["model"], max_batch=32, n_streams=3, topk=16, tau=TAU,
-                              precision=p, max_wait_us=300)
+    # (servers started after this take the context's collection form)
+    lib.mrc_ctx_set_scan(env["ctx"], lib.SCAN_PERSISTENT if form == "persistent" else lib.SCAN_GRID)
+    try:
+        srv = lib.mrc_serve_start(env["ctx"], env["db"], env["model"], max_batch=32, n_streams=3, topk=16, tau=TAU,
+                                  precision=p, max_wait_us=300)
+    finally:
+        lib.mrc_ctx_set_scan(env["ctx"], lib.SCAN_GRID)
     results = {}
     lock = threading.Lock()
 
@@ -81,7 +87,7 @@ def test_alone_equals_mixed(lib, env, prec):
         np.testing.assert_array_equal(got_s.view(np.uint32), sc[valid].view(np.uint32))
         assert r.n_hits == hits
         lat.append(r.t_done_ms - r.t_submit_ms)
-    flush(f"  {prec}: {len(docs)} queries mixed == alone; latency p50 {np.percentile(lat, 50):.2f} ms "
+    flush(f"  {prec} {form}: {len(docs)} queries mixed == alone; latency p50 {np.percentile(lat, 50):.2f} ms "
           f"p99 {np.percentile(lat, 99):.2f} ms")
 
 
