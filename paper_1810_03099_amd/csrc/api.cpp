@@ -205,14 +205,15 @@ mrc_status build_model(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
 
 }  // namespace
 
-mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
-                               const mrc_ref_spec* spec, mrc_model** out, void* hip_stream) {
+static mrc_status build_vocab_idf_impl(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
+                                       const mrc_ref_spec* spec, mrc_model** out, void* hip_stream) {
     return build_model(ctx, corpus, vocab_size, spec, out, nullptr, nullptr, (hipStream_t)hip_stream,
                        "mrc_build_vocab_idf");
 }
 
-mrc_status mrc_build_and_sign(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size, const mrc_ref_spec* spec,
-                              mrc_model** out, float* sig_out, float* norm_out, void* hip_stream) {
+static mrc_status build_and_sign_impl(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
+                                      const mrc_ref_spec* spec, mrc_model** out, float* sig_out, float* norm_out,
+                                      void* hip_stream) {
     if (corpus && corpus->n_docs > 0 && !sig_out) return fail(MRC_E_INVAL, "mrc_build_and_sign: sig_out is NULL");
     float* sig = sig_out;
     float dummy = 0.f;
@@ -363,8 +364,8 @@ mrc_status mrc_model_load(mrc_ctx* ctx, const char* path, mrc_model** out) {
 
 // ------------------------------------------------------------------ signing
 
-mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float* sig_out,
-                    float* norm_out, void* hip_stream) {
+static mrc_status sign_impl(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float* sig_out,
+                            float* norm_out, void* hip_stream) {
     MRC_TRY(check_ctx(ctx, "mrc_sign"));
     MRC_TRY(check_docs(docs, "mrc_sign"));
     if (!model) return fail(MRC_E_INVAL, "mrc_sign: model is NULL");
@@ -375,8 +376,8 @@ mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, 
     return sync_flags(ctx, s, 1, "mrc_sign");
 }
 
-mrc_status mrc_sign_matrix(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, const float* R, int32_t k,
-                           float* sig_out, float* norm_out, void* hip_stream) {
+static mrc_status sign_matrix_impl(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, const float* R,
+                                   int32_t k, float* sig_out, float* norm_out, void* hip_stream) {
     MRC_TRY(check_ctx(ctx, "mrc_sign_matrix"));
     MRC_TRY(check_docs(docs, "mrc_sign_matrix"));
     if (!model) return fail(MRC_E_INVAL, "mrc_sign_matrix: model is NULL");
@@ -414,9 +415,9 @@ mrc_status mrc_score_pairs(mrc_ctx* ctx, const float* unit, int64_t n, int32_t k
     return MRC_OK;
 }
 
-mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const mrc_compare_opts* opts,
-                       mrc_pair* pairs_out, int64_t capacity, int64_t* n_found, mrc_compare_stats* stats,
-                       void* hip_stream) {
+static mrc_status compare_impl(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const mrc_compare_opts* opts,
+                               mrc_pair* pairs_out, int64_t capacity, int64_t* n_found, mrc_compare_stats* stats,
+                               void* hip_stream) {
     MRC_TRY(check_ctx(ctx, "mrc_compare"));
     if (!opts || !n_found) return fail(MRC_E_INVAL, "mrc_compare: NULL opts or n_found");
     if (n < 0 || n > 0x7FFFFFFFLL || k < 1 || k > 1024) return fail(MRC_E_INVAL, "mrc_compare: bad n or k");
@@ -589,6 +590,74 @@ mrc_status mrc_exact_cosine(mrc_ctx* ctx, const mrc_model* model, const mrc_docs
     *n_found = ctx->h_flags[4];
     if (*n_found > capacity) return fail(MRC_E_OVERFLOW, "mrc_exact_cosine: more pairs than capacity");
     return MRC_OK;
+}
+
+// ------------------------------------------------------------------ logged entry points
+// (each records one line when MRC_LOG >= 1; the work is in the *_impl above)
+
+static void log_docs(CallLog& L, const mrc_docs* d) {
+    L.add("n_docs", d ? d->n_docs : (int64_t)-1);
+    L.add("tokens", d ? d->n_tokens : (int64_t)-1);
+}
+
+mrc_status mrc_build_vocab_idf(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size,
+                               const mrc_ref_spec* spec, mrc_model** out, void* hip_stream) {
+    CallLog L(ctx, "mrc_build_vocab_idf");
+    log_docs(L, corpus);
+    L.add("vocab", (int64_t)vocab_size);
+    L.add("k", (int64_t)(spec ? spec->k : -1));
+    const mrc_status st = build_vocab_idf_impl(ctx, corpus, vocab_size, spec, out, hip_stream);
+    if (st == MRC_OK && out && *out) L.add("n_listed", (*out)->n_listed);
+    return L.done(st);
+}
+
+mrc_status mrc_build_and_sign(mrc_ctx* ctx, const mrc_docs* corpus, int32_t vocab_size, const mrc_ref_spec* spec,
+                              mrc_model** out, float* sig_out, float* norm_out, void* hip_stream) {
+    CallLog L(ctx, "mrc_build_and_sign");
+    log_docs(L, corpus);
+    L.add("vocab", (int64_t)vocab_size);
+    L.add("k", (int64_t)(spec ? spec->k : -1));
+    const mrc_status st = build_and_sign_impl(ctx, corpus, vocab_size, spec, out, sig_out, norm_out, hip_stream);
+    if (st == MRC_OK && out && *out) L.add("n_listed", (*out)->n_listed);
+    return L.done(st);
+}
+
+mrc_status mrc_sign(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, float* sig_out,
+                    float* norm_out, void* hip_stream) {
+    CallLog L(ctx, "mrc_sign");
+    log_docs(L, docs);
+    L.add("k", (int64_t)(model ? model->k : -1));
+    return L.done(sign_impl(ctx, model, docs, sig_out, norm_out, hip_stream));
+}
+
+mrc_status mrc_sign_matrix(mrc_ctx* ctx, const mrc_model* model, const mrc_docs* docs, const float* R, int32_t k,
+                           float* sig_out, float* norm_out, void* hip_stream) {
+    CallLog L(ctx, "mrc_sign_matrix");
+    log_docs(L, docs);
+    L.add("k", (int64_t)k);
+    return L.done(sign_matrix_impl(ctx, model, docs, R, k, sig_out, norm_out, hip_stream));
+}
+
+mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const mrc_compare_opts* opts,
+                       mrc_pair* pairs_out, int64_t capacity, int64_t* n_found, mrc_compare_stats* stats,
+                       void* hip_stream) {
+    CallLog L(ctx, "mrc_compare");
+    L.add("n", n);
+    L.add("k", (int64_t)k);
+    L.add("precision", (int64_t)(opts ? opts->precision : -1));
+    L.add("tau", (double)(opts ? opts->tau : 0.f));
+    mrc_compare_stats local{};
+    const mrc_status st =
+        compare_impl(ctx, sig, n, k, opts, pairs_out, capacity, n_found, stats ? stats : &local, hip_stream);
+    const mrc_compare_stats& cs = stats ? *stats : local;
+    if (st == MRC_OK || st == MRC_E_OVERFLOW) {
+        L.add("flagged", cs.n_flagged);
+        L.add("band_pairs", cs.n_band);
+        L.add("band_pairs_nominal", cs.n_band_nominal);
+        L.add("flips_outside_nominal", cs.n_flip_outside_nominal);
+        L.add("max_abs_err", (double)cs.max_abs_err);
+    }
+    return L.done(st);
 }
 
 }  // extern "C"

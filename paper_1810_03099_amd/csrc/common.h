@@ -140,6 +140,31 @@ void timer_begin(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev_p
 void timer_end(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev_pair);
 void timer_collect(mrc_ctx* ctx);
 
+// Structured log: env MRC_LOG = 0 (off, default) .. 3 and MRC_LOG_FILE (a path,
+// default stderr), read once per process. One JSON object per line, each with
+// "t_ms" (milliseconds since the library's first log line) and "event".
+// Level 1: one line per main entry point call (status, sizes, counts, wall
+// time); 2: also the call's per-kernel device times; 3: also one line per
+// serving batch and the server's totals at stop.
+int log_level();
+void log_line(const std::string& event, const std::string& fields);  // fields: `"k": v, ...` or empty
+
+// The log record of one entry point call (nothing unless MRC_LOG >= 1).
+// Level 2 turns the context's kernel timers on for the call and reports what
+// its kernels took.
+struct CallLog {
+    mrc_ctx* ctx;
+    const char* name;
+    bool on = false, timers = false, timing_was = false;
+    double t0 = 0.0;
+    std::map<std::string, KernelTimer> before;
+    std::string fields;
+    CallLog(mrc_ctx* c, const char* n);
+    void add(const char* key, int64_t v);
+    void add(const char* key, double v);
+    mrc_status done(mrc_status st);  // writes the line; returns st
+};
+
 struct ScopedTimer {
     mrc_ctx* ctx;
     const char* name;

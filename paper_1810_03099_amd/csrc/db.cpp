@@ -137,7 +137,7 @@ mrc_status mrc_db_size(const mrc_db* db, int64_t* n, int32_t* k) {
     return MRC_OK;
 }
 
-mrc_status mrc_db_insert(mrc_db* db, const float* sig, int64_t n, int64_t* first_id, void* hip_stream) {
+static mrc_status db_insert_impl(mrc_db* db, const float* sig, int64_t n, int64_t* first_id, void* hip_stream) {
     if (!db) return fail(MRC_E_INVAL, "mrc_db_insert: db is NULL");
     MRC_TRY(ctx_ready(db->ctx, "mrc_db_insert"));
     if (n < 0 || (n > 0 && !sig)) return fail(MRC_E_INVAL, "mrc_db_insert: bad arguments");
@@ -256,8 +256,8 @@ mrc_status mrc_db_load(mrc_ctx* ctx, const char* path, uint32_t precisions, mrc_
     return MRC_OK;
 }
 
-mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, const mrc_docs* q, int32_t topk, float tau,
-                     int32_t precision, mrc_hit* topk_out, int32_t* n_hits, void* hip_stream) {
+static mrc_status query_impl(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, const mrc_docs* q, int32_t topk,
+                             float tau, int32_t precision, mrc_hit* topk_out, int32_t* n_hits, void* hip_stream) {
     MRC_TRY(ctx_ready(ctx, "mrc_query"));
     if (!db || !model || !q || !q->offsets) return fail(MRC_E_INVAL, "mrc_query: NULL argument");
     if (model->k != db->k) return fail(MRC_E_INVAL, "mrc_query: model and database differ in k");
@@ -274,6 +274,28 @@ mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, con
     if (ctx->h_flags[0] & (kErrOffsets | kErrToken | kErrDocLen))
         return fail(MRC_E_INVAL, "mrc_query: malformed offsets, token ids or document lengths");
     return MRC_OK;
+}
+
+// ------------------------------------------------------------------ logged entry points
+
+mrc_status mrc_db_insert(mrc_db* db, const float* sig, int64_t n, int64_t* first_id, void* hip_stream) {
+    CallLog L(db ? db->ctx : nullptr, "mrc_db_insert");
+    L.add("n", n);
+    const mrc_status st = db_insert_impl(db, sig, n, first_id, hip_stream);
+    if (st == MRC_OK && db) L.add("rows", (int64_t)__atomic_load_n(&db->size, __ATOMIC_ACQUIRE));
+    return L.done(st);
+}
+
+mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, const mrc_docs* q, int32_t topk, float tau,
+                     int32_t precision, mrc_hit* topk_out, int32_t* n_hits, void* hip_stream) {
+    CallLog L(ctx, "mrc_query");
+    L.add("n_queries", q ? q->n_docs : (int64_t)-1);
+    L.add("tokens", q ? q->n_tokens : (int64_t)-1);
+    L.add("rows", db ? (int64_t)__atomic_load_n(&db->size, __ATOMIC_ACQUIRE) : (int64_t)-1);
+    L.add("topk", (int64_t)topk);
+    L.add("precision", (int64_t)precision);
+    L.add("scan", (int64_t)(ctx ? ctx->scan_form : -1));
+    return L.done(query_impl(ctx, db, model, q, topk, tau, precision, topk_out, n_hits, hip_stream));
 }
 
 }  // extern "C"

@@ -1,7 +1,9 @@
 // Host runtime of libmrc: thread-local errors, budgeted device allocation,
 // named scratch buffers, and per-kernel HIP-event timing.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -106,6 +108,99 @@ void timer_end(mrc_ctx* ctx, const char* name, hipStream_t s, hipEvent_t* ev) {
     if (!ctx || !ctx->timing || !ev[0] || !ev[1]) return;
     (void)hipEventRecord(ev[1], s);
     ctx->pending.push_back({name, {ev[0], ev[1]}});
+}
+
+// ------------------------------------------------------------------ logging
+
+namespace {
+std::once_flag g_log_once;
+int g_log_level = 0;
+FILE* g_log_file = nullptr;
+std::mutex g_log_mu;
+std::chrono::steady_clock::time_point g_log_t0;
+
+void log_init() {
+    const char* lv = std::getenv("MRC_LOG");
+    g_log_level = lv ? std::max(0, std::min(3, std::atoi(lv))) : 0;
+    if (g_log_level == 0) return;
+    const char* path = std::getenv("MRC_LOG_FILE");
+    g_log_file = path && *path ? std::fopen(path, "a") : nullptr;
+    if (!g_log_file) g_log_file = stderr;
+    g_log_t0 = std::chrono::steady_clock::now();
+}
+
+double now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - g_log_t0).count();
+}
+
+std::string num(double v) {
+    char b[64];
+    std::snprintf(b, sizeof b, "%.6g", v);
+    return b;
+}
+}  // namespace
+
+int log_level() {
+    std::call_once(g_log_once, log_init);
+    return g_log_level;
+}
+
+void log_line(const std::string& event, const std::string& fields) {
+    if (log_level() == 0) return;
+    std::string line = "{\"t_ms\": " + num(now_ms()) + ", \"event\": \"" + event + "\"";
+    if (!fields.empty()) line += ", " + fields;
+    line += "}\n";
+    std::lock_guard<std::mutex> g(g_log_mu);
+    std::fputs(line.c_str(), g_log_file);
+    std::fflush(g_log_file);
+}
+
+CallLog::CallLog(mrc_ctx* c, const char* n) : ctx(c), name(n) {
+    on = log_level() >= 1;
+    if (!on) return;
+    t0 = now_ms();
+    if (log_level() >= 2 && ctx && ctx->sticky == MRC_OK) {
+        timer_collect(ctx);
+        before = ctx->timers;
+        timing_was = ctx->timing;
+        ctx->timing = true;
+        timers = true;
+    }
+}
+
+void CallLog::add(const char* key, int64_t v) {
+    if (!on) return;
+    if (!fields.empty()) fields += ", ";
+    fields += "\"" + std::string(key) + "\": " + std::to_string(v);
+}
+
+void CallLog::add(const char* key, double v) {
+    if (!on) return;
+    if (!fields.empty()) fields += ", ";
+    fields += "\"" + std::string(key) + "\": " + num(v);
+}
+
+mrc_status CallLog::done(mrc_status st) {
+    if (!on) return st;
+    std::string f = "\"call\": \"" + std::string(name) + "\", \"status\": " + std::to_string(st) +
+                    ", \"wall_ms\": " + num(now_ms() - t0);
+    if (!fields.empty()) f += ", " + fields;
+    if (timers) {
+        timer_collect(ctx);
+        std::string stages;
+        for (const auto& kv : ctx->timers) {
+            auto it = before.find(kv.first);
+            const double ms = kv.second.total_ms - (it == before.end() ? 0.0 : it->second.total_ms);
+            const int64_t nl = kv.second.launches - (it == before.end() ? 0 : it->second.launches);
+            if (nl <= 0) continue;
+            if (!stages.empty()) stages += ", ";
+            stages += "\"" + kv.first + "\": {\"ms\": " + num(ms) + ", \"launches\": " + std::to_string(nl) + "}";
+        }
+        f += ", \"stages\": {" + stages + "}";
+        ctx->timing = timing_was;
+    }
+    log_line("call", f);
+    return st;
 }
 
 void timer_collect(mrc_ctx* ctx) {

@@ -5,6 +5,8 @@
 // overlap on the device.
 #include <algorithm>
 
+#include <chrono>
+
 #include "common.h"
 #include "serve_core.h"
 
@@ -63,6 +65,18 @@ class GpuExecutor : public mrc_serve::Executor {
         return (size_t)t * 4 + (size_t)(n + 1) * 8 + (size_t)n * per_doc;
     }
     int run(int slot, mrc_serve::Batch& b, std::vector<mrc_serve::Result>& out) override {
+        if (log_level() < 3) return run_batch(slot, b, out);
+        const auto t0 = std::chrono::steady_clock::now();
+        const int rc = run_batch(slot, b, out);
+        const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        log_line("serve_batch", "\"slot\": " + std::to_string(slot) + ", \"kind\": \"" +
+                                    (b.kind == mrc_serve::kInsert ? "insert" : "query") + "\", \"docs\": " +
+                                    std::to_string(b.reqs.size()) + ", \"tokens\": " + std::to_string(b.tokens) +
+                                    ", \"status\": " + std::to_string(rc) + ", \"ms\": " + std::to_string(ms));
+        return rc;
+    }
+
+    int run_batch(int slot, mrc_serve::Batch& b, std::vector<mrc_serve::Result>& out) {
         GpuSlot& sl = slots_[slot];
         const int64_t n = (int64_t)b.reqs.size(), T = std::max<int64_t>(1, b.tokens);
         mrc_status st = reserve(sl, n, T);
@@ -271,6 +285,15 @@ mrc_status mrc_serve_poll(mrc_server* srv, uint64_t ticket, mrc_result* out, int
 mrc_status mrc_serve_stop(mrc_server* srv) {
     if (!srv) return MRC_OK;
     srv->sched->stop();
+    if (log_level() >= 1) {
+        const mrc_serve::Stats st = srv->sched->stats();
+        log_line("serve_stop", "\"submitted\": " + std::to_string(st.submitted) + ", \"rejected\": " +
+                                   std::to_string(st.rejected) + ", \"completed\": " + std::to_string(st.completed) +
+                                   ", \"failed\": " + std::to_string(st.failed) + ", \"batches\": " +
+                                   std::to_string(st.batches) + ", \"peak_in_flight_bytes\": " +
+                                   std::to_string(st.peak_in_flight_bytes) + ", \"peak_concurrent_batches\": " +
+                                   std::to_string(st.peak_concurrent_batches));
+    }
     delete srv->sched;
     delete srv->ex;
     // a database or model destroyed while this server ran is freed now
