@@ -25,9 +25,28 @@ constexpr int kWT = 64;
 // own buffer and reserves global output space with one atomic per flush.
 constexpr int kStage = 512;
 
+// (the buffer is typed as LDS: through a generic pointer its stores would be
+// FLAT operations, after which the compiler can only wait for all memory
+// operations in flight)
+// (16-byte pairs held as a builtin 4-int vector, which stores to LDS directly)
+typedef int pair_bits __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) pair_bits lds_pair;
+static_assert(sizeof(mrc_pair) == sizeof(pair_bits), "a pair is 16 bytes");
+__device__ __forceinline__ void stage_put(lds_pair* buf, int pos, const mrc_pair& p) {
+    pair_bits v;
+    __builtin_memcpy(&v, &p, sizeof v);
+    buf[pos] = v;
+}
+__device__ __forceinline__ mrc_pair stage_get(const lds_pair* buf, int pos) {
+    const pair_bits v = buf[pos];
+    mrc_pair p;
+    __builtin_memcpy(&p, &v, sizeof p);
+    return p;
+}
 struct PairStage {
-    mrc_pair* buf;  // LDS, kStage entries of this wavefront
+    lds_pair* buf;  // LDS, kStage entries of this wavefront
     int n;          // staged entries (wavefront-uniform)
+    __device__ PairStage(mrc_pair* lds_buf, int n0) : buf((lds_pair*)lds_buf), n(n0) {}
 
     __device__ __forceinline__ void flush(const PairSink& sink) {
         if (n == 0) return;
@@ -38,13 +57,28 @@ struct PairStage {
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         for (int e = lane; e < n; e += 64) {
             const int64_t dst = (int64_t)base + e;
-            if (dst < sink.capacity) sink.pairs[dst] = buf[e];
+            if (dst < sink.capacity) sink.pairs[dst] = stage_get(buf, e);
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
         n = 0;
     }
 };
+
+// Exclusive prefix sum over the wavefront of a per-lane count below 64, and
+// the total: bit b of every lane's count is one ballot, whose set lanes below
+// this one (mbcnt) contribute 2^b; no data moves between lanes.
+__device__ __forceinline__ void wave_prefix6(int cnt, int* excl, int* total) {
+    int e = 0, t = 0;
+#pragma unroll
+    for (int b = 0; b < 6; ++b) {
+        const uint64_t bal = __ballot((cnt >> b) & 1);
+        e += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u)) << b;
+        t += __popcll(bal) << b;
+    }
+    *excl = e;
+    *total = t;
+}
 
 // Epilogue of one 64x64 wavefront tile, half H (accumulator rows x = 2H, 2H+1).
 // Lane (li, lg) holds acc[x][y][r] = score of row ib + 16x + r, column
@@ -76,13 +110,8 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
         m &= valid;
     }
     const int cnt = __popc(m);
-    int incl = cnt;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const int t = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += t;
-    }
-    const int total = __shfl(incl, 63, 64);
+    int excl, total;
+    wave_prefix6(cnt, &excl, &total);
     if (total == 0) return;
     if (m) {
 #pragma unroll
@@ -96,9 +125,9 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
     if (direct) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(sink.counter, (unsigned long long)total);
-        pos = (int64_t)__shfl(base, 0, 64) + incl - cnt;
+        pos = (int64_t)__shfl(base, 0, 64) + excl;
     } else {
-        pos = st.n + incl - cnt;
+        pos = st.n + excl;
         st.n += total;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -111,7 +140,7 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
         if (direct) {
             if (pos < sink.capacity) sink.pairs[pos] = pr;
         } else {
-            st.buf[pos] = pr;
+            stage_put(st.buf, (int)pos, pr);
         }
         ++pos;
     }

@@ -99,6 +99,98 @@ __global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u
     st.flush(sink);
 }
 
+// k in (32, 64] (four 16-column chunks): one wavefront per SIMD, so that its
+// matrix-core products stream at the single-wavefront rate, fed by a ring of
+// four chunk buffers in registers: the loads of chunk c + 3 are issued before
+// the products of chunk c (during a tile's chunks 1-3, the next tile's chunks
+// 0-2), so three chunks are in flight while one is multiplied. Chunk c of
+// every tile lives in buffer c, so the ring needs no register copies, and the
+// loads are unconditional (without a next tile: this one again), so the
+// compiler's waits stay exact. Same products in the same order as
+// k_compare_f32: every score is the plain chain.
+__global__ __launch_bounds__(256, 1) void k_compare_f32r(const float* __restrict__ u, int n, float tau,
+                                                         TileOrder ord, PairSink sink) {
+    constexpr int NC = 4;
+    __shared__ TileLds lds;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int li = lane & 15, lg = lane >> 4;
+    PairStage st{lds.stage[wave], 0};
+    float* scr = lds.scr[wave];
+    const int64_t xcd = blockIdx.x % 8, per_xcd_blocks = gridDim.x / 8, bx = blockIdx.x / 8;
+    const int64_t t_lo = ord.n_tiles * xcd / 8, t_hi = ord.n_tiles * (xcd + 1) / 8;
+    const int64_t stride = per_xcd_blocks * 4;
+    int64_t t = t_lo + bx * 4 + wave;
+    if (t >= t_hi) return;
+    TileOrder::Cursor cur = ord.seek(t);
+    int bi, bj;
+    ord.tile(cur, t, &bi, &bj);
+    // a 64-row panel (16 KB) as a buffer: wavefront-uniform descriptor, the
+    // lane's fixed 16-byte offset, the fragment's offset in a scalar register
+    constexpr int kPanelB = 64 * NC * 64;
+    auto panel = [&](int blk) {
+        return __builtin_amdgcn_make_buffer_rsrc((void*)(u + (int64_t)blk * (kPanelB / 4)), (short)0, kPanelB,
+                                                 0x00020000);
+    };
+    const int lane16 = 16 * lane;
+    auto frag = [&](__amdgpu_buffer_rsrc_t p, int x, int c) {
+        const auto v = __builtin_amdgcn_raw_buffer_load_b128(p, lane16, (x * NC + c) * 1024, 0);
+        f32x4 f;
+        __builtin_memcpy(&f, &v, 16);
+        return f;
+    };
+    __amdgpu_buffer_rsrc_t pa = panel(bi), pb = panel(bj);
+    f32x4 ra[NC][4], rb[NC][4];  // [chunk = buffer][16-row block]
+    auto load = [&](__amdgpu_buffer_rsrc_t p, __amdgpu_buffer_rsrc_t q, int c) __attribute__((always_inline)) {
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            ra[c][x] = frag(p, x, c);
+            rb[c][x] = frag(q, x, c);
+        }
+    };
+    load(pa, pb, 0);
+    load(pa, pb, 1);
+    load(pa, pb, 2);
+    while (true) {
+        const int64_t tn = t + stride;
+        const bool more = tn < t_hi;
+        int ni = bi, nj = bj;
+        if (more) ord.tile(cur, tn, &ni, &nj);
+        const __amdgpu_buffer_rsrc_t na = panel(ni), nb = panel(nj);
+        f32x4 acc[4][4];
+#pragma unroll
+        for (int x = 0; x < 4; ++x)
+#pragma unroll
+            for (int y = 0; y < 4; ++y) acc[x][y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int row0 = bi * kWT, col0 = bj * kWT;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            // chunk c + 3: this tile's last chunk, then the next tile's first three
+            if (c == 0) load(pa, pb, 3);
+            else load(na, nb, c - 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int m = 0; m < 4; ++m)
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 4; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f32_16x16x4f32(ra[c][x][m], rb[c][y][m], acc[x][y], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        const bool interior = row0 + kWT <= col0 && col0 + kWT <= n;
+        const int ib = row0 + 4 * lg, jb = col0 + li;
+        tile_epilogue(acc, tau, interior, ib, jb, n, scr, st, sink);
+        if (!more) break;
+        t = tn;
+        bi = ni;
+        bj = nj;
+        pa = na;
+        pb = nb;
+    }
+    st.flush(sink);
+}
+
 }  // namespace
 
 namespace mrc {
@@ -111,6 +203,12 @@ mrc_status launch_compare_f32_small(mrc_ctx* ctx, const float* umfma, int64_t n,
     MRC_TRY(make_tile_order(ctx, (int)ceil_div(n, kWT), 4, &ord, &grid, s, table));
     const int nc = mfma_chunks(k);
     ScopedTimer tm(ctx, "compare_f32", s);
+    if (nc == 4) {
+        const int64_t pgrid = persistent_grid(ctx, (const void*)k_compare_f32r, 256, grid);
+        hipLaunchKernelGGL(k_compare_f32r, dim3((unsigned)pgrid), dim3(256), 0, s, umfma, (int)n, tau, ord, sink);
+        MRC_HIP_TRY(ctx, hipGetLastError());
+        return MRC_OK;
+    }
     switch (nc) {
 #define MRC_NC(c)                                                                                        \
     case c: {                                                                                            \

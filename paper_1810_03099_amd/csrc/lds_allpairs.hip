@@ -354,13 +354,8 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
                         m |= (scr[i * 64 + lane] >= thr && r < cc && cc < n ? 1u : 0u) << i;
                     }
                     const int cnt = __popc(m);
-                    int incl = cnt;
-#pragma unroll
-                    for (int off = 1; off < 64; off <<= 1) {
-                        const int u = __shfl_up(incl, off, 64);
-                        if (lane >= off) incl += u;
-                    }
-                    const int total = __shfl(incl, 63, 64);
+                    int excl, total;
+                    wave_prefix6(cnt, &excl, &total);
                     if (total == 0) continue;
                     __builtin_amdgcn_sched_barrier(0);
                     if (st.n + total > kStageB) st.flush(cand);
@@ -369,9 +364,9 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
                     if (direct) {
                         unsigned long long base = 0;
                         if (lane == 0) base = atomicAdd(cand.counter, (unsigned long long)total);
-                        pos = (int64_t)__shfl(base, 0, 64) + incl - cnt;
+                        pos = (int64_t)__shfl(base, 0, 64) + excl;
                     } else {
-                        pos = st.n + incl - cnt;
+                        pos = st.n + excl;
                         st.n += total;
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -383,7 +378,7 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
                         if (direct) {
                             if (pos < cand.capacity) cand.pairs[pos] = pr;
                         } else {
-                            st.buf[pos] = pr;
+                            stage_put(st.buf, (int)pos, pr);
                         }
                         ++pos;
                     }
