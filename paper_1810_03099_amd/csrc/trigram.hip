@@ -111,12 +111,16 @@ __global__ __launch_bounds__(kTriBlock) void k_tri_offsets(const int64_t* __rest
 // Four bytes at the 4-byte-aligned address x, as a little-endian word; a word
 // that reaches outside [lo, hi) is assembled from its bytes inside it (zero
 // elsewhere), so no access leaves the caller's buffer.
-__device__ __forceinline__ uint32_t tri_word(uintptr_t x, uintptr_t lo, uintptr_t hi) {
-    if (x >= lo && x + 4 <= hi) return *(const uint32_t*)x;
+// (The loads go through `text` itself, the buffer's first byte at address
+// lo, so that they are global loads: through a pointer made from an integer
+// they would be FLAT, after which every wait drains all loads in flight.)
+__device__ __forceinline__ uint32_t tri_word(const uint8_t* __restrict__ text, uintptr_t x, uintptr_t lo,
+                                             uintptr_t hi) {
+    if (x >= lo && x + 4 <= hi) return *(const uint32_t*)(text + (x - lo));
     uint32_t w = 0;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-        if (x + i >= lo && x + i < hi) w |= (uint32_t)(*(const uint8_t*)(x + i)) << (8 * i);
+        if (x + i >= lo && x + i < hi) w |= (uint32_t)text[x + i - lo] << (8 * i);
     return w;
 }
 
@@ -163,10 +167,10 @@ __global__ __launch_bounds__(kTriBlock) void k_trigrams(const uint8_t* __restric
 #pragma unroll
                 for (int j = 0; j < kTriWords; ++j) {
                     const uintptr_t x = r + 256 * j + 4 * (uintptr_t)lane;
-                    w[j] = x <= pend ? tri_word(x, lo, hi) : 0u;
+                    w[j] = x <= pend ? tri_word(text, x, lo, hi) : 0u;
                 }
                 const uintptr_t xt = r + 256 * kTriWords;
-                const uint32_t tail = (lane == 63 && xt <= pend) ? tri_word(xt, lo, hi) : 0u;
+                const uint32_t tail = (lane == 63 && xt <= pend) ? tri_word(text, xt, lo, hi) : 0u;
                 const uint32_t tail_all = __shfl(tail, 63, 64);
 #pragma unroll
                 for (int j = 0; j < kTriWords; ++j) {
