@@ -95,6 +95,33 @@ __device__ __forceinline__ void top_insert(float (&s)[kTop], int (&id)[kTop], fl
     }
 }
 
+// Candidate marks of one query group on one 64-row tile: bit 4x + r of lane
+// (li, lg) is set when row row0 + 16x + 4lg + r scores at least the query's
+// threshold. The sign of score - threshold decides, which for finite values
+// is the comparison itself (a difference is zero only for equal operands, and
+// a flush to zero keeps its sign); a funnel shift moves each sign into the
+// word, one instruction per score. Invalid queries carry threshold +inf;
+// rowmask clears rows past the end of the database.
+__device__ __forceinline__ uint32_t tile_marks(const f32x4 (&acc)[4], float thr, uint32_t rowmask) {
+#pragma clang fp contract(off)  // (the score as rounded, not fused into the difference)
+    uint32_t below = 0;
+#pragma unroll
+    for (int e = 15; e >= 0; --e)
+        below = __builtin_amdgcn_alignbit(below, __float_as_uint(acc[e >> 2][e & 3] - thr), 31);
+    return ~below & rowmask;
+}
+
+// The marks a tile's rows allow: all 16, except on the last tile, where the
+// rows at or past rows_left (counted from the tile's first row) drop out.
+__device__ __forceinline__ uint32_t tile_rowmask(int64_t rows_left, int lg) {
+    if (rows_left >= kTileRows) return 0xffffu;
+    uint32_t m = 0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+        if (16 * (e >> 2) + 4 * lg + (e & 3) < rows_left) m |= 1u << e;
+    return m;
+}
+
 struct ScanArgs {
     const uint8_t* db;        // [rows_pad][ld_db] codes (FP32: matrix-core layout floats)
     int ld_db;                // bytes per row
@@ -110,7 +137,7 @@ struct ScanArgs {
     int32_t* part_id;
     // MODE_COLLECT: candidates with score >= thr[q]
     const float* thr;
-    int64_t* cand;            // [nq][cap] packed (id << 32 | float bits)
+    int32_t* cand;            // [nq][cap] row ids
     int32_t* ccount;          // [nq]
     int cap;
     // persistent collection: items (query block, kPersistTiles tiles) taken in
@@ -122,6 +149,40 @@ struct ScanArgs {
 
 // Tiles per work item of the persistent collection.
 constexpr int kPersistTiles = 16;
+
+// Slots for a tile's marks: every lane with marks adds its count to its
+// query's candidate counter (a query's lanes take their ranges in any order:
+// the final pass orders the candidates itself).
+template <int G>
+__device__ __forceinline__ void reserve_marks(const ScanArgs& a, const uint32_t (&m)[G], const int (&q)[G],
+                                              int (&base)[G]) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        base[g] = 0;
+        if (m[g]) base[g] = atomicAdd(&a.ccount[q[g]], __popc(m[g]));
+    }
+}
+
+// Write the row ids of a tile's marks into their slots; those past the
+// capacity are dropped (the counter still counts them: the host grows the
+// capacity and collects again).
+template <int G>
+__device__ __forceinline__ void write_marks(const ScanArgs& a, const uint32_t (&m)[G], const int (&q)[G],
+                                            const int (&base)[G], int64_t row0, int lg) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        uint32_t mm = m[g];
+        int b = base[g];
+        int32_t* dst = a.cand + (int64_t)q[g] * a.cap;
+        const int r0 = (int)row0 + 4 * lg;
+        while (mm) {
+            const int e = __builtin_ctz(mm);
+            mm &= mm - 1;
+            if (b < a.cap) dst[b] = r0 + 16 * (e >> 2) + (e & 3);
+            ++b;
+        }
+    }
+}
 
 enum { MODE_TOP = 0, MODE_COLLECT = 1 };
 
@@ -145,6 +206,17 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     int q[G];
     bool qvalid[G];
     float qsc[G], thr[G];
+    // collection: the previous tile's marks, their reserved slots and first
+    // row (written once the next tile's loads have returned, by when the
+    // slot atomics issued before them have too)
+    uint32_t pm[G];
+    int pb[G];
+    int64_t prow0 = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        pm[g] = 0;
+        pb[g] = 0;
+    }
     // the query fragments of block y (PERS: the block of the current item)
     auto load_queries = [&](int64_t y) {
 #pragma unroll
@@ -155,7 +227,10 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
 #pragma unroll
             for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
             qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
-            thr[g] = (MODE == MODE_COLLECT && qvalid[g]) ? a.thr[q[g]] : 0.f;
+            if (MODE == MODE_COLLECT) {
+                const float t = qvalid[g] ? a.thr[q[g]] : INFINITY;
+                thr[g] = t == t ? t : INFINITY;  // (no marks for a NaN threshold)
+            }
         }
     };
     int64_t cur_y = PERS ? -1 : (int64_t)blockIdx.y;
@@ -177,6 +252,11 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     const int64_t stride = PERS ? 1 : (int64_t)gridDim.x * 4;
     while (true) {
         if (PERS && t >= t_end) {
+            if (MODE == MODE_COLLECT) {  // the pending marks belong to the current query block
+                write_marks(a, pm, q, pb, prow0, lg);
+#pragma unroll
+                for (int g = 0; g < G; ++g) pm[g] = 0;
+            }
             unsigned long long it = 0;
             if (lane == 0) it = atomicAdd(a.work, 1ull);
             const int64_t item = (int64_t)__shfl(it, 0, 64);
@@ -225,62 +305,41 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
                     for (int r = 0; r < 4; ++r) acc[g][x][r] = acc[g][x][r] * sc[r] * qsc[g];
             }
         }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            // the lane's largest score decides whether any of its 16 can matter:
-            // below the list's last entry or below the collection threshold,
-            // the tile changes nothing
+        if constexpr (MODE == MODE_TOP) {
+            // the lane's largest score decides whether any of its 16 can
+            // matter: below the list's last entry the tile changes nothing
             float mx = -INFINITY;
 #pragma unroll
             for (int x = 0; x < 4; ++x)
-                mx = fmaxf(mx, fmaxf(fmaxf(acc[g][x][0], acc[g][x][1]), fmaxf(acc[g][x][2], acc[g][x][3])));
-            if (MODE == MODE_TOP) {
-                if (mx < ts[kTop - 1] || !qvalid[g]) continue;
+                mx = fmaxf(mx, fmaxf(fmaxf(acc[0][x][0], acc[0][x][1]), fmaxf(acc[0][x][2], acc[0][x][3])));
+            if (!(mx < ts[kTop - 1] || !qvalid[0])) {
 #pragma unroll
                 for (int x = 0; x < 4; ++x)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
                         const int64_t row = row0 + 16 * x + 4 * lg + r;
-                        const float v = acc[g][x][r];
+                        const float v = acc[0][x][r];
                         if (row < a.rows && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1]))
                             top_insert(ts, tid_, v, (int)row);
                     }
-            } else {
-                // candidates of this lane (bit 4x + r), counted per query over
-                // its 4 lanes (lane groups) so that one atomic reserves them all
-                uint32_t m = 0;
-                if (qvalid[g] && mx >= thr[g]) {
-#pragma unroll
-                    for (int x = 0; x < 4; ++x)
-#pragma unroll
-                        for (int r = 0; r < 4; ++r)
-                            if (row0 + 16 * x + 4 * lg + r < a.rows && acc[g][x][r] >= thr[g]) m |= 1u << (4 * x + r);
-                }
-                if (__ballot(m != 0) == 0) continue;  // (wavefront-uniform)
-                const int cnt = __popc(m);
-                const int c0 = __shfl(cnt, li, 64), c1 = __shfl(cnt, li + 16, 64), c2 = __shfl(cnt, li + 32, 64),
-                          c3 = __shfl(cnt, li + 48, 64);
-                const int pre = (lg > 0 ? c0 : 0) + (lg > 1 ? c1 : 0) + (lg > 2 ? c2 : 0);
-                const int tot = c0 + c1 + c2 + c3;
-                int base = 0;
-                if (lg == 0 && tot > 0) base = atomicAdd(&a.ccount[q[g]], tot);
-                base = __shfl(base, li, 64) + pre;
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (m & (1u << (4 * x + r))) {
-                            if (base < a.cap)
-                                a.cand[(int64_t)q[g] * a.cap + base] =
-                                    ((int64_t)(row0 + 16 * x + 4 * lg + r) << 32) |
-                                    (int64_t)__float_as_uint(acc[g][x][r]);
-                            ++base;
-                        }
             }
+        } else {
+            uint32_t m[G];
+            const uint32_t rm = tile_rowmask(a.rows - row0, lg);
+#pragma unroll
+            for (int g = 0; g < G; ++g) m[g] = tile_marks(acc[g], thr[g], rm);
+            write_marks(a, pm, q, pb, prow0, lg);
+            reserve_marks(a, m, q, pb);
+#pragma unroll
+            for (int g = 0; g < G; ++g) pm[g] = m[g];
+            prow0 = row0;
         }
         t += stride;
     }
-    if (MODE == MODE_COLLECT) return;
+    if (MODE == MODE_COLLECT) {
+        write_marks(a, pm, q, pb, prow0, lg);
+        return;
+    }
     // workgroup merge: 16 lists (4 wavefronts x 4 lane groups) per query
 #pragma unroll
     for (int p = 0; p < kTop; ++p) {
@@ -452,7 +511,7 @@ __global__ __launch_bounds__(256) void k_query_e16(const mrc_hit* __restrict__ l
 // Exact decisions for the collected candidates of each query (one workgroup
 // per query): FP32 chain over the natural-order query unit vector and the
 // database row in matrix-core layout, then top list and hit count.
-__global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__ cand, const int32_t* __restrict__ ccount,
+__global__ __launch_bounds__(256) void k_query_final(const int32_t* __restrict__ cand, const int32_t* __restrict__ ccount,
                                                      int cap, const float* __restrict__ qunit, int k,
                                                      const float* __restrict__ db_umfma, int kp, float tau, int topk,
                                                      mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
@@ -479,8 +538,7 @@ __global__ __launch_bounds__(256) void k_query_final(const int64_t* __restrict__
     }
     int hits = 0;
     for (int e = threadIdx.x; e < nc; e += 256) {
-        const int64_t pk = cand[(int64_t)q * cap + e];
-        const int row = (int)(pk >> 32);
+        const int row = cand[(int64_t)q * cap + e];
         const float acc = chain_score_wide(qs, db_umfma + (int64_t)row * kp, k);
         hits += acc >= tau ? 1 : 0;
         if (better(acc, row, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, acc, row);
@@ -563,8 +621,17 @@ __global__ void k_max_err(const float* __restrict__ db_max, const float* __restr
 // workgroup barrier per tile (every wavefront walks the same tiles).
 constexpr int kLdsRowMax = 1024;  // bytes per database row this kernel stages
 
+// Two wavefronts per SIMD (256 registers each) where the query fragments
+// and accumulators leave room in that budget: one's products then overlap
+// the other's marks, writes and barrier waits.
+template <int PREC, int NK, int G>
+constexpr int collect_waves() {
+    return PREC != MRC_PREC_FP8 && G * NK * QT<PREC>::kLaneBytes / 4 + 16 * G <= 128 ? 2 : 1;
+}
+
 template <int PREC, int NK, int G, bool PERS = false>
-__global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
+__global__ __attribute__((amdgpu_flat_work_group_size(1, 256), amdgpu_waves_per_eu(collect_waves<PREC, NK, G>())))
+void k_query_collect_lds(ScanArgs a) {
     using T = QT<PREC>;
     constexpr int ROW = NK * T::kChunkBytes;  // bytes per database row (= a.ld_db)
     constexpr int LD = ROW + 16;              // padded LDS row
@@ -590,14 +657,40 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
 #pragma unroll
             for (int c = 0; c < NK; ++c) qb[g][c] = T::load(pq + c * T::kChunkBytes);
             qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
-            thr[g] = qvalid[g] ? a.thr[q[g]] : 0.f;
+            const float th = qvalid[g] ? a.thr[q[g]] : INFINITY;
+            thr[g] = th == th ? th : INFINITY;  // (no marks for a NaN threshold)
         }
     };
     const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
-    // staging: thread piece j is 16 bytes at (row, column) of the tile
+    // staging: a tile is 64 consecutive rows of ROW bytes; thread piece j is
+    // the 16 bytes at tile offset 16 (threadIdx.x + 256 j), read through a
+    // per-tile buffer descriptor (uniform base, one lane offset, the piece's
+    // offset a constant)
     i32x4 st[PER];
+    const int voff = 16 * threadIdx.x;
+    auto stage_load = [&](int64_t tile) {
+        const auto rs = __builtin_amdgcn_make_buffer_rsrc((void*)(a.db + tile * (kTileRows * ROW)), (short)0,
+                                                          kTileRows * ROW, 0x00020000);
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b128(rs, voff, 4096 * j, 0);
+            __builtin_memcpy(&st[j], &v, 16);
+        }
+    };
     int cur = 0;
     int64_t cur_y = -1;
+    // the previous tile's marks, their reserved slots and first row: written
+    // after the next tile's staging loads have returned (the slot atomics,
+    // issued before them, have too), so the atomics' latency hides behind a
+    // tile of products
+    uint32_t pm[G];
+    int pb[G];
+    int64_t prow0 = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        pm[g] = 0;
+        pb[g] = 0;
+    }
     // grid form: one pass over tiles blockIdx.x, + gridDim.x, ... of query
     // block blockIdx.y; persistent form: items (query block, kPersistTiles
     // tiles) taken by the workgroup from the work counter until it passes the
@@ -625,11 +718,7 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
             step = gridDim.x;
         }
     if (t < t_end) {
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
-            st[j] = *(const i32x4*)(a.db + (t * kTileRows + r) * a.ld_db + c * 16);  // rows padded to 64
-        }
+        stage_load(t);  // (the database's rows are padded to whole tiles)
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
             const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
@@ -643,12 +732,10 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
         // the next tile's loads overlap this tile's products (without a next
         // tile: this one again, valid and unused, so that nothing branches
         // around the staged values)
-        const int64_t tl = more ? tn : t;
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {
-            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
-            st[j] = *(const i32x4*)(a.db + (tl * kTileRows + r) * a.ld_db + c * 16);
-        }
+        stage_load(more ? tn : t);
+        // (the scheduler keeps the loads here, a tile of products ahead of
+        // their use, and the marks below ahead of the pending writes)
+        __builtin_amdgcn_sched_barrier(0);
         const int64_t row0 = t * kTileRows;
         const uint8_t* pa = &buf[cur][li * LD + lg * T::kLaneBytes];
         f32x4 acc[G][4];
@@ -676,48 +763,31 @@ __global__ __launch_bounds__(256) void k_query_collect_lds(ScanArgs a) {
                     for (int r = 0; r < 4; ++r) acc[g][x][r] = acc[g][x][r] * sc[r] * qsc[g];
             }
         }
+        uint32_t m[G];
+        const uint32_t rm = tile_rowmask(a.rows - row0, lg);
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            float mx = -INFINITY;
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-                mx = fmaxf(mx, fmaxf(fmaxf(acc[g][x][0], acc[g][x][1]), fmaxf(acc[g][x][2], acc[g][x][3])));
-            uint32_t m = 0;
-            if (qvalid[g] && mx >= thr[g]) {
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r)
-                        if (row0 + 16 * x + 4 * lg + r < a.rows && acc[g][x][r] >= thr[g]) m |= 1u << (4 * x + r);
-            }
-            if (__ballot(m != 0) == 0) continue;  // (wavefront-uniform)
-            const int cnt = __popc(m);
-            const int c0 = __shfl(cnt, li, 64), c1 = __shfl(cnt, li + 16, 64), c2 = __shfl(cnt, li + 32, 64),
-                      c3 = __shfl(cnt, li + 48, 64);
-            const int pre = (lg > 0 ? c0 : 0) + (lg > 1 ? c1 : 0) + (lg > 2 ? c2 : 0);
-            const int tot = c0 + c1 + c2 + c3;
-            int base = 0;
-            if (lg == 0 && tot > 0) base = atomicAdd(&a.ccount[q[g]], tot);
-            base = __shfl(base, li, 64) + pre;
-#pragma unroll
-            for (int x = 0; x < 4; ++x)
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (m & (1u << (4 * x + r))) {
-                        if (base < a.cap)
-                            a.cand[(int64_t)q[g] * a.cap + base] = ((int64_t)(row0 + 16 * x + 4 * lg + r) << 32) |
-                                                                   (int64_t)__float_as_uint(acc[g][x][r]);
-                        ++base;
-                    }
+            m[g] = tile_marks(acc[g], thr[g], rm);
+            asm volatile("" : "+v"(m[g]));  // (computed here, not sunk to its use)
         }
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int j = 0; j < PER; ++j) {  // (after the last tile: written, never read)
             const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
             *(i32x4*)(&buf[cur ^ 1][r * LD + c * 16]) = st[j];
         }
+        write_marks(a, pm, q, pb, prow0, lg);
+        reserve_marks(a, m, q, pb);
+#pragma unroll
+        for (int g = 0; g < G; ++g) pm[g] = m[g];
+        prow0 = row0;
         __syncthreads();
         cur ^= 1;
     }
+        // the pending marks belong to this query block
+        write_marks(a, pm, q, pb, prow0, lg);
+#pragma unroll
+        for (int g = 0; g < G; ++g) pm[g] = 0;
         if (!PERS) break;
     }
 }
@@ -948,18 +1018,18 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     };
     int cap = 2048;
     auto it = ctx->scratch.find("q_cand");
-    if (it != ctx->scratch.end()) cap = std::max<int64_t>(cap, (int64_t)(it->second.second / 8 / nq));
+    if (it != ctx->scratch.end()) cap = std::max<int64_t>(cap, (int64_t)(it->second.second / 4 / nq));
     for (int attempt = 0; attempt < 3; ++attempt) {
-        MRC_TRY(scratch(ctx, "q_cand", (size_t)nq * cap * 8, &cand));
+        MRC_TRY(scratch(ctx, "q_cand", (size_t)nq * cap * 4, &cand));
         MRC_TRY(scratch(ctx, "q_ccount", (size_t)nq * 4, &cc));
         MRC_HIP_TRY(ctx, hipMemsetAsync(cc, 0, (size_t)nq * 4, s));
         MRC_TRY(clear_words(ctx, ctx->d_flags + kQueryCapWord, 1, s));
         a.thr = (const float*)thr;
-        a.cand = (int64_t*)cand;
+        a.cand = (int32_t*)cand;
         a.ccount = (int32_t*)cc;
         a.cap = cap;
         MRC_TRY(collect());
-        hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int64_t*)cand,
+        hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int32_t*)cand,
                            (const int32_t*)cc, cap, (const float*)unit, k, db->d_unit, L.kp, tau, topk, topk_out,
                            n_hits, fp32 ? 0 : 1, (unsigned long long*)(ctx->d_flags + kQueryCapWord));
         MRC_HIP_TRY(ctx, hipGetLastError());
