@@ -378,10 +378,11 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     }
 }
 
-// Per query: merge the workgroup lists into the final top list (one wavefront
-// per query; each lane first reduces its share of the lists).
+// Per query: the best topk of its `total` partial entries (workgroup lists,
+// or stream maxima), one wavefront per query; each lane first reduces its
+// share of the entries.
 __global__ __launch_bounds__(256) void k_query_merge(const float* __restrict__ part_s, const int32_t* __restrict__ part_id,
-                                                     int gx, int nq, int topk, const int32_t* __restrict__ hits,
+                                                     int64_t total, int nq, int topk, const int32_t* __restrict__ hits,
                                                      mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
                                                      float* __restrict__ l16) {
     const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -394,7 +395,6 @@ __global__ __launch_bounds__(256) void k_query_merge(const float* __restrict__ p
         ts[p] = -INFINITY;
         ti[p] = 0x7fffffff;
     }
-    const int64_t total = (int64_t)gx * kTop;
     for (int64_t e = lane; e < total; e += 64) {
         const float v = part_s[(int64_t)q * total + e];
         const int id = part_id[(int64_t)q * total + e];
@@ -461,33 +461,6 @@ __device__ __forceinline__ float chain_score(const float* __restrict__ qu, const
     return acc;
 }
 
-// The same chain with the query row in LDS and the database row read four
-// 16-component blocks per round trip (components in the same ascending order,
-// so the same bits as chain_score).
-__device__ __forceinline__ float chain_score_wide(const float* __restrict__ qu_lds, const float* __restrict__ dr,
-                                                  int k) {
-    float acc = 0.f;
-    for (int c0 = 0; c0 < k; c0 += 64) {
-        f32x4 blk[4][4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-            if (c0 + 16 * b < k) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) blk[b][j] = *(const f32x4*)(dr + c0 + 16 * b + 4 * j);
-            }
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int cb = c0 + 16 * b;
-            if (cb >= k) break;
-            const int m = min(16, k - cb);
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c < m) acc = __builtin_fmaf(qu_lds[cb + c], blk[b][c & 3][c >> 2], acc);
-        }
-    }
-    return acc;
-}
-
 // E16[q]: the exact (chain) score of the 16th best of the query's 16 best rows
 // by the low-precision score (-inf with fewer than 16 rows). The exact 16th
 // best over all rows is at least this, so a row can only enter the exact
@@ -509,25 +482,32 @@ __global__ __launch_bounds__(256) void k_query_e16(const mrc_hit* __restrict__ l
 }
 
 // Exact decisions for the collected candidates of each query (one workgroup
-// per query): FP32 chain over the natural-order query unit vector and the
-// database row in matrix-core layout, then top list and hit count.
+// per query): the FP32 chain over the natural-order query unit vector and the
+// database row in matrix-core layout, then the top list and the hit count.
+// The query sits in LDS padded with zeros to the row's kp components (the
+// database rows are zero there too): fmaf(0, 0, acc) is acc, so the chain
+// over kp components has the bits of the chain over k. A lane reads four
+// 16-component blocks of its row per round trip (16-byte loads) and the
+// matching query blocks from LDS (the same address in every lane), then
+// consumes them in component order.
 __global__ __launch_bounds__(256) void k_query_final(const int32_t* __restrict__ cand, const int32_t* __restrict__ ccount,
                                                      int cap, const float* __restrict__ qunit, int k,
                                                      const float* __restrict__ db_umfma, int kp, float tau, int topk,
                                                      mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
                                                      int flags, unsigned long long* __restrict__ err) {
-    __shared__ float ss[4][kTop];
-    __shared__ int si[4][kTop];
-    __shared__ int shits;
-    __shared__ float qs[1024];  // the query's unit vector (k <= 1024)
+    __shared__ f32x4 qs[256];  // the query, kp <= 1024 components
+    __shared__ float ss[4 * kTop];
+    __shared__ int si[4 * kTop];
+    __shared__ int sh[4];
     const int q = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int nc = ccount[q];
-    if (nc > cap) {
+    if (nc > cap) {  // (the same for the whole workgroup)
         if (threadIdx.x == 0) atomicOr(err, kErrQueryCap);
         return;
     }
-    if (threadIdx.x == 0) shits = 0;
-    for (int c = threadIdx.x; c < k; c += 256) qs[c] = qunit[(int64_t)q * k + c];
+    float* qf = (float*)qs;
+    for (int c = threadIdx.x; c < kp; c += 256) qf[c] = c < k ? qunit[(int64_t)q * k + c] : 0.f;
     __syncthreads();
     float ts[kTop];
     int ti[kTop];
@@ -537,16 +517,45 @@ __global__ __launch_bounds__(256) void k_query_final(const int32_t* __restrict__
         ti[p] = 0x7fffffff;
     }
     int hits = 0;
+    const int nb = kp / 16;  // (even: kp is a whole number of 32-component pairs)
     for (int e = threadIdx.x; e < nc; e += 256) {
         const int row = cand[(int64_t)q * cap + e];
-        const float acc = chain_score_wide(qs, db_umfma + (int64_t)row * kp, k);
+        const f32x4* dr = (const f32x4*)(db_umfma + (int64_t)row * kp);
+        float acc = 0.f;
+        int b = 0;
+        for (; b + 4 <= nb; b += 4) {
+            f32x4 blk[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) blk[j] = dr[4 * b + j];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                f32x4 qv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) qv[j] = qs[4 * (b + h) + j];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) acc = __builtin_fmaf(qv[c >> 2][c & 3], blk[4 * h + (c & 3)][c >> 2], acc);
+            }
+        }
+        if (b < nb) {  // the last two blocks
+            f32x4 blk[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) blk[j] = dr[4 * b + j];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                f32x4 qv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) qv[j] = qs[4 * (b + h) + j];
+#pragma unroll
+                for (int c = 0; c < 16; ++c) acc = __builtin_fmaf(qv[c >> 2][c & 3], blk[4 * h + (c & 3)][c >> 2], acc);
+            }
+        }
         hits += acc >= tau ? 1 : 0;
         if (better(acc, row, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, acc, row);
     }
-    // merge 256 lists: within each wavefront, then across the 4 in LDS
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    // each wavefront's best topk of its 64 lists (repeatedly the best head
+    // across lanes), then the best topk of the four in wavefront 0
     int h = 0;
-    for (int p = 0; p < kTop; ++p) {
+    for (int p = 0; p < topk; ++p) {
         float hs = -INFINITY;
         int hi = 0x7fffffff;
 #pragma unroll
@@ -565,35 +574,41 @@ __global__ __launch_bounds__(256) void k_query_final(const int32_t* __restrict__
                 bi = oi;
             }
         }
-        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;
+        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;  // ids are unique: one lane pops
         if (lane == 0) {
-            ss[w][p] = bs;
-            si[w][p] = bi;
+            ss[w * kTop + p] = bs;
+            si[w * kTop + p] = bi;
         }
     }
     hits = mrc_dev::wave_sum(hits);
-    if (lane == 0) atomicAdd(&shits, hits);
+    if (lane == 0) sh[w] = hits;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        int hd[4] = {0, 0, 0, 0};
-        for (int p = 0; p < topk; ++p) {
-            int bw = 0;
-            float bs = -INFINITY;
-            int bi = 0x7fffffff;
-            for (int x = 0; x < 4; ++x) {
-                if (hd[x] < kTop && better(ss[x][hd[x]], si[x][hd[x]], bs, bi)) {
-                    bs = ss[x][hd[x]];
-                    bi = si[x][hd[x]];
-                    bw = x;
-                }
+    if (w != 0) return;
+    const int src = (lane >> 4) * kTop + (lane & 15);  // lane: entry (lane & 15) of wavefront lane >> 4
+    float v = (lane & 15) < topk ? ss[src] : -INFINITY;
+    int id = (lane & 15) < topk ? si[src] : 0x7fffffff;
+    for (int p = 0; p < topk; ++p) {
+        float bs = v;
+        int bi = id;
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float os = __shfl_xor(bs, off, 64);
+            const int oi = __shfl_xor(bi, off, 64);
+            if (better(os, oi, bs, bi)) {
+                bs = os;
+                bi = oi;
             }
-            hd[bw] += 1;
+        }
+        if (bi != 0x7fffffff && id == bi && v == bs) {  // (ids are unique: one lane)
+            v = -INFINITY;
+            id = 0x7fffffff;
+        }
+        if (lane == 0) {
             out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
             out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
             out[(int64_t)q * topk + p].flags = flags;
         }
-        n_hits[q] = shits;
     }
+    if (lane == 0) n_hits[q] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
 // delta = the largest rescoring band between the database rows (db_max: their
@@ -629,9 +644,10 @@ constexpr int collect_waves() {
     return PREC != MRC_PREC_FP8 && G * NK * QT<PREC>::kLaneBytes / 4 + 16 * G <= 128 ? 2 : 1;
 }
 
-template <int PREC, int NK, int G, bool PERS = false>
+template <int PREC, int NK, int G, int MODE, bool PERS = false>
 __global__ __attribute__((amdgpu_flat_work_group_size(1, 256), amdgpu_waves_per_eu(collect_waves<PREC, NK, G>())))
 void k_query_collect_lds(ScanArgs a) {
+    static_assert(!PERS || MODE == MODE_COLLECT, "the persistent form collects");
     using T = QT<PREC>;
     constexpr int ROW = NK * T::kChunkBytes;  // bytes per database row (= a.ld_db)
     constexpr int LD = ROW + 16;              // padded LDS row
@@ -686,10 +702,16 @@ void k_query_collect_lds(ScanArgs a) {
     uint32_t pm[G];
     int pb[G];
     int64_t prow0 = 0;
+    // MODE_TOP: the best (score, row) of each lane's stream of rows (lane
+    // group lg of this workgroup's tiles, ascending)
+    float bv[G];
+    int bi[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
         pm[g] = 0;
         pb[g] = 0;
+        bv[g] = -INFINITY;
+        bi[g] = 0x7fffffff;
     }
     // grid form: one pass over tiles blockIdx.x, + gridDim.x, ... of query
     // block blockIdx.y; persistent form: items (query block, kPersistTiles
@@ -763,47 +785,97 @@ void k_query_collect_lds(ScanArgs a) {
                     for (int r = 0; r < 4; ++r) acc[g][x][r] = acc[g][x][r] * sc[r] * qsc[g];
             }
         }
-        uint32_t m[G];
-        const uint32_t rm = tile_rowmask(a.rows - row0, lg);
+        auto stage_store = [&]() {  // (after the last tile: written, never read)
 #pragma unroll
-        for (int g = 0; g < G; ++g) {
-            m[g] = tile_marks(acc[g], thr[g], rm);
-            asm volatile("" : "+v"(m[g]));  // (computed here, not sunk to its use)
+            for (int j = 0; j < PER; ++j) {
+                const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
+                *(i32x4*)(&buf[cur ^ 1][r * LD + c * 16]) = st[j];
+            }
+        };
+        if constexpr (MODE == MODE_COLLECT) {
+            uint32_t m[G];
+            const uint32_t rm = tile_rowmask(a.rows - row0, lg);
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                m[g] = tile_marks(acc[g], thr[g], rm);
+                asm volatile("" : "+v"(m[g]));  // (computed here, not sunk to its use)
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            stage_store();
+            write_marks(a, pm, q, pb, prow0, lg);
+            reserve_marks(a, m, q, pb);
+#pragma unroll
+            for (int g = 0; g < G; ++g) pm[g] = m[g];
+            prow0 = row0;
+        } else {
+            const int64_t rows_left = a.rows - row0;
+            if (rows_left < kTileRows) {  // the last tile: rows past the end take no part
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e)
+                        if (16 * (e >> 2) + 4 * lg + (e & 3) >= rows_left) acc[g][e >> 2][e & 3] = -INFINITY;
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                // the tile's best of the lane's 16 (the first of equals: rows
+                // ascend with e), then against the stream's best so far
+                float tv = -INFINITY;
+                int te = 0;
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const float v = acc[g][e >> 2][e & 3];
+                    if (v > tv) {
+                        tv = v;
+                        te = e;
+                    }
+                }
+                if (tv > bv[g]) {
+                    bv[g] = tv;
+                    bi[g] = (int)row0 + 16 * (te >> 2) + 4 * lg + (te & 3);
+                }
+            }
+            stage_store();
         }
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int j = 0; j < PER; ++j) {  // (after the last tile: written, never read)
-            const int pc = threadIdx.x + 256 * j, r = pc / PIECES, c = pc % PIECES;
-            *(i32x4*)(&buf[cur ^ 1][r * LD + c * 16]) = st[j];
-        }
-        write_marks(a, pm, q, pb, prow0, lg);
-        reserve_marks(a, m, q, pb);
-#pragma unroll
-        for (int g = 0; g < G; ++g) pm[g] = m[g];
-        prow0 = row0;
         __syncthreads();
         cur ^= 1;
     }
-        // the pending marks belong to this query block
-        write_marks(a, pm, q, pb, prow0, lg);
+        if constexpr (MODE == MODE_COLLECT) {  // the pending marks belong to this query block
+            write_marks(a, pm, q, pb, prow0, lg);
 #pragma unroll
-        for (int g = 0; g < G; ++g) pm[g] = 0;
+            for (int g = 0; g < G; ++g) pm[g] = 0;
+        }
         if (!PERS) break;
+    }
+    if constexpr (MODE == MODE_TOP) {
+        // stream blockIdx.x * 4 + lg of each query: distinct rows in every
+        // stream, so any 16 stream maxima are 16 distinct rows
+        const int64_t streams = (int64_t)gridDim.x * 4;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+            if (q[g] < a.nq) {
+                const int64_t o = (int64_t)q[g] * streams + blockIdx.x * 4 + lg;
+                a.part_s[o] = bv[g];
+                a.part_id[o] = bi[g];
+            }
     }
 }
 
 // pers: the persistent form (grid = the workgroups resident at once, at most
 // a.n_items), else `grid`
-template <int PREC, int G, int NK>
+template <int PREC, int G, int NK, int MODE>
 bool launch_collect_lds_nk(mrc_ctx* ctx, bool pers, const ScanArgs& a, dim3 grid, hipStream_t s) {
     if constexpr (NK * QT<PREC>::kChunkBytes <= kLdsRowMax && G * NK * QT<PREC>::kLaneBytes / 4 <= 128) {
-        if (pers) {
-            const void* kf = (const void*)k_query_collect_lds<PREC, NK, G, true>;
-            const int64_t pg = persistent_grid(ctx, kf, 256, a.n_items);
-            hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G, true>), dim3((unsigned)pg), dim3(256), 0, s, a);
-        } else {
-            hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G>), grid, dim3(256), 0, s, a);
+        if constexpr (MODE == MODE_COLLECT) {
+            if (pers) {
+                const void* kf = (const void*)k_query_collect_lds<PREC, NK, G, MODE, true>;
+                const int64_t pg = persistent_grid(ctx, kf, 256, a.n_items);
+                hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G, MODE, true>), dim3((unsigned)pg), dim3(256), 0,
+                                   s, a);
+                return true;
+            }
         }
+        hipLaunchKernelGGL((k_query_collect_lds<PREC, NK, G, MODE>), grid, dim3(256), 0, s, a);
         return true;
     } else {
         return false;
@@ -811,9 +883,9 @@ bool launch_collect_lds_nk(mrc_ctx* ctx, bool pers, const ScanArgs& a, dim3 grid
 }
 
 // false: no instantiation for this shape (the caller uses k_query_scan)
-template <int PREC, int G>
+template <int PREC, int G, int MODE = MODE_COLLECT>
 bool launch_collect_lds(mrc_ctx* ctx, bool pers, int nk, const ScanArgs& a, dim3 grid, hipStream_t s) {
-#define MRC_Q(c) case c: return launch_collect_lds_nk<PREC, G, c>(ctx, pers, a, grid, s);
+#define MRC_Q(c) case c: return launch_collect_lds_nk<PREC, G, c, MODE>(ctx, pers, a, grid, s);
     if constexpr (PREC == MRC_PREC_FP32) {
         switch (nk) { MRC_Q(2) MRC_Q(4) MRC_Q(6) MRC_Q(8) MRC_Q(12) MRC_Q(16) default: return false; }
     } else if constexpr (PREC == MRC_PREC_BF16) {
@@ -937,19 +1009,63 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         return dim3(gx, (unsigned)groups);
     };
     ScopedTimer tm(ctx, "query", s);
-    // pass 1: each query's 16 best rows of a prefix of the database (a lower
-    // bound for the whole: any 16 rows' smallest exact score is at most the
-    // exact 16th best), their exact scores, and the collection threshold
+    // pass 1: 16 high-scoring rows of a prefix of the database for each
+    // query (its 16 best for small batches; for large ones the 16 best of the
+    // per-stream maxima, which are distinct rows and nearly the same set),
+    // their exact scores (a lower bound for the whole: any 16 rows' smallest
+    // exact score is at most the exact 16th best), and the collection threshold
     // thr = min(E16 - delta, tau - delta) (delta = 0 for FP32 scores, which
     // are the chain itself). FP8's band is wide: its first pass takes the
     // whole database, so that E16 is as high as it can be
     const int64_t sample = precision == MRC_PREC_FP8
                                ? rows
                                : std::min<int64_t>(rows, std::max<int64_t>(kPrefixMin, ceil_div(rows, 16)));
+    // G query groups per wavefront in the collection (and the LDS-shared
+    // first pass): as many as the batch fills and 128 registers hold
+    int g = nq <= 16 ? 1 : nq <= 48 ? 2 : 4;
+    while (g > 1 && g * nk * lane_regs > 128) g /= 2;
+    // batches above 64 queries: the LDS-shared forms (64 g queries per
+    // workgroup, all four wavefronts on the same tiles) where they are built
+    const bool lds_form = nq > 64;
+    auto lds_launch = [&](int mode, bool pers, dim3 grid) {
+        if (fp32)
+            return mode == MODE_TOP
+                       ? (g == 4 ? launch_collect_lds<MRC_PREC_FP32, 4, MODE_TOP>(ctx, pers, nk, a, grid, s)
+                          : g == 2 ? launch_collect_lds<MRC_PREC_FP32, 2, MODE_TOP>(ctx, pers, nk, a, grid, s)
+                                   : launch_collect_lds<MRC_PREC_FP32, 1, MODE_TOP>(ctx, pers, nk, a, grid, s))
+                       : (g == 4 ? launch_collect_lds<MRC_PREC_FP32, 4>(ctx, pers, nk, a, grid, s)
+                          : g == 2 ? launch_collect_lds<MRC_PREC_FP32, 2>(ctx, pers, nk, a, grid, s)
+                                   : launch_collect_lds<MRC_PREC_FP32, 1>(ctx, pers, nk, a, grid, s));
+        if (bf)
+            return mode == MODE_TOP
+                       ? (g == 4 ? launch_collect_lds<MRC_PREC_BF16, 4, MODE_TOP>(ctx, pers, nk, a, grid, s)
+                          : g == 2 ? launch_collect_lds<MRC_PREC_BF16, 2, MODE_TOP>(ctx, pers, nk, a, grid, s)
+                                   : launch_collect_lds<MRC_PREC_BF16, 1, MODE_TOP>(ctx, pers, nk, a, grid, s))
+                       : (g == 4 ? launch_collect_lds<MRC_PREC_BF16, 4>(ctx, pers, nk, a, grid, s)
+                          : g == 2 ? launch_collect_lds<MRC_PREC_BF16, 2>(ctx, pers, nk, a, grid, s)
+                                   : launch_collect_lds<MRC_PREC_BF16, 1>(ctx, pers, nk, a, grid, s));
+        return mode == MODE_TOP
+                   ? (g == 4 ? launch_collect_lds<MRC_PREC_FP8, 4, MODE_TOP>(ctx, pers, nk, a, grid, s)
+                      : g == 2 ? launch_collect_lds<MRC_PREC_FP8, 2, MODE_TOP>(ctx, pers, nk, a, grid, s)
+                               : launch_collect_lds<MRC_PREC_FP8, 1, MODE_TOP>(ctx, pers, nk, a, grid, s))
+                   : (g == 4 ? launch_collect_lds<MRC_PREC_FP8, 4>(ctx, pers, nk, a, grid, s)
+                      : g == 2 ? launch_collect_lds<MRC_PREC_FP8, 2>(ctx, pers, nk, a, grid, s)
+                               : launch_collect_lds<MRC_PREC_FP8, 1>(ctx, pers, nk, a, grid, s));
+    };
+    auto lds_grid = [&](int64_t r) {
+        const int64_t tiles = std::max<int64_t>(1, ceil_div(r, kTileRows));
+        const int64_t groups = ceil_div(nq, 64 * g);
+        return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), tiles)), (unsigned)groups);
+    };
+    // the first pass's partial entries per query: top lists of kTop per
+    // workgroup (k_query_scan), or one stream maximum per lane group and
+    // workgroup (the LDS-shared form: 4 gx streams, each over distinct rows)
     const dim3 g1 = grid_for_rows(sample, ceil_div(nq, 16));
+    const dim3 g1l = lds_grid(sample);
+    const int64_t per_q = std::max<int64_t>((int64_t)g1.x * kTop, (int64_t)g1l.x * 4);
     void *ps, *pi, *l16, *thr, *delta, *cand, *cc, *mtop;
-    MRC_TRY(scratch(ctx, "q_part_s", (size_t)nq * g1.x * kTop * 4, &ps));
-    MRC_TRY(scratch(ctx, "q_part_id", (size_t)nq * g1.x * kTop * 4, &pi));
+    MRC_TRY(scratch(ctx, "q_part_s", (size_t)nq * per_q * 4, &ps));
+    MRC_TRY(scratch(ctx, "q_part_id", (size_t)nq * per_q * 4, &pi));
     MRC_TRY(scratch(ctx, "q_l16", (size_t)nq * 4, &l16));
     MRC_TRY(scratch(ctx, "q_thr", (size_t)nq * 4, &thr));
     MRC_TRY(scratch(ctx, "q_delta", 256, &delta));
@@ -957,15 +1073,24 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     a.rows = sample;
     a.part_s = (float*)ps;
     a.part_id = (int32_t*)pi;
-    MRC_TRY(scan(MODE_TOP, 1, g1));
+    int64_t entries = (int64_t)g1.x * kTop;
+    if (lds_form && lds_launch(MODE_TOP, false, g1l)) {
+        MRC_HIP_TRY(ctx, hipGetLastError());
+        entries = (int64_t)g1l.x * 4;
+    } else {
+        MRC_TRY(scan(MODE_TOP, 1, g1));
+    }
     hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
-                       (const int32_t*)pi, (int)g1.x, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
+                       (const int32_t*)pi, entries, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
                        (int32_t*)nullptr, (float*)nullptr);
     if (fp32) {
         MRC_TRY(clear_words(ctx, (int64_t*)delta, 1, s));
     } else {
         const float* q_err = (const float*)qerr + (bf ? 0 : nq_pad);
-        hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db->d_errmax + (bf ? 0 : 1), q_err, nq, 0.02f,
+        // (no nominal floor under the bound: every candidate is rescored
+        // exactly, so the band only has to keep each row whose exact score
+        // reaches the threshold)
+        hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db->d_errmax + (bf ? 0 : 1), q_err, nq, 0.f,
                            lowp_acc_unit(precision, k), (float*)delta);
     }
     hipLaunchKernelGGL(k_query_e16, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const mrc_hit*)mtop, (int)nq,
@@ -975,18 +1100,8 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     MRC_HIP_TRY(ctx, hipGetLastError());
     // pass 2: every row at or above the threshold, G query groups per
     // wavefront, then exact decisions; grow the per-query capacity on overflow
-    int g = nq <= 16 ? 1 : nq <= 48 ? 2 : 4;
-    while (g > 1 && g * nk * lane_regs > 128) g /= 2;
     a.rows = rows;
-    // batches above 64 queries: the LDS-shared form (64 g queries per
-    // workgroup, all four wavefronts on the same tiles) where it is built
-    const bool lds_form = nq > 64;
-    dim3 g2 = grid_for_rows(rows, ceil_div(nq, 16 * g));
-    if (lds_form) {
-        const int64_t tiles = std::max<int64_t>(1, ceil_div(rows, kTileRows));
-        const int64_t groups = ceil_div(nq, 64 * g);
-        g2 = dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(2048, groups), tiles)), (unsigned)groups);
-    }
+    const dim3 g2 = lds_form ? lds_grid(rows) : grid_for_rows(rows, ceil_div(nq, 16 * g));
     // persistent form: items of kPersistTiles tiles per query block, taken
     // from a counter in context scratch (cleared by a fill kernel per launch)
     const bool pers = ctx->scan_form == MRC_SCAN_PERSISTENT;
@@ -998,17 +1113,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         if (pers) MRC_TRY(clear_words(ctx, (int64_t*)work, 1, s));
         if (lds_form) {
             a.n_items = ceil_div(nq, 64 * g) * a.tile_ranges;
-            bool ok;
-            if (fp32) ok = g == 4 ? launch_collect_lds<MRC_PREC_FP32, 4>(ctx, pers, nk, a, g2, s)
-                         : g == 2 ? launch_collect_lds<MRC_PREC_FP32, 2>(ctx, pers, nk, a, g2, s)
-                                  : launch_collect_lds<MRC_PREC_FP32, 1>(ctx, pers, nk, a, g2, s);
-            else if (bf) ok = g == 4 ? launch_collect_lds<MRC_PREC_BF16, 4>(ctx, pers, nk, a, g2, s)
-                            : g == 2 ? launch_collect_lds<MRC_PREC_BF16, 2>(ctx, pers, nk, a, g2, s)
-                                     : launch_collect_lds<MRC_PREC_BF16, 1>(ctx, pers, nk, a, g2, s);
-            else ok = g == 4 ? launch_collect_lds<MRC_PREC_FP8, 4>(ctx, pers, nk, a, g2, s)
-                    : g == 2 ? launch_collect_lds<MRC_PREC_FP8, 2>(ctx, pers, nk, a, g2, s)
-                             : launch_collect_lds<MRC_PREC_FP8, 1>(ctx, pers, nk, a, g2, s);
-            if (ok) {
+            if (lds_launch(MODE_COLLECT, pers, g2)) {
                 MRC_HIP_TRY(ctx, hipGetLastError());
                 return MRC_OK;
             }
