@@ -63,6 +63,7 @@ struct mrc_ctx {
     std::mutex mu;               // guards `used` (databases may be touched by server threads)
     int tile_order_nb = -1;      // the band table in scratch "tile_order" is for this many tile rows
     int scan_form = 0;           // MRC_SCAN_GRID or MRC_SCAN_PERSISTENT (query collection)
+    int query_attempts = 0;      // collection passes of the last mrc_query (above 1: capacity grew)
     void* model_spare = nullptr; // table block of the last destroyed model, kept for the next build
     size_t model_spare_bytes = 0;
     // Models and databases hold their context: destroyed while any of them

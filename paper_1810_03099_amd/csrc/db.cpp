@@ -295,7 +295,10 @@ mrc_status mrc_query(mrc_ctx* ctx, const mrc_db* db, const mrc_model* model, con
     L.add("topk", (int64_t)topk);
     L.add("precision", (int64_t)precision);
     L.add("scan", (int64_t)(ctx ? ctx->scan_form : -1));
-    return L.done(query_impl(ctx, db, model, q, topk, tau, precision, topk_out, n_hits, hip_stream));
+    if (ctx) ctx->query_attempts = 0;
+    const mrc_status st = query_impl(ctx, db, model, q, topk, tau, precision, topk_out, n_hits, hip_stream);
+    L.add("collect_attempts", (int64_t)(ctx ? ctx->query_attempts : -1));
+    return L.done(st);
 }
 
 }  // extern "C"

@@ -340,6 +340,7 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
 // Long documents (the last length class of k_validate_offsets): a [V]
 // uint32 count table per workgroup in global memory (all zero between
 // documents).
+constexpr int kLongUnroll = 8;
 template <int MODE>
 __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off, int32_t V,
                                                        const int32_t* __restrict__ tok, PassArgs a,
@@ -362,16 +363,32 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
         const int64_t d = list[item];
         const int64_t o = off[d];
         const int64_t L = off[d + 1] - o;
-        for (int64_t p = tid; p < L; p += kBlock) {
-            const int t = tok[o + p];
-            if ((unsigned)t >= (unsigned)V) {
-                atomicOr(err, kErrToken);
-                continue;
+        // kLongUnroll tokens per thread and round: their loads, then their
+        // term-table loads, then their atomics (one memory latency per round
+        // rather than two per token)
+        for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kBlock * kLongUnroll) {
+            int t[kLongUnroll];
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                const int64_t p = p0 + (int64_t)u * kBlock;
+                t[u] = p < L ? tok[o + p] : -1;
+                if (p < L && (unsigned)t[u] >= (unsigned)V) {
+                    atomicOr(err, kErrToken);
+                    t[u] = -1;
+                }
             }
-            atomicAdd(&cnt[t], 1u);
+            TermInfo ti[kLongUnroll];
             if constexpr (MODE == MODE_SIGN) {
-                const TermInfo ti = a.tinfo[t];
-                if (ti.part >= 0) atomicAdd(&bins[ti.part], mrc_dev::fixed32(ref_coef(a, ti.idf)));
+#pragma unroll
+                for (int u = 0; u < kLongUnroll; ++u) ti[u] = t[u] >= 0 ? a.tinfo[t[u]] : TermInfo{0.f, -1};
+            }
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                if (t[u] < 0) continue;
+                atomicAdd(&cnt[t[u]], 1u);
+                if constexpr (MODE == MODE_SIGN) {
+                    if (ti[u].part >= 0) atomicAdd(&bins[ti[u].part], mrc_dev::fixed32(ref_coef(a, ti[u].idf)));
+                }
             }
         }
         __threadfence();
@@ -379,11 +396,24 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
         double nrm = 0.0;
         if constexpr (MODE != MODE_COUNT) {
             u128 acc = 0;
-            for (int64_t p = tid; p < L; p += kBlock) {
-                const int t = tok[o + p];
-                if ((unsigned)t >= (unsigned)V) continue;
-                const unsigned tf = __hip_atomic_load(&cnt[t], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                acc += occ_sq_fixed(tf, a.tinfo[t].idf);
+            for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kBlock * kLongUnroll) {
+                int t[kLongUnroll];
+#pragma unroll
+                for (int u = 0; u < kLongUnroll; ++u) {
+                    const int64_t p = p0 + (int64_t)u * kBlock;
+                    t[u] = p < L ? tok[o + p] : -1;
+                    if ((unsigned)t[u] >= (unsigned)V) t[u] = -1;
+                }
+                unsigned tf[kLongUnroll];
+                float idf[kLongUnroll];
+#pragma unroll
+                for (int u = 0; u < kLongUnroll; ++u) {
+                    tf[u] = t[u] >= 0 ? __hip_atomic_load(&cnt[t[u]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+                    idf[u] = t[u] >= 0 ? a.tinfo[t[u]].idf : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < kLongUnroll; ++u)
+                    if (t[u] >= 0) acc += occ_sq_fixed(tf[u], idf[u]);
             }
             nrm = norm_from_fixed(team_sum<kBlock>(acc, red));
         }
@@ -413,10 +443,16 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
             }
         }
         __syncthreads();
-        for (int64_t p = tid; p < L; p += kBlock) {
-            const int t = tok[o + p];
-            if ((unsigned)t >= (unsigned)V) continue;
-            __hip_atomic_store(&cnt[t], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kBlock * kLongUnroll) {
+            int t[kLongUnroll];
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u) {
+                const int64_t p = p0 + (int64_t)u * kBlock;
+                t[u] = p < L ? tok[o + p] : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u)
+                if ((unsigned)t[u] < (unsigned)V) __hip_atomic_store(&cnt[t[u]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
         __threadfence();

@@ -8,16 +8,17 @@
 // whose A operand is 64 database rows, so lane (li, lg) of a wavefront holds
 // the scores of query li against 16 of the 64 rows.
 //
-// Two passes. The first gives each query its 16 best rows of a prefix of the
-// database (every lane keeps a private top-16 list in registers while the
-// wavefront streams its share of the prefix; lists are merged per workgroup
-// in LDS, then per query) and E16, the smallest exact (chain) score among
-// those rows: the exact 16th best over all rows is at least E16. The second
-// pass collects every row whose score is >= min(E16 - delta, tau - delta)
-// (delta: the largest rescoring band of the BF16/FP8 codes, 0 for FP32 scores,
-// which are the plain chain itself), with up to 4 query groups per wavefront
-// sharing each database fragment; the candidates, a superset of the exact
-// top-16 and of all rows >= tau, are then scored with the FP32 chain.
+// Two passes. The first finds, for each query, 16 high-scoring rows of a
+// prefix of the database: every lane keeps the best row of its own stream
+// (its lane group's rows of its wavefront's tiles), and the 16 best of these
+// stream maxima per query (distinct rows, nearly always the prefix's own 16
+// best) give E16, the smallest exact (chain) score among them: the exact
+// 16th best over all rows is at least E16. The second pass collects every row
+// whose score is >= min(E16 - b, tau - b) (b: the query's rescoring band
+// against the database's BF16/FP8 codes, 0 for FP32 scores, which are the
+// plain chain itself), with up to 4 query groups per wavefront sharing each
+// database fragment; the candidates, a superset of the exact top-16 and of
+// all rows >= tau, are then scored with the FP32 chain.
 #include <algorithm>
 
 #include "common.h"
@@ -122,6 +123,88 @@ __device__ __forceinline__ uint32_t tile_rowmask(int64_t rows_left, int lg) {
     return m;
 }
 
+// One step of an all-lanes (score, id) reduction: each lane compares with
+// the lane a DPP pattern names (within its row of 16) and keeps the better.
+template <int CTRL>
+__device__ __forceinline__ void best_step(float& v, int& id) {
+    const float ov = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xf, 0xf, true));
+    const int oi = __builtin_amdgcn_mov_dpp(id, CTRL, 0xf, 0xf, true);
+    if (better(ov, oi, v, id)) {
+        v = ov;
+        id = oi;
+    }
+}
+
+// The best (score, id) of the wavefront, returned in every lane: within each
+// row of 16 lanes by DPP (quad lanes xor 1, xor 2, then rotations of the row
+// by 4 and by 8: every lane then holds its row's best), then the four rows'
+// bests read from lanes 0, 16, 32, 48 (no LDS round trips).
+__device__ __forceinline__ void wave_best(float& v, int& id) {
+    best_step<0xb1>(v, id);   // quad_perm [1, 0, 3, 2]
+    best_step<0x4e>(v, id);   // quad_perm [2, 3, 0, 1]
+    best_step<0x124>(v, id);  // row_ror:4
+    best_step<0x128>(v, id);  // row_ror:8
+    float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    int bi = __builtin_amdgcn_readlane(id, 0);
+#pragma unroll
+    for (int r = 1; r < 4; ++r) {
+        const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16 * r));
+        const int ci = __builtin_amdgcn_readlane(id, 16 * r);
+        if (better(c, ci, b, bi)) {
+            b = c;
+            bi = ci;
+        }
+    }
+    v = b;
+    id = bi;
+}
+
+// The best topk (score, id) pairs of a workgroup's 256 lists (one sorted
+// list per thread; id 0x7fffffff marks an empty entry): each wavefront takes
+// the best topk of its 64 lists (repeatedly the best head across lanes) into
+// LDS (ss, si: 4 kTop entries each), then wavefront 0 takes the best topk of
+// those four and hands entry p to emit(p, score, id) on its lane 0. Every
+// thread of the workgroup calls it (it holds a workgroup barrier).
+template <typename Emit>
+__device__ __forceinline__ void block_top(const float (&ts)[kTop], const int (&ti)[kTop], int topk, float* ss,
+                                          int* si, Emit emit) {
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int h = 0;
+    for (int p = 0; p < topk; ++p) {
+        float hs = -INFINITY;
+        int hi = 0x7fffffff;
+#pragma unroll
+        for (int x = 0; x < kTop; ++x)
+            if (x == h) {
+                hs = ts[x];
+                hi = ti[x];
+            }
+        float bs = hs;
+        int bi = hi;
+        wave_best(bs, bi);
+        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;  // ids are unique: one lane pops
+        if (lane == 0) {
+            ss[w * kTop + p] = bs;
+            si[w * kTop + p] = bi;
+        }
+    }
+    __syncthreads();
+    if (w != 0) return;
+    const int src = (lane >> 4) * kTop + (lane & 15);  // lane: entry (lane & 15) of wavefront lane >> 4
+    float v = (lane & 15) < topk ? ss[src] : -INFINITY;
+    int id = (lane & 15) < topk ? si[src] : 0x7fffffff;
+    for (int p = 0; p < topk; ++p) {
+        float bs = v;
+        int bi = id;
+        wave_best(bs, bi);
+        if (bi != 0x7fffffff && id == bi && v == bs) {  // (ids are unique: one lane)
+            v = -INFINITY;
+            id = 0x7fffffff;
+        }
+        if (lane == 0) emit(p, bs, bi);
+    }
+}
+
 struct ScanArgs {
     const uint8_t* db;        // [rows_pad][ld_db] codes (FP32: matrix-core layout floats)
     int ld_db;                // bytes per row
@@ -132,8 +215,9 @@ struct ScanArgs {
     const float* q_scale;
     int nq;
     float tau;
-    // MODE_TOP: per-workgroup top lists
-    float* part_s;            // [nq][gx][kTop]
+    // MODE_TOP: each query's stream maxima, [nq][streams] (16 per workgroup
+    // of k_query_scan, 4 per workgroup of the LDS-shared kernel)
+    float* part_s;
     int32_t* part_id;
     // MODE_COLLECT: candidates with score >= thr[q]
     const float* thr;
@@ -195,8 +279,6 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     using T = QT<PREC>;
     static_assert(MODE == MODE_COLLECT || G == 1, "top lists for one query group per wavefront");
     static_assert(!PERS || MODE == MODE_COLLECT, "the persistent form collects");
-    __shared__ float ls[256][kTop];    // 16 lists per query: 4 wavefronts x 4 lane groups
-    __shared__ int lid[256][kTop];
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int li = lane & 15, lg = lane >> 4;
@@ -235,13 +317,10 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     };
     int64_t cur_y = PERS ? -1 : (int64_t)blockIdx.y;
     if (!PERS) load_queries(cur_y);
-    float ts[kTop];
-    int tid_[kTop];
-#pragma unroll
-    for (int p = 0; p < kTop; ++p) {
-        ts[p] = -INFINITY;
-        tid_[p] = 0x7fffffff;
-    }
+    // MODE_TOP: the best (score, row) of the lane's stream of rows (lane
+    // group lg of this wavefront's tiles, ascending)
+    float bv = -INFINITY;
+    int bi = 0x7fffffff;
     const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
     // grid form: this wavefront's tiles t0, t0 + stride, ...; persistent form:
     // each wavefront takes items (query block, kPersistTiles tiles) from the
@@ -306,22 +385,25 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
             }
         }
         if constexpr (MODE == MODE_TOP) {
-            // the lane's largest score decides whether any of its 16 can
-            // matter: below the list's last entry the tile changes nothing
-            float mx = -INFINITY;
+            const int64_t rows_left = a.rows - row0;
+            if (rows_left < kTileRows) {  // the last tile: rows past the end take no part
 #pragma unroll
-            for (int x = 0; x < 4; ++x)
-                mx = fmaxf(mx, fmaxf(fmaxf(acc[0][x][0], acc[0][x][1]), fmaxf(acc[0][x][2], acc[0][x][3])));
-            if (!(mx < ts[kTop - 1] || !qvalid[0])) {
+                for (int e = 0; e < 16; ++e)
+                    if (16 * (e >> 2) + 4 * lg + (e & 3) >= rows_left) acc[0][e >> 2][e & 3] = -INFINITY;
+            }
+            float tv = -INFINITY;  // the tile's best of the lane's 16 (the first of equals)
+            int te = 0;
 #pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int64_t row = row0 + 16 * x + 4 * lg + r;
-                        const float v = acc[0][x][r];
-                        if (row < a.rows && better(v, (int)row, ts[kTop - 1], tid_[kTop - 1]))
-                            top_insert(ts, tid_, v, (int)row);
-                    }
+            for (int e = 0; e < 16; ++e) {
+                const float v = acc[0][e >> 2][e & 3];
+                if (v > tv) {
+                    tv = v;
+                    te = e;
+                }
+            }
+            if (tv > bv) {
+                bv = tv;
+                bi = (int)row0 + 16 * (te >> 2) + 4 * lg + (te & 3);
             }
         } else {
             uint32_t m[G];
@@ -340,156 +422,145 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
         write_marks(a, pm, q, pb, prow0, lg);
         return;
     }
-    // workgroup merge: 16 lists (4 wavefronts x 4 lane groups) per query
-#pragma unroll
-    for (int p = 0; p < kTop; ++p) {
-        ls[li * 16 + wave * 4 + lg][p] = ts[p];
-        lid[li * 16 + wave * 4 + lg][p] = tid_[p];
-    }
-    __syncthreads();
-    if (threadIdx.x < 16) {
-        const int qq = blockIdx.y * 16 + threadIdx.x;
-        if (qq < a.nq) {
-            int head[16];
-#pragma unroll
-            for (int l = 0; l < 16; ++l) head[l] = 0;
-            float* os = a.part_s + ((int64_t)qq * gridDim.x + blockIdx.x) * kTop;
-            int32_t* oi = a.part_id + ((int64_t)qq * gridDim.x + blockIdx.x) * kTop;
-            for (int p = 0; p < kTop; ++p) {
-                int bl = 0;
-                float bs = -INFINITY;
-                int bidx = 0x7fffffff;
-                for (int l = 0; l < 16; ++l) {
-                    if (head[l] < kTop) {
-                        const float sv = ls[threadIdx.x * 16 + l][head[l]];
-                        const int id = lid[threadIdx.x * 16 + l][head[l]];
-                        if (better(sv, id, bs, bidx)) {
-                            bs = sv;
-                            bidx = id;
-                            bl = l;
-                        }
-                    }
-                }
-                os[p] = bs;
-                oi[p] = bidx;
-                head[bl] += 1;
-            }
-        }
+    // stream (blockIdx.x * 4 + wave) * 4 + lg of each query: distinct rows in
+    // every stream, so any 16 stream maxima are 16 distinct rows
+    if (qvalid[0]) {
+        const int64_t o = (int64_t)q[0] * ((int64_t)gridDim.x * 16) + (blockIdx.x * 4 + wave) * 4 + lg;
+        a.part_s[o] = bv;
+        a.part_id[o] = bi;
     }
 }
 
-// Per query: the best topk of its `total` partial entries (workgroup lists,
-// or stream maxima), one wavefront per query; each lane first reduces its
-// share of the entries.
+// Per query: topk high-scoring rows of its `total` stream maxima, one
+// workgroup per query: each thread takes the best of its share (the maximum
+// of a coarser stream), then block_top picks the best topk of those 256
+// (distinct rows, as any set of stream maxima).
 __global__ __launch_bounds__(256) void k_query_merge(const float* __restrict__ part_s, const int32_t* __restrict__ part_id,
-                                                     int64_t total, int nq, int topk, const int32_t* __restrict__ hits,
-                                                     mrc_hit* __restrict__ out, int32_t* __restrict__ n_hits,
-                                                     float* __restrict__ l16) {
-    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (q >= nq) return;
+                                                     int64_t total, int topk, mrc_hit* __restrict__ out) {
+    __shared__ float ss[4 * kTop];
+    __shared__ int si[4 * kTop];
+    const int q = blockIdx.x;
+    float bv = -INFINITY;
+    int bi = 0x7fffffff;
+    for (int64_t e0 = threadIdx.x; e0 < total; e0 += 256 * 8) {  // 8 entries per round trip
+        float v[8];
+        int id[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = e0 + 256 * u;
+            v[u] = e < total ? part_s[(int64_t)q * total + e] : -INFINITY;
+            id[u] = e < total ? part_id[(int64_t)q * total + e] : 0x7fffffff;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (id[u] != 0x7fffffff && better(v[u], id[u], bv, bi)) {
+                bv = v[u];
+                bi = id[u];
+            }
+    }
     float ts[kTop];
     int ti[kTop];
 #pragma unroll
     for (int p = 0; p < kTop; ++p) {
-        ts[p] = -INFINITY;
-        ti[p] = 0x7fffffff;
+        ts[p] = p == 0 ? bv : -INFINITY;
+        ti[p] = p == 0 ? bi : 0x7fffffff;
     }
-    for (int64_t e = lane; e < total; e += 64) {
-        const float v = part_s[(int64_t)q * total + e];
-        const int id = part_id[(int64_t)q * total + e];
-        if (id != 0x7fffffff && better(v, id, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, v, id);
-    }
-    // wavefront merge: repeatedly take the best head across lanes
-    int h = 0;
-    for (int p = 0; p < kTop; ++p) {
-        float hs = -INFINITY;
-        int hi = 0x7fffffff;
-#pragma unroll
-        for (int x = 0; x < kTop; ++x)
-            if (x == h) {
-                hs = ts[x];
-                hi = ti[x];
-            }
-        float bs = hs;
-        int bi = hi;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float os = __shfl_xor(bs, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (better(os, oi, bs, bi)) {
-                bs = os;
-                bi = oi;
-            }
-        }
-        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;   // ids are unique: one lane pops
-        if (lane == 0) {
-            if (p < topk) {
-                out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
-                out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
-                out[(int64_t)q * topk + p].flags = 0;
-            }
-            if (l16 && p == kTop - 1) l16[q] = bs;
-        }
-    }
-    if (lane == 0 && n_hits && hits) n_hits[q] = hits[q];
+    block_top(ts, ti, topk, ss, si, [&](int p, float bs, int b) {
+        out[(int64_t)q * topk + p].id = b == 0x7fffffff ? -1 : b;
+        out[(int64_t)q * topk + p].s = b == 0x7fffffff ? 0.f : bs;
+        out[(int64_t)q * topk + p].flags = 0;
+    });
 }
 
-// thr[q] = min(E16[q] - delta, tau - delta)
-__global__ void k_query_thr(const float* __restrict__ e16, int nq, float tau, const float* __restrict__ delta,
-                            float* __restrict__ thr) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nq) return;
-    const float d = *delta;
-    thr[q] = fminf(e16[q] - d, tau - d);
-}
 
-// The plain FP32 chain acc = fmaf(q_c, r_c, acc), c = 0..k-1, of a
-// natural-order query row and a database row in the matrix-core layout (each
-// 16-component block stored with its 4x4 sub-blocks transposed): a block is
-// read as four 16-byte loads, then consumed in component order.
-__device__ __forceinline__ float chain_score(const float* __restrict__ qu, const float* __restrict__ dr, int k) {
+// The plain FP32 chain acc = fmaf(q_c, r_c, acc), c = 0..kp-1, of a query
+// held in LDS in natural order (zero past k) and a database row in the
+// matrix-core layout (each 16-component block stored with its 4x4 sub-blocks
+// transposed; zero past k): fmaf(0, 0, acc) is acc, so this is the chain
+// over k. nb = kp / 16 blocks (even); a lane reads four row blocks per round
+// trip (16-byte loads) and the matching query blocks from LDS (the same
+// address in every lane), then consumes them in component order.
+__device__ __forceinline__ float chain_blocks(const f32x4* qs, const f32x4* __restrict__ dr, int nb) {
     float acc = 0.f;
-    for (int c0 = 0; c0 < k; c0 += 16) {
-        f32x4 blk[4];
+    int b = 0;
+    for (; b + 4 <= nb; b += 4) {
+        f32x4 blk[16];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) blk[j] = *(const f32x4*)(dr + c0 + 4 * j);
-        const int m = min(16, k - c0);
+        for (int j = 0; j < 16; ++j) blk[j] = dr[4 * b + j];
 #pragma unroll
-        for (int c = 0; c < 16; ++c)
-            if (c < m) acc = __builtin_fmaf(qu[c0 + c], blk[c & 3][c >> 2], acc);
+        for (int h = 0; h < 4; ++h) {
+            f32x4 qv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qv[j] = qs[4 * (b + h) + j];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc = __builtin_fmaf(qv[c >> 2][c & 3], blk[4 * h + (c & 3)][c >> 2], acc);
+        }
+    }
+    if (b < nb) {  // the last two blocks
+        f32x4 blk[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) blk[j] = dr[4 * b + j];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            f32x4 qv[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) qv[j] = qs[4 * (b + h) + j];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) acc = __builtin_fmaf(qv[c >> 2][c & 3], blk[4 * h + (c & 3)][c >> 2], acc);
+        }
     }
     return acc;
 }
 
-// E16[q]: the exact (chain) score of the 16th best of the query's 16 best rows
-// by the low-precision score (-inf with fewer than 16 rows). The exact 16th
-// best over all rows is at least this, so a row can only enter the exact
-// top 16 if its low-precision score is >= E16 - delta.
+// Per query (one wavefront each): E16 = the smallest exact score of the 16
+// first-pass rows (a row id of -1: fewer than 16 rows, E16 = -inf), the band
+// b = e_q + e_db + e_q e_db + a (1 + e_q)(1 + e_db) + 2^-20 of the query's
+// low-precision error e_q against the database rows' largest e_db (none for
+// FP32 scores, which are the chain itself: db_err is NULL), and the
+// collection threshold thr = min(E16 - b, tau - b). It also zeroes the
+// query's candidate count, and block 0 the capacity signal and the
+// persistent collection's work counter (when given), so the collection
+// needs no clearing launches of its own.
 __global__ __launch_bounds__(256) void k_query_e16(const mrc_hit* __restrict__ lp_top, int nq,
                                                    const float* __restrict__ qunit, int k,
-                                                   const float* __restrict__ db_umfma, int kp,
-                                                   float* __restrict__ e16) {
-    const int q = blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (q >= nq) return;
+                                                   const float* __restrict__ db_umfma, int kp, float tau,
+                                                   const float* __restrict__ db_err, const float* __restrict__ q_err,
+                                                   float acc_unit, float* __restrict__ thr,
+                                                   int32_t* __restrict__ ccount, unsigned long long* __restrict__ cap_word,
+                                                   unsigned long long* __restrict__ work) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        *cap_word = 0ull;
+        if (work) *work = 0ull;
+    }
+    __shared__ f32x4 qs[4][256];  // each wavefront's query, kp <= 1024 components
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + w;
+    if (q >= nq) return;  // (no workgroup barrier below: each wavefront on its own)
+    float* qf = (float*)qs[w];
+    for (int c = lane; c < kp; c += 64) qf[c] = c < k ? qunit[(int64_t)q * k + c] : 0.f;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     float v = INFINITY;
     if (lane < kTop) {
         const int64_t row = lp_top[(int64_t)q * kTop + lane].id;
-        v = row < 0 ? -INFINITY : chain_score(qunit + (int64_t)q * k, db_umfma + row * kp, k);
+        v = row < 0 ? -INFINITY : chain_blocks(qs[w], (const f32x4*)(db_umfma + row * kp), kp / 16);
     }
     for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
-    if (lane == 0) e16[q] = v;
+    if (lane == 0) {
+        float b = 0.f;
+        if (db_err) {
+            const float ei = q_err[q], ej = *db_err;
+            b = ei + ej + ei * ej + acc_unit * (1.f + ei) * (1.f + ej) + 9.5367431640625e-07f;
+        }
+        thr[q] = fminf(v - b, tau - b);
+        ccount[q] = 0;
+    }
 }
 
 // Exact decisions for the collected candidates of each query (one workgroup
-// per query): the FP32 chain over the natural-order query unit vector and the
-// database row in matrix-core layout, then the top list and the hit count.
-// The query sits in LDS padded with zeros to the row's kp components (the
-// database rows are zero there too): fmaf(0, 0, acc) is acc, so the chain
-// over kp components has the bits of the chain over k. A lane reads four
-// 16-component blocks of its row per round trip (16-byte loads) and the
-// matching query blocks from LDS (the same address in every lane), then
-// consumes them in component order.
+// per query): the FP32 chain (chain_blocks) of the query and each candidate
+// row, then the top list (block_top) and the hit count.
 __global__ __launch_bounds__(256) void k_query_final(const int32_t* __restrict__ cand, const int32_t* __restrict__ ccount,
                                                      int cap, const float* __restrict__ qunit, int k,
                                                      const float* __restrict__ db_umfma, int kp, float tau, int topk,
@@ -517,117 +588,22 @@ __global__ __launch_bounds__(256) void k_query_final(const int32_t* __restrict__
         ti[p] = 0x7fffffff;
     }
     int hits = 0;
-    const int nb = kp / 16;  // (even: kp is a whole number of 32-component pairs)
     for (int e = threadIdx.x; e < nc; e += 256) {
         const int row = cand[(int64_t)q * cap + e];
-        const f32x4* dr = (const f32x4*)(db_umfma + (int64_t)row * kp);
-        float acc = 0.f;
-        int b = 0;
-        for (; b + 4 <= nb; b += 4) {
-            f32x4 blk[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) blk[j] = dr[4 * b + j];
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                f32x4 qv[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) qv[j] = qs[4 * (b + h) + j];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) acc = __builtin_fmaf(qv[c >> 2][c & 3], blk[4 * h + (c & 3)][c >> 2], acc);
-            }
-        }
-        if (b < nb) {  // the last two blocks
-            f32x4 blk[8];
-#pragma unroll
-            for (int j = 0; j < 8; ++j) blk[j] = dr[4 * b + j];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                f32x4 qv[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) qv[j] = qs[4 * (b + h) + j];
-#pragma unroll
-                for (int c = 0; c < 16; ++c) acc = __builtin_fmaf(qv[c >> 2][c & 3], blk[4 * h + (c & 3)][c >> 2], acc);
-            }
-        }
+        const float acc = chain_blocks(qs, (const f32x4*)(db_umfma + (int64_t)row * kp), kp / 16);
         hits += acc >= tau ? 1 : 0;
         if (better(acc, row, ts[kTop - 1], ti[kTop - 1])) top_insert(ts, ti, acc, row);
     }
-    // each wavefront's best topk of its 64 lists (repeatedly the best head
-    // across lanes), then the best topk of the four in wavefront 0
-    int h = 0;
-    for (int p = 0; p < topk; ++p) {
-        float hs = -INFINITY;
-        int hi = 0x7fffffff;
-#pragma unroll
-        for (int x = 0; x < kTop; ++x)
-            if (x == h) {
-                hs = ts[x];
-                hi = ti[x];
-            }
-        float bs = hs;
-        int bi = hi;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float os = __shfl_xor(bs, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (better(os, oi, bs, bi)) {
-                bs = os;
-                bi = oi;
-            }
-        }
-        if (bi != 0x7fffffff && hi == bi && hs == bs) ++h;  // ids are unique: one lane pops
-        if (lane == 0) {
-            ss[w * kTop + p] = bs;
-            si[w * kTop + p] = bi;
-        }
-    }
     hits = mrc_dev::wave_sum(hits);
     if (lane == 0) sh[w] = hits;
-    __syncthreads();
-    if (w != 0) return;
-    const int src = (lane >> 4) * kTop + (lane & 15);  // lane: entry (lane & 15) of wavefront lane >> 4
-    float v = (lane & 15) < topk ? ss[src] : -INFINITY;
-    int id = (lane & 15) < topk ? si[src] : 0x7fffffff;
-    for (int p = 0; p < topk; ++p) {
-        float bs = v;
-        int bi = id;
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float os = __shfl_xor(bs, off, 64);
-            const int oi = __shfl_xor(bi, off, 64);
-            if (better(os, oi, bs, bi)) {
-                bs = os;
-                bi = oi;
-            }
-        }
-        if (bi != 0x7fffffff && id == bi && v == bs) {  // (ids are unique: one lane)
-            v = -INFINITY;
-            id = 0x7fffffff;
-        }
-        if (lane == 0) {
-            out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
-            out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
-            out[(int64_t)q * topk + p].flags = flags;
-        }
-    }
-    if (lane == 0) n_hits[q] = sh[0] + sh[1] + sh[2] + sh[3];
+    block_top(ts, ti, topk, ss, si, [&](int p, float bs, int bi) {
+        out[(int64_t)q * topk + p].id = bi == 0x7fffffff ? -1 : bi;
+        out[(int64_t)q * topk + p].s = bi == 0x7fffffff ? 0.f : bs;
+        out[(int64_t)q * topk + p].flags = flags;
+    });
+    if (threadIdx.x == 0) n_hits[q] = sh[0] + sh[1] + sh[2] + sh[3];  // (written before block_top's barrier)
 }
 
-// delta = the largest rescoring band between the database rows (db_max: their
-// largest error bound, kept at insert) and the queries' rows e2[0..n2).
-__global__ void k_max_err(const float* __restrict__ db_max, const float* __restrict__ e2, int64_t n2,
-                          float nominal, float acc_unit, float* __restrict__ delta) {
-    __shared__ float red[16];
-    float m = *db_max;
-    for (int64_t i = threadIdx.x; i < n2; i += 1024) m = fmaxf(m, e2[i]);
-    m = mrc_dev::wave_max(m);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        float e = 0.f;
-        for (int w = 0; w < 16; ++w) e = fmaxf(e, red[w]);
-        const float b = e + e + e * e + acc_unit * (1.f + e) * (1.f + e) + 9.5367431640625e-07f;
-        delta[0] = fmaxf(nominal, b);
-    }
-}
 
 // Collection for large batches: the 4 wavefronts of a workgroup each hold G
 // query groups and read the same 64-row database tile from LDS, so a tile
@@ -1010,13 +986,12 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     };
     ScopedTimer tm(ctx, "query", s);
     // pass 1: 16 high-scoring rows of a prefix of the database for each
-    // query (its 16 best for small batches; for large ones the 16 best of the
-    // per-stream maxima, which are distinct rows and nearly the same set),
-    // their exact scores (a lower bound for the whole: any 16 rows' smallest
-    // exact score is at most the exact 16th best), and the collection threshold
-    // thr = min(E16 - delta, tau - delta) (delta = 0 for FP32 scores, which
-    // are the chain itself). FP8's band is wide: its first pass takes the
-    // whole database, so that E16 is as high as it can be
+    // query (the 16 best of the per-stream maxima: distinct rows, nearly
+    // always the prefix's own 16 best), their exact scores (a lower bound for
+    // the whole: any 16 rows' smallest exact score is at most the exact 16th
+    // best), and the collection threshold thr = min(E16 - b, tau - b) (b = 0
+    // for FP32 scores, which are the chain itself). FP8's band is wide: its
+    // first pass takes the whole database, so that E16 is as high as it can be
     const int64_t sample = precision == MRC_PREC_FP8
                                ? rows
                                : std::min<int64_t>(rows, std::max<int64_t>(kPrefixMin, ceil_div(rows, 16)));
@@ -1063,12 +1038,10 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     const dim3 g1 = grid_for_rows(sample, ceil_div(nq, 16));
     const dim3 g1l = lds_grid(sample);
     const int64_t per_q = std::max<int64_t>((int64_t)g1.x * kTop, (int64_t)g1l.x * 4);
-    void *ps, *pi, *l16, *thr, *delta, *cand, *cc, *mtop;
+    void *ps, *pi, *thr, *cand, *cc, *mtop;
     MRC_TRY(scratch(ctx, "q_part_s", (size_t)nq * per_q * 4, &ps));
     MRC_TRY(scratch(ctx, "q_part_id", (size_t)nq * per_q * 4, &pi));
-    MRC_TRY(scratch(ctx, "q_l16", (size_t)nq * 4, &l16));
     MRC_TRY(scratch(ctx, "q_thr", (size_t)nq * 4, &thr));
-    MRC_TRY(scratch(ctx, "q_delta", 256, &delta));
     MRC_TRY(scratch(ctx, "q_top_lp", (size_t)nq * kTop * sizeof(mrc_hit), &mtop));
     a.rows = sample;
     a.part_s = (float*)ps;
@@ -1080,37 +1053,31 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     } else {
         MRC_TRY(scan(MODE_TOP, 1, g1));
     }
-    hipLaunchKernelGGL(k_query_merge, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const float*)ps,
-                       (const int32_t*)pi, entries, (int)nq, kTop, (const int32_t*)nullptr, (mrc_hit*)mtop,
-                       (int32_t*)nullptr, (float*)nullptr);
-    if (fp32) {
-        MRC_TRY(clear_words(ctx, (int64_t*)delta, 1, s));
-    } else {
-        const float* q_err = (const float*)qerr + (bf ? 0 : nq_pad);
-        // (no nominal floor under the bound: every candidate is rescored
-        // exactly, so the band only has to keep each row whose exact score
-        // reaches the threshold)
-        hipLaunchKernelGGL(k_max_err, dim3(1), dim3(1024), 0, s, db->d_errmax + (bf ? 0 : 1), q_err, nq, 0.f,
-                           lowp_acc_unit(precision, k), (float*)delta);
-    }
+    hipLaunchKernelGGL(k_query_merge, dim3((unsigned)nq), dim3(256), 0, s, (const float*)ps, (const int32_t*)pi,
+                       entries, kTop, (mrc_hit*)mtop);
+    // (no nominal floor under the band: every candidate is rescored exactly,
+    // so the band only has to keep each row whose exact score reaches the
+    // threshold)
+    const bool pers = ctx->scan_form == MRC_SCAN_PERSISTENT;
+    void* work = nullptr;
+    if (pers) MRC_TRY(scratch(ctx, "q_work", 256, &work));
+    MRC_TRY(scratch(ctx, "q_ccount", (size_t)ceil_div(nq, 2) * 8, &cc));  // (whole words: cleared as such)
+    unsigned long long* cap_word = (unsigned long long*)(ctx->d_flags + kQueryCapWord);
     hipLaunchKernelGGL(k_query_e16, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const mrc_hit*)mtop, (int)nq,
-                       (const float*)unit, k, db->d_unit, L.kp, (float*)l16);
-    hipLaunchKernelGGL(k_query_thr, dim3((unsigned)ceil_div(nq, 256)), dim3(256), 0, s, (const float*)l16, (int)nq,
-                       tau, (const float*)delta, (float*)thr);
+                       (const float*)unit, k, db->d_unit, L.kp, tau,
+                       fp32 ? (const float*)nullptr : db->d_errmax + (bf ? 0 : 1),
+                       (const float*)qerr + (bf ? 0 : nq_pad), fp32 ? 0.f : lowp_acc_unit(precision, k), (float*)thr,
+                       (int32_t*)cc, cap_word, (unsigned long long*)work);
     MRC_HIP_TRY(ctx, hipGetLastError());
     // pass 2: every row at or above the threshold, G query groups per
     // wavefront, then exact decisions; grow the per-query capacity on overflow
     a.rows = rows;
     const dim3 g2 = lds_form ? lds_grid(rows) : grid_for_rows(rows, ceil_div(nq, 16 * g));
     // persistent form: items of kPersistTiles tiles per query block, taken
-    // from a counter in context scratch (cleared by a fill kernel per launch)
-    const bool pers = ctx->scan_form == MRC_SCAN_PERSISTENT;
-    void* work = nullptr;
-    if (pers) MRC_TRY(scratch(ctx, "q_work", 256, &work));
+    // from a counter in context scratch (zeroed before each collection)
     a.work = (unsigned long long*)work;
     a.tile_ranges = ceil_div(std::max<int64_t>(1, ceil_div(rows, kTileRows)), kPersistTiles);
     auto collect = [&]() -> mrc_status {
-        if (pers) MRC_TRY(clear_words(ctx, (int64_t*)work, 1, s));
         if (lds_form) {
             a.n_items = ceil_div(nq, 64 * g) * a.tile_ranges;
             if (lds_launch(MODE_COLLECT, pers, g2)) {
@@ -1126,9 +1093,11 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     if (it != ctx->scratch.end()) cap = std::max<int64_t>(cap, (int64_t)(it->second.second / 4 / nq));
     for (int attempt = 0; attempt < 3; ++attempt) {
         MRC_TRY(scratch(ctx, "q_cand", (size_t)nq * cap * 4, &cand));
-        MRC_TRY(scratch(ctx, "q_ccount", (size_t)nq * 4, &cc));
-        MRC_HIP_TRY(ctx, hipMemsetAsync(cc, 0, (size_t)nq * 4, s));
-        MRC_TRY(clear_words(ctx, ctx->d_flags + kQueryCapWord, 1, s));
+        if (attempt > 0) {  // (the first collection's counters were zeroed by k_query_e16)
+            MRC_TRY(clear_words(ctx, (int64_t*)cc, ceil_div(nq, 2), s));
+            MRC_TRY(clear_words(ctx, (int64_t*)cap_word, 1, s));
+            if (pers) MRC_TRY(clear_words(ctx, (int64_t*)work, 1, s));
+        }
         a.thr = (const float*)thr;
         a.cand = (int32_t*)cand;
         a.ccount = (int32_t*)cc;
@@ -1136,7 +1105,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         MRC_TRY(collect());
         hipLaunchKernelGGL(k_query_final, dim3((unsigned)nq), dim3(256), 0, s, (const int32_t*)cand,
                            (const int32_t*)cc, cap, (const float*)unit, k, db->d_unit, L.kp, tau, topk, topk_out,
-                           n_hits, fp32 ? 0 : 1, (unsigned long long*)(ctx->d_flags + kQueryCapWord));
+                           n_hits, fp32 ? 0 : 1, cap_word);
         MRC_HIP_TRY(ctx, hipGetLastError());
         // word 0 holds the signing pass's input errors (the scans ran on
         // whatever the early-returning document kernels left, in bounds);
@@ -1146,6 +1115,7 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
         MRC_HIP_TRY(ctx, hipStreamSynchronize(s));
         if (ctx->h_flags[0] & (kErrOffsets | kErrToken | kErrDocLen))
             return fail(MRC_E_INVAL, "mrc_query: malformed offsets, token ids or document lengths");
+        ctx->query_attempts = attempt + 1;
         if (!(ctx->h_flags[kQueryCapWord] & kErrQueryCap)) return MRC_OK;
         std::vector<int32_t> counts(nq);
         MRC_HIP_TRY(ctx, hipMemcpy(counts.data(), cc, (size_t)nq * 4, hipMemcpyDeviceToHost));

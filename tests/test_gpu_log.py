@@ -52,6 +52,7 @@ def test_log_levels_two_and_three(tmp_path):
     assert cmp_["flagged"] == flagged and cmp_["band_pairs"] == band
     assert "compare_lowp" in cmp_["stages"] and cmp_["stages"]["compare_lowp"]["ms"] > 0
     assert "sign_counts" in calls["mrc_build_and_sign"]["stages"]
+    assert calls["mrc_query"]["collect_attempts"] >= 1
     assert calls["mrc_build_and_sign"]["n_docs"] == 600
     batches = [x for x in lines if x["event"] == "serve_batch"]
     assert sum(x["docs"] for x in batches if x["kind"] == "query") == 20
