@@ -341,8 +341,9 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
 // uint32 count table per workgroup in global memory (all zero between
 // documents).
 constexpr int kLongUnroll = 8;
+constexpr int kLongThreads = 1024;  // a workgroup per long document: 16 wavefronts
 template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict__ off, int32_t V,
+__global__ __launch_bounds__(kLongThreads) void k_doc_global(const int64_t* __restrict__ off, int32_t V,
                                                        const int32_t* __restrict__ tok, PassArgs a,
                                                        uint32_t* __restrict__ tables,
                                                        unsigned long long* __restrict__ err,
@@ -352,11 +353,11 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
     unsigned long long* bins = (unsigned long long*)smem;
     const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
     u128* red = (u128*)(smem + (size_t)kpad * 8);
-    int* tcount = (int*)(red + 4);
+    int* tcount = (int*)(red + kLongThreads / 64);
     uint32_t* cnt = tables + (size_t)blockIdx.x * (size_t)V;
     const int tid = threadIdx.x;
     if (pass_disabled(err)) return;
-    for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
+    for (int j = tid; j < kpad; j += kLongThreads) bins[j] = 0ull;
     __syncthreads();
     const int64_t n_items = (int64_t)__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -366,11 +367,11 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
         // kLongUnroll tokens per thread and round: their loads, then their
         // term-table loads, then their atomics (one memory latency per round
         // rather than two per token)
-        for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kBlock * kLongUnroll) {
+        for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kLongThreads * kLongUnroll) {
             int t[kLongUnroll];
 #pragma unroll
             for (int u = 0; u < kLongUnroll; ++u) {
-                const int64_t p = p0 + (int64_t)u * kBlock;
+                const int64_t p = p0 + (int64_t)u * kLongThreads;
                 t[u] = p < L ? tok[o + p] : -1;
                 if (p < L && (unsigned)t[u] >= (unsigned)V) {
                     atomicOr(err, kErrToken);
@@ -396,11 +397,11 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
         double nrm = 0.0;
         if constexpr (MODE != MODE_COUNT) {
             u128 acc = 0;
-            for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kBlock * kLongUnroll) {
+            for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kLongThreads * kLongUnroll) {
                 int t[kLongUnroll];
 #pragma unroll
                 for (int u = 0; u < kLongUnroll; ++u) {
-                    const int64_t p = p0 + (int64_t)u * kBlock;
+                    const int64_t p = p0 + (int64_t)u * kLongThreads;
                     t[u] = p < L ? tok[o + p] : -1;
                     if ((unsigned)t[u] >= (unsigned)V) t[u] = -1;
                 }
@@ -415,15 +416,15 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
                 for (int u = 0; u < kLongUnroll; ++u)
                     if (t[u] >= 0) acc += occ_sq_fixed(tf[u], idf[u]);
             }
-            nrm = norm_from_fixed(team_sum<kBlock>(acc, red));
+            nrm = norm_from_fixed(team_sum<kLongThreads>(acc, red));
         }
         if constexpr (MODE == MODE_SIGN) {
-            write_signature(a, d, bins, nrm, tid, kBlock);
+            write_signature(a, d, bins, nrm, tid, kLongThreads);
         } else {
             // each distinct term once: the occurrence that swaps its count out emits it
             if (tid == 0) *tcount = 0;
             __syncthreads();
-            for (int64_t p = tid; p < L; p += kBlock) {
+            for (int64_t p = tid; p < L; p += kLongThreads) {
                 const int t = tok[o + p];
                 if ((unsigned)t >= (unsigned)V) continue;
                 const unsigned tf = atomicExch(&cnt[t], 0u);
@@ -443,18 +444,18 @@ __global__ __launch_bounds__(kBlock) void k_doc_global(const int64_t* __restrict
             }
         }
         __syncthreads();
-        for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kBlock * kLongUnroll) {
+        for (int64_t p0 = tid; p0 < L; p0 += (int64_t)kLongThreads * kLongUnroll) {
             int t[kLongUnroll];
 #pragma unroll
             for (int u = 0; u < kLongUnroll; ++u) {
-                const int64_t p = p0 + (int64_t)u * kBlock;
+                const int64_t p = p0 + (int64_t)u * kLongThreads;
                 t[u] = p < L ? tok[o + p] : -1;
             }
 #pragma unroll
             for (int u = 0; u < kLongUnroll; ++u)
                 if ((unsigned)t[u] < (unsigned)V) __hip_atomic_store(&cnt[t[u]], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        for (int j = tid; j < kpad; j += kBlock) bins[j] = 0ull;
+        for (int j = tid; j < kpad; j += kLongThreads) bins[j] = 0ull;
         __threadfence();
         __syncthreads();
     }
@@ -904,8 +905,8 @@ mrc_status run_docpass(mrc_ctx* ctx, const mrc_docs* docs, int32_t V, const Pass
         void* tables = nullptr;
         MRC_TRY(scratch(ctx, "long_tables", table_bytes, &tables));
         if (fresh) MRC_HIP_TRY(ctx, hipMemsetAsync(tables, 0, ctx->scratch["long_tables"].second, s));
-        const size_t lds = (size_t)kpad * 8 + 4 * sizeof(u128) + 16;
-        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kBlock), lds, s, docs->offsets, V,
+        const size_t lds = (size_t)kpad * 8 + (kLongThreads / 64) * sizeof(u128) + 16;
+        hipLaunchKernelGGL((k_doc_global<MODE>), dim3(kLongBlocks), dim3(kLongThreads), lds, s, docs->offsets, V,
                            docs->tokens, a, (uint32_t*)tables, err, list(3), count(3));
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
