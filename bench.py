@@ -798,15 +798,15 @@ def serving_fp8(mrc, synth, ctx, run, tau):
            "stream": "alternating insert / query, lengths lognormal median 400, sigma 1.2, 20-50,000 tokens, 20% "
                      "of the documents near duplicates of database documents"}
     rng = np.random.default_rng(43)
-    # the persistent collection (work items from a device counter, as many
-    # workgroups as are resident) for both precisions; FP8 also on the
-    # grid-strided collection
-    for pname, p, form in [("fp8", mrc.PREC_FP8, mrc.SCAN_PERSISTENT), ("fp32", mrc.PREC_FP32, mrc.SCAN_PERSISTENT),
-                           ("fp8_grid_scan", mrc.PREC_FP8, mrc.SCAN_GRID)]:
+    # the grid-strided collection for both precisions; FP8 also with the
+    # persistent collection (work items from a device counter, as many
+    # workgroups as are resident)
+    for pname, p, form in [("fp8", mrc.PREC_FP8, mrc.SCAN_GRID), ("fp32", mrc.PREC_FP32, mrc.SCAN_GRID),
+                           ("fp8_persistent_scan", mrc.PREC_FP8, mrc.SCAN_PERSISTENT)]:
         mrc.mrc_ctx_set_scan(ctx, form)
         srv = mrc.mrc_serve_start(ctx, db, model, max_batch=4096, n_streams=2, topk=16, tau=tau, precision=p,
                                   max_wait_us=500, hbm_frac=0.8)
-        sat = run([0.0] * 4096, srv=srv, docs=docs, mixed=True)
+        sat = run([0.0] * 8192, srv=srv, docs=docs, mixed=True)
         lam = 0.5 * sat["docs_per_s"]
         half = run(rng.exponential(1.0 / lam, int(min(max(lam * 3.0, 200), 40000))).tolist(), srv=srv, docs=docs,
                    mixed=True)
