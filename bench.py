@@ -94,8 +94,12 @@ def copy_probe(mib):
 
 
 def source_digest(rel):
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the kernel's source files ("a.hip+b.h": all of them, in order)."""
+    h = hashlib.sha256()
+    for part in rel.split("+"):
+        with open(os.path.join(ROOT, part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(kernel):

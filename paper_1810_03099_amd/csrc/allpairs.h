@@ -80,26 +80,33 @@ __device__ __forceinline__ void wave_prefix6(int cnt, int* excl, int* total) {
     *total = t;
 }
 
-// Epilogue of one 64x64 wavefront tile, half H (accumulator rows x = 2H, 2H+1).
-// Lane (li, lg) holds acc[x][y][r] = score of row ib + 16x + r, column
-// jb + 16y (ib = row0 + 4lg, jb = col0 + li). Each lane first builds a bitmask
-// of its flagged slots (score >= thr, and i < j < n outside interior tiles);
-// a wavefront scan of the counts gives every lane its output positions; lanes
-// with flags park their 32 scores in LDS (scr) so that the flagged ones can be
-// read back by slot index, and write their pairs to the stage (or, for more
-// flags than the stage holds, straight to the output).
+// Flag marks of one half of a 64x64 wavefront tile (accumulator rows x = 2H,
+// 2H+1): bit xx*16 + y*4 + r is set when acc[2H+xx][y][r] >= thr. The sign of
+// score - thr decides, which for finite values is the comparison itself (a
+// difference is zero only for equal operands, and a flush to zero keeps its
+// sign); a funnel shift moves each sign into the word, one instruction per
+// score.
 template <int H>
-__device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, bool interior, int ib, int jb,
+__device__ __forceinline__ uint32_t half_marks(const f32x4 (&acc)[4][4], float thr) {
+    uint32_t below = 0;
+#pragma unroll
+    for (int b = 31; b >= 0; --b)
+        below = __builtin_amdgcn_alignbit(below, __float_as_uint(acc[2 * H + (b >> 4)][(b >> 2) & 3][b & 3] - thr), 31);
+    return ~below;
+}
+
+// Epilogue of one 64x64 wavefront tile, half H (accumulator rows x = 2H, 2H+1),
+// from its marks m (half_marks). Lane (li, lg) holds acc[x][y][r] = score of
+// row ib + 16x + r, column jb + 16y (ib = row0 + 4lg, jb = col0 + li). Outside
+// interior tiles the marks keep only i < j < n; a wavefront scan of the
+// counts gives every lane its output positions; lanes with flags park their
+// 32 scores in LDS (scr) so that the flagged ones can be read back by slot
+// index, and write their pairs to the stage (or, for more flags than the
+// stage holds, straight to the output).
+template <int H>
+__device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], uint32_t m, bool interior, int ib, int jb,
                                           int n, float* __restrict__ scr, PairStage& st, const PairSink& sink) {
     const int lane = __lane_id();
-    uint32_t m = 0;
-#pragma unroll
-    for (int xx = 0; xx < 2; ++xx)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                m |= (acc[2 * H + xx][y][r] >= thr ? 1u : 0u) << (xx * 16 + y * 4 + r);
     if (!interior) {
         uint32_t valid = 0;
 #pragma nounroll
@@ -148,24 +155,15 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], float thr, b
     __builtin_amdgcn_wave_barrier();
 }
 
-// Whole epilogue of one 64x64 wavefront tile (lane layout as in tile_half). A
-// tile whose largest score is below thr in every lane (the common case away
-// from duplicates) ends after a max tree.
+// Whole epilogue of one 64x64 wavefront tile (lane layout as in tile_half):
+// both halves' marks first, so that a tile with no score >= thr in any lane
+// (the common case away from duplicates) ends after one ballot.
 __device__ __forceinline__ void tile_epilogue(const f32x4 (&acc)[4][4], float thr, bool interior, int ib, int jb,
                                               int n, float* __restrict__ scr, PairStage& st, const PairSink& sink) {
-    float mx[16];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y)
-            mx[x * 4 + y] = fmaxf(fmaxf(acc[x][y][0], acc[x][y][1]), fmaxf(acc[x][y][2], acc[x][y][3]));
-#pragma unroll
-    for (int w = 8; w >= 1; w >>= 1)
-#pragma unroll
-        for (int i = 0; i < w; ++i) mx[i] = fmaxf(mx[i], mx[i + w]);
-    if (__ballot(mx[0] >= thr) == 0) return;
-    tile_half<0>(acc, thr, interior, ib, jb, n, scr, st, sink);
-    tile_half<1>(acc, thr, interior, ib, jb, n, scr, st, sink);
+    const uint32_t m0 = half_marks<0>(acc, thr), m1 = half_marks<1>(acc, thr);
+    if (__ballot((m0 | m1) != 0) == 0) return;
+    tile_half<0>(acc, m0, interior, ib, jb, n, scr, st, sink);
+    tile_half<1>(acc, m1, interior, ib, jb, n, scr, st, sink);
 }
 
 // LDS of the all-pairs kernels (4 wavefronts): pair stages and score parking.

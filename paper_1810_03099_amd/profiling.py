@@ -13,8 +13,8 @@ Two commands, both reading rocprofv3's CSV output (``--output-format csv``):
     dispatch, averaged over its dispatches) by what the same counters read for
     a device-to-device copy of B bytes each way, and records the resulting HBM
     bytes per launch under key K in ``profiles/traffic.json`` together with a
-    digest of the kernel's source file (a figure whose source digest no longer
-    matches is stale and is not reported).
+    digest of the kernel's source files (REL, or "a.hip+b.h" for several; a
+    figure whose source digest no longer matches is stale and is not reported).
 """
 from __future__ import annotations
 
@@ -31,8 +31,13 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def source_digest(rel: str) -> str:
-    with open(os.path.join(ROOT, rel), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Digest of the kernel's source files ("a.hip+b.h": all of them, in order;
+    one file gives the digest of that file alone)."""
+    h = hashlib.sha256()
+    for part in rel.split("+"):
+        with open(os.path.join(ROOT, part), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def short_name(n: str) -> str:
