@@ -340,8 +340,16 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
 // Long documents (the last length class of k_validate_offsets): a [V]
 // uint32 count table per workgroup in global memory (all zero between
 // documents).
+// Counts go first to a small LDS cache of terms (one slot per hashed id, the
+// first term to claim a slot keeps it for the document), the rest to the
+// global table; a long Zipf document repeats its hottest terms thousands of
+// times, and same-address global atomics serialise in L2 where LDS ones are
+// cheap. The cache is flushed into the global table (and, when signing, into
+// the part sums: count x the term's fixed-point coefficient, the same integer
+// as the sum of one coefficient per occurrence) before the norm pass.
 constexpr int kLongUnroll = 8;
 constexpr int kLongThreads = 1024;  // a workgroup per long document: 16 wavefronts
+constexpr int kHotLog2 = 11;        // 2,048 cached terms (16 KB of LDS)
 template <int MODE>
 __global__ __launch_bounds__(kLongThreads) void k_doc_global(const int64_t* __restrict__ off, int32_t V,
                                                        const int32_t* __restrict__ tok, PassArgs a,
@@ -354,10 +362,16 @@ __global__ __launch_bounds__(kLongThreads) void k_doc_global(const int64_t* __re
     const int kpad = MODE == MODE_SIGN ? ((a.k + 1) & ~1) : 0;
     u128* red = (u128*)(smem + (size_t)kpad * 8);
     int* tcount = (int*)(red + kLongThreads / 64);
+    __shared__ int hot_key[1 << kHotLog2];
+    __shared__ uint32_t hot_cnt[1 << kHotLog2];
     uint32_t* cnt = tables + (size_t)blockIdx.x * (size_t)V;
     const int tid = threadIdx.x;
     if (pass_disabled(err)) return;
     for (int j = tid; j < kpad; j += kLongThreads) bins[j] = 0ull;
+    for (int j = tid; j < (1 << kHotLog2); j += kLongThreads) {
+        hot_key[j] = -1;
+        hot_cnt[j] = 0u;
+    }
     __syncthreads();
     const int64_t n_items = (int64_t)__hip_atomic_load(count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (int64_t item = blockIdx.x; item < n_items; item += gridDim.x) {
@@ -383,14 +397,37 @@ __global__ __launch_bounds__(kLongThreads) void k_doc_global(const int64_t* __re
 #pragma unroll
                 for (int u = 0; u < kLongUnroll; ++u) ti[u] = t[u] >= 0 ? a.tinfo[t[u]] : TermInfo{0.f, -1};
             }
+            int held[kLongUnroll];
+#pragma unroll
+            for (int u = 0; u < kLongUnroll; ++u)
+                held[u] = t[u] >= 0 ? atomicCAS(&hot_key[hash_slot(t[u], kHotLog2)], -1, t[u]) : -2;
 #pragma unroll
             for (int u = 0; u < kLongUnroll; ++u) {
                 if (t[u] < 0) continue;
+                if (held[u] == -1 || held[u] == t[u]) {  // the slot is this term's
+                    atomicAdd(&hot_cnt[hash_slot(t[u], kHotLog2)], 1u);
+                    continue;
+                }
                 atomicAdd(&cnt[t[u]], 1u);
                 if constexpr (MODE == MODE_SIGN) {
                     if (ti[u].part >= 0) atomicAdd(&bins[ti[u].part], mrc_dev::fixed32(ref_coef(a, ti[u].idf)));
                 }
             }
+        }
+        __syncthreads();
+        // flush the cached counts (and their part sums) into the global table
+        for (int j = tid; j < (1 << kHotLog2); j += kLongThreads) {
+            const int key = hot_key[j];
+            if (key < 0) continue;
+            const uint32_t c = hot_cnt[j];
+            atomicAdd(&cnt[key], c);
+            if constexpr (MODE == MODE_SIGN) {
+                const TermInfo ti = a.tinfo[key];
+                if (ti.part >= 0)
+                    atomicAdd(&bins[ti.part], (unsigned long long)c * mrc_dev::fixed32(ref_coef(a, ti.idf)));
+            }
+            hot_key[j] = -1;
+            hot_cnt[j] = 0u;
         }
         __threadfence();
         __syncthreads();
