@@ -99,9 +99,10 @@ __global__ __launch_bounds__(256) void k_compare_f32(const float* __restrict__ u
     st.flush(sink);
 }
 
-// k in (32, 64] (four 16-column chunks): one wavefront per SIMD, so that its
-// matrix-core products stream at the single-wavefront rate, fed by a ring of
-// four chunk buffers in registers: the loads of chunk c + 3 are issued before
+// k in (32, 64] (four 16-column chunks): a ring of four chunk buffers in
+// registers feeds the matrix-core products (240 registers: two wavefronts per
+// SIMD, so that one's flag walk overlaps the other's products, as the 64 KB
+// of LDS per workgroup also allows): the loads of chunk c + 3 are issued before
 // the products of chunk c (during a tile's chunks 1-3, the next tile's chunks
 // 0-2), so three chunks are in flight while one is multiplied. Chunk c of
 // every tile lives in buffer c, so the ring needs no register copies, and the
