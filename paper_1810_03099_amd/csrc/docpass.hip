@@ -261,43 +261,84 @@ __global__ __launch_bounds__(kBlock) void k_doc_lds(const int64_t* __restrict__ 
             t_r[r] = p < L ? tok[o + p] : kEmpty;
         }
         TermInfo ti_r[MAXPER];
-        if constexpr (MODE != MODE_COUNT) {
+        if constexpr (MODE == MODE_CSR) {
 #pragma unroll
             for (int r = 0; r < MAXPER; ++r)
                 ti_r[r] = (unsigned)t_r[r] < (unsigned)V ? a.tinfo[t_r[r]] : TermInfo{1.f, -1};
         }
-        int slot_r[MAXPER];
+        // insert: the first probes of all of this thread's tokens go out
+        // together, then each token probes on (linear) until its slot holds
+        // it; the counts are added without waiting, and the slots this
+        // thread claimed join the used list with one reservation
+        int slot_r[MAXPER], prev_r[MAXPER];
+        bool ok_r[MAXPER];
 #pragma unroll
         for (int r = 0; r < MAXPER; ++r) {
-            slot_r[r] = -1;
-            if (tid + r * TEAM < L) {
-                const int t = t_r[r];
-                if ((unsigned)t >= (unsigned)V) {
-                    atomicOr(err, kErrToken);
-                    continue;
-                }
-                int h = hash_slot(t, LOG2_SLOTS);
-                bool won = false;
-                while (true) {
-                    const int prev = atomicCAS(&keys[h], kEmpty, t);
-                    if (prev == kEmpty) {
-                        won = true;
-                        break;
-                    }
-                    if (prev == t) break;
-                    h = (h + 1) & (SLOTS - 1);
-                }
-                atomicAdd(&cnt[h], 1);
-                if (won) used[atomicAdd(nused, 1)] = (unsigned short)h;
-                slot_r[r] = h;
-                if constexpr (MODE == MODE_SIGN) {
-                    if (ti_r[r].part >= 0) atomicAdd(&bins[ti_r[r].part], mrc_dev::fixed32(ref_coef(a, ti_r[r].idf)));
-                }
+            ok_r[r] = tid + r * TEAM < L;
+            if (ok_r[r] && (unsigned)t_r[r] >= (unsigned)V) {
+                atomicOr(err, kErrToken);
+                ok_r[r] = false;
             }
+            slot_r[r] = ok_r[r] ? hash_slot(t_r[r], LOG2_SLOTS) : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < MAXPER; ++r) prev_r[r] = ok_r[r] ? atomicCAS(&keys[slot_r[r]], kEmpty, t_r[r]) : kEmpty;
+        uint32_t won = 0;
+#pragma unroll
+        for (int r = 0; r < MAXPER; ++r) {
+            if (!ok_r[r]) {
+                slot_r[r] = -1;
+                continue;
+            }
+            int h = slot_r[r], prev = prev_r[r];
+            while (prev != kEmpty && prev != t_r[r]) {
+                h = (h + 1) & (SLOTS - 1);
+                prev = atomicCAS(&keys[h], kEmpty, t_r[r]);
+            }
+            slot_r[r] = h;
+            if (prev == kEmpty) won |= 1u << r;
+        }
+#pragma unroll
+        for (int r = 0; r < MAXPER; ++r)
+            if (slot_r[r] >= 0) atomicAdd(&cnt[slot_r[r]], 1);
+        if (won) {
+            int u = atomicAdd(nused, __popc(won));
+#pragma unroll
+            for (int r = 0; r < MAXPER; ++r)
+                if (won & (1u << r)) used[u++] = (unsigned short)slot_r[r];
         }
         team_sync<TEAM>();
         double nrm = 0.0;
-        if constexpr (MODE != MODE_COUNT) {
+        if constexpr (MODE == MODE_SIGN) {
+            // once per distinct term (not per occurrence): its term data, its
+            // part sum tf x coefficient and its norm term (tf idf)^2, the
+            // same integers as the per-occurrence sums
+            const int nu0 = *nused;
+            u128 nacc = 0;
+            for (int u0 = tid; u0 < nu0; u0 += 4 * TEAM) {
+                int tt[4];
+                uint32_t tf[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int u = u0 + q * TEAM;
+                    const int sl = u < nu0 ? (int)used[u] : -1;
+                    tt[q] = sl >= 0 ? keys[sl] : -1;
+                    tf[q] = sl >= 0 ? (uint32_t)cnt[sl] : 0u;
+                }
+                TermInfo ti[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) ti[q] = tt[q] >= 0 ? a.tinfo[tt[q]] : TermInfo{1.f, -1};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    if (tt[q] < 0) continue;
+                    if (ti[q].part >= 0)
+                        atomicAdd(&bins[ti[q].part], (unsigned long long)tf[q] * mrc_dev::fixed32(ref_coef(a, ti[q].idf)));
+                    nacc += term_sq_fixed(tf[q], ti[q].idf);
+                }
+            }
+            team_sync<TEAM>();  // (the part sums complete before they are read)
+            nrm = norm_from_fixed(team_sum<TEAM>(nacc, red));
+        } else if constexpr (MODE == MODE_CSR) {
             u128 nacc = 0;
 #pragma unroll
             for (int r = 0; r < MAXPER; ++r)
