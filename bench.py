@@ -128,6 +128,21 @@ def timed(mrc, ctx, kernel, fn, reps):
     return (ms / n if n else None), wall * 1e3, out
 
 
+def cpu_affinity():
+    """The host CPUs this process may run on, as ranges ("0-15")."""
+    try:
+        cpus = sorted(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        return None
+    out, lo = [], None
+    for x, nxt in zip(cpus, cpus[1:] + [None]):
+        lo = x if lo is None else lo
+        if nxt != x + 1:
+            out.append(f"{lo}-{x}" if x != lo else str(x))
+            lo = None
+    return ",".join(out)
+
+
 def cpu_baseline(c, k, tau, sample_note="full workload"):
     """The FP64 oracle on the same workload (one whole step: build, sign, compare)."""
     from oracle import mrc as om
@@ -146,7 +161,7 @@ def cpu_baseline(c, k, tau, sample_note="full workload"):
     pairs = n * (n - 1) / 2
     return {"value": pairs / dt, "unit": "pairs/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{sample_note}: {n} docs, one step (build + sign + all-pairs compare), float64 NumPy, "
-                      f"{dt:.2f} s", "seconds": dt, "host_cpus": os.cpu_count()}, shat, (i, j)
+                      f"{dt:.2f} s", "seconds": dt, "host_cpus": os.cpu_count(), "affinity": cpu_affinity()}, shat, (i, j)
 
 
 def main():
@@ -363,7 +378,8 @@ def text_front_end(a, mrc):
         ot.trigram_csr(t50, o50)
         sec = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": t50.size / sec, "unit": "bytes/s", "cores": 1, "kind": "oracle",
-                               "sample": f"the 50,000 generated documents ({t50.size} bytes), NumPy", "seconds": sec}
+                               "sample": f"the 50,000 generated documents ({t50.size} bytes), NumPy", "seconds": sec,
+                               "affinity": cpu_affinity()}
     return out
 
 
