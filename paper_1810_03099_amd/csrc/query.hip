@@ -112,6 +112,21 @@ __device__ __forceinline__ uint32_t tile_marks(const f32x4 (&acc)[4], float thr,
     return ~below & rowmask;
 }
 
+// The marks with a per-row threshold thr - b e_r (FP8: e = the errors of the
+// lane's 16 rows, e[x][r] for row row0 + 16x + 4lg + r): the threshold is
+// one fused multiply-add per score, then the same sign test.
+__device__ __forceinline__ uint32_t tile_marks_rows(const f32x4 (&acc)[4], float thr, float b, const f32x4 (&e)[4],
+                                                   uint32_t rowmask) {
+#pragma clang fp contract(off)  // (the score as rounded, not fused into the difference)
+    uint32_t below = 0;
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+        const float t = __builtin_fmaf(-b, e[i >> 2][i & 3], thr);
+        below = __builtin_amdgcn_alignbit(below, __float_as_uint(acc[i >> 2][i & 3] - t), 31);
+    }
+    return ~below & rowmask;
+}
+
 // The marks a tile's rows allow: all 16, except on the last tile, where the
 // rows at or past rows_left (counted from the tile's first row) drop out.
 __device__ __forceinline__ uint32_t tile_rowmask(int64_t rows_left, int lg) {
@@ -220,7 +235,9 @@ struct ScanArgs {
     float* part_s;
     int32_t* part_id;
     // MODE_COLLECT: candidates with score >= thr[q]
-    const float* thr;
+    const float* thr;         // per query: the threshold (FP8: its part C_q without the row term)
+    const float* thr_b;       // FP8: per query B_q, the row term's coefficient (threshold C_q - B_q e_r)
+    const float* row_err;     // FP8: per database row e_r, its code's error bound
     int32_t* cand;            // [nq][cap] row ids
     int32_t* ccount;          // [nq]
     int cap;
@@ -287,7 +304,7 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
     typename T::F qb[G][NK];
     int q[G];
     bool qvalid[G];
-    float qsc[G], thr[G];
+    float qsc[G], thr[G], thrb[G];
     // collection: the previous tile's marks, their reserved slots and first
     // row (written once the next tile's loads have returned, by when the
     // slot atomics issued before them have too)
@@ -312,6 +329,7 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
             if (MODE == MODE_COLLECT) {
                 const float t = qvalid[g] ? a.thr[q[g]] : INFINITY;
                 thr[g] = t == t ? t : INFINITY;  // (no marks for a NaN threshold)
+                thrb[g] = (PREC == MRC_PREC_FP8 && qvalid[g]) ? a.thr_b[q[g]] : 0.f;
             }
         }
     };
@@ -374,9 +392,11 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
         }
         // lane holds query li of each group against rows row0 + 16x + 4lg + r
         // (ascending ids in this order)
+        f32x4 rerr[4];  // FP8 collection: the errors of the lane's rows (the per-row band)
         if (PREC == MRC_PREC_FP8) {
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
+                if (MODE == MODE_COLLECT) rerr[x] = *(const f32x4*)(a.row_err + row0 + 16 * x + 4 * lg);
                 const f32x4 sc = *(const f32x4*)(a.db_scale + row0 + 16 * x + 4 * lg);  // rows padded to 64
 #pragma unroll
                 for (int g = 0; g < G; ++g)
@@ -409,7 +429,9 @@ __global__ __launch_bounds__(256) void k_query_scan(ScanArgs a) {
             uint32_t m[G];
             const uint32_t rm = tile_rowmask(a.rows - row0, lg);
 #pragma unroll
-            for (int g = 0; g < G; ++g) m[g] = tile_marks(acc[g], thr[g], rm);
+            for (int g = 0; g < G; ++g)
+                m[g] = PREC == MRC_PREC_FP8 ? tile_marks_rows(acc[g], thr[g], thrb[g], rerr, rm)
+                                            : tile_marks(acc[g], thr[g], rm);
             write_marks(a, pm, q, pb, prow0, lg);
             reserve_marks(a, m, q, pb);
 #pragma unroll
@@ -514,10 +536,13 @@ __device__ __forceinline__ float chain_blocks(const f32x4* qs, const f32x4* __re
 
 // Per query (one wavefront each): E16 = the smallest exact score of the 16
 // first-pass rows (a row id of -1: fewer than 16 rows, E16 = -inf), the band
-// b = e_q + e_db + e_q e_db + a (1 + e_q)(1 + e_db) + 2^-20 of the query's
-// low-precision error e_q against the database rows' largest e_db (none for
-// FP32 scores, which are the chain itself: db_err is NULL), and the
-// collection threshold thr = min(E16 - b, tau - b). It also zeroes the
+// b = e_q + e_r + e_q e_r + a (1 + e_q)(1 + e_r) + 2^-20 of the query's
+// low-precision error e_q against a row's e_r (none for FP32 scores, which
+// are the chain itself: db_err is NULL), and the collection threshold
+// min(E16 - b, tau - b). With thr_b (FP8) the band is the row's own:
+// b = A + B e_r, thr = min(E16, tau) - A and thr_b = B, and the collection
+// tests score >= thr - B e_r; otherwise e_r is the database's largest error
+// (db_err) and thr is the whole threshold. It also zeroes the
 // query's candidate count, and block 0 the capacity signal and the
 // persistent collection's work counter (when given), so the collection
 // needs no clearing launches of its own.
@@ -525,7 +550,7 @@ __global__ __launch_bounds__(256) void k_query_e16(const mrc_hit* __restrict__ l
                                                    const float* __restrict__ qunit, int k,
                                                    const float* __restrict__ db_umfma, int kp, float tau,
                                                    const float* __restrict__ db_err, const float* __restrict__ q_err,
-                                                   float acc_unit, float* __restrict__ thr,
+                                                   float acc_unit, float* __restrict__ thr, float* __restrict__ thr_b,
                                                    int32_t* __restrict__ ccount, unsigned long long* __restrict__ cap_word,
                                                    unsigned long long* __restrict__ work) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -548,12 +573,20 @@ __global__ __launch_bounds__(256) void k_query_e16(const mrc_hit* __restrict__ l
     }
     for (int off = 32; off >= 1; off >>= 1) v = fminf(v, __shfl_xor(v, off, 64));
     if (lane == 0) {
-        float b = 0.f;
+        // b = A + B e_db with A = e_q + a (1 + e_q) + 2^-20, B = 1 + e_q + a (1 + e_q)
+        float A = 0.f, B = 0.f;
         if (db_err) {
-            const float ei = q_err[q], ej = *db_err;
-            b = ei + ej + ei * ej + acc_unit * (1.f + ei) * (1.f + ej) + 9.5367431640625e-07f;
+            const float ei = q_err[q];
+            A = ei + acc_unit * (1.f + ei) + 9.5367431640625e-07f;
+            B = 1.f + ei + acc_unit * (1.f + ei);
         }
-        thr[q] = fminf(v - b, tau - b);
+        if (thr_b) {  // per-row band: the collection subtracts B e_r itself
+            thr[q] = fminf(v, tau) - A;
+            thr_b[q] = B;
+        } else {
+            const float b = db_err ? A + B * *db_err : 0.f;
+            thr[q] = fminf(v - b, tau - b);
+        }
         ccount[q] = 0;
     }
 }
@@ -638,7 +671,7 @@ void k_query_collect_lds(ScanArgs a) {
     typename T::F qb[G][NK];
     int q[G];
     bool qvalid[G];
-    float qsc[G], thr[G];
+    float qsc[G], thr[G], thrb[G];
     // the fragments of query block y (rows of the padded query arrays)
     auto load_queries = [&](int64_t y) {
 #pragma unroll
@@ -651,6 +684,7 @@ void k_query_collect_lds(ScanArgs a) {
             qsc[g] = (PREC == MRC_PREC_FP8) ? a.q_scale[q[g]] : 1.f;
             const float th = qvalid[g] ? a.thr[q[g]] : INFINITY;
             thr[g] = th == th ? th : INFINITY;  // (no marks for a NaN threshold)
+            thrb[g] = (PREC == MRC_PREC_FP8 && MODE == MODE_COLLECT && qvalid[g]) ? a.thr_b[q[g]] : 0.f;
         }
     };
     const int64_t n_tiles = (a.rows + kTileRows - 1) / kTileRows;
@@ -751,9 +785,11 @@ void k_query_collect_lds(ScanArgs a) {
 #pragma unroll
                 for (int x = 0; x < 4; ++x) acc[g][x] = T::mma(fa[x], qb[g][c], acc[g][x]);
         }
+        f32x4 rerr[4];  // FP8 collection: the errors of the lane's rows (the per-row band)
         if (PREC == MRC_PREC_FP8) {
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
+                if (MODE == MODE_COLLECT) rerr[x] = *(const f32x4*)(a.row_err + row0 + 16 * x + 4 * lg);
                 const f32x4 sc = *(const f32x4*)(a.db_scale + row0 + 16 * x + 4 * lg);
 #pragma unroll
                 for (int g = 0; g < G; ++g)
@@ -773,7 +809,8 @@ void k_query_collect_lds(ScanArgs a) {
             const uint32_t rm = tile_rowmask(a.rows - row0, lg);
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                m[g] = tile_marks(acc[g], thr[g], rm);
+                m[g] = PREC == MRC_PREC_FP8 ? tile_marks_rows(acc[g], thr[g], thrb[g], rerr, rm)
+                                            : tile_marks(acc[g], thr[g], rm);
                 asm volatile("" : "+v"(m[g]));  // (computed here, not sunk to its use)
             }
             __builtin_amdgcn_sched_barrier(0);
@@ -1063,11 +1100,19 @@ mrc_status run_query(mrc_ctx* ctx, const mrc_db* db, int64_t rows, const mrc_mod
     if (pers) MRC_TRY(scratch(ctx, "q_work", 256, &work));
     MRC_TRY(scratch(ctx, "q_ccount", (size_t)ceil_div(nq, 2) * 8, &cc));  // (whole words: cleared as such)
     unsigned long long* cap_word = (unsigned long long*)(ctx->d_flags + kQueryCapWord);
+    // FP8: the band of each (query, row) pair from the row's own error (the
+    // database keeps every row's), so well-quantised rows get a narrower
+    // window; BF16 errors barely vary between rows: the largest serves
+    const bool per_row = precision == MRC_PREC_FP8;
+    void* thrb = nullptr;
+    if (per_row) MRC_TRY(scratch(ctx, "q_thr_b", (size_t)nq * 4, &thrb));
     hipLaunchKernelGGL(k_query_e16, dim3((unsigned)ceil_div(nq, 4)), dim3(256), 0, s, (const mrc_hit*)mtop, (int)nq,
                        (const float*)unit, k, db->d_unit, L.kp, tau,
                        fp32 ? (const float*)nullptr : db->d_errmax + (bf ? 0 : 1),
                        (const float*)qerr + (bf ? 0 : nq_pad), fp32 ? 0.f : lowp_acc_unit(precision, k), (float*)thr,
-                       (int32_t*)cc, cap_word, (unsigned long long*)work);
+                       (float*)thrb, (int32_t*)cc, cap_word, (unsigned long long*)work);
+    a.thr_b = (const float*)thrb;
+    a.row_err = per_row ? db->d_err + db->cap_pad : nullptr;
     MRC_HIP_TRY(ctx, hipGetLastError());
     // pass 2: every row at or above the threshold, G query groups per
     // wavefront, then exact decisions; grow the per-query capacity on overflow
