@@ -12,6 +12,7 @@
 //    accumulators for every j in that term's posting list (one term at a
 //    time, so each accumulator sees its terms in order).
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -151,9 +152,16 @@ __global__ __launch_bounds__(256) void k_gram_head(const float* __restrict__ wh,
 }
 
 // Row pass: the chain of row i continues over its (rank-sorted) tail terms,
-// then every j > i with score >= tau is emitted.
+// then every j > i with score >= tau is emitted. Terms are applied one at a
+// time (a workgroup barrier after each keeps every accumulator's terms in
+// rank order); their posting ranges and weights are staged in LDS 512 terms
+// at a time, and each thread's posting entries are loaded two terms ahead
+// (up to kPostQ per thread; a longer list loads the rest in place), so a term
+// costs a barrier rather than three dependent global loads.
 constexpr int kRowChunk = 16384;
-constexpr int kRowStage = 1024;
+constexpr int kRowStage = 512;
+constexpr int kMetaTerms = 512;
+constexpr int kPostQ = 4;
 
 __global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ G, int64_t ldg, int r0, int n,
                                                     const int64_t* __restrict__ off,
@@ -165,29 +173,77 @@ __global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ G,
                                                     const float* __restrict__ post_w, float tau, PairSink sink) {
     __shared__ float acc[kRowChunk];
     __shared__ mrc_pair stage[kRowStage];
+    __shared__ uint32_t sm_p0[kMetaTerms], sm_len[kMetaTerms];
+    __shared__ float sm_w[kMetaTerms];
     __shared__ int scount;
     __shared__ unsigned long long sbase;
     const int i = r0 + blockIdx.x;
     if (i >= n) return;
+    const int tid = threadIdx.x;
     const int64_t o = off[i];
     const int m = nnz_tail[i];
     const float* grow = G + (int64_t)blockIdx.x * ldg;
+    int dq[3][kPostQ];
+    float wq[3][kPostQ];
     for (int c0 = i + 1; c0 < n; c0 += kRowChunk) {
         const int c1 = min(n, c0 + kRowChunk);
-        for (int j = c0 + threadIdx.x; j < c1; j += 256) acc[j - c0] = grow[j];
-        if (threadIdx.x == 0) scount = 0;
+        for (int j = c0 + tid; j < c1; j += 256) acc[j - c0] = grow[j];
+        if (tid == 0) scount = 0;
         __syncthreads();
-        for (int e = 0; e < m; ++e) {
-            const int r = ent_rank[o + e] - H;
-            const float wi = ent_w[o + e];
-            const uint32_t p1 = poff[r + 1];
-            for (uint32_t p = poff[r] + threadIdx.x; p < p1; p += 256) {
-                const int j = post_doc[p];
-                if (j >= c0 && j < c1) acc[j - c0] = __builtin_fmaf(wi, post_w[p], acc[j - c0]);
+        for (int eb = 0; eb < m; eb += kMetaTerms) {
+            const int nb = min(kMetaTerms, m - eb);
+            for (int e = tid; e < nb; e += 256) {
+                const int r = ent_rank[o + eb + e] - H;
+                const uint32_t p0 = poff[r];
+                sm_p0[e] = p0;
+                sm_len[e] = poff[r + 1] - p0;
+                sm_w[e] = ent_w[o + eb + e];
             }
             __syncthreads();
+            // term e's first kPostQ * 256 entries into ring slot S
+            auto load = [&](int e, auto slot) __attribute__((always_inline)) {
+                constexpr int S = decltype(slot)::value;
+                const bool has = e < nb;
+                const uint32_t p0 = has ? sm_p0[e] : 0u, len = has ? sm_len[e] : 0u;
+#pragma unroll
+                for (int q = 0; q < kPostQ; ++q) {
+                    const uint32_t x = (uint32_t)(tid + 256 * q);
+                    dq[S][q] = x < len ? post_doc[p0 + x] : -1;
+                    wq[S][q] = x < len ? post_w[p0 + x] : 0.f;
+                }
+            };
+            auto apply = [&](int e, auto slot) __attribute__((always_inline)) {
+                constexpr int S = decltype(slot)::value;
+                const float wi = sm_w[e];
+#pragma unroll
+                for (int q = 0; q < kPostQ; ++q) {
+                    const int j = dq[S][q];
+                    if (j >= c0 && j < c1) acc[j - c0] = __builtin_fmaf(wi, wq[S][q], acc[j - c0]);
+                }
+                const uint32_t len = sm_len[e];
+                if (len > 256u * kPostQ) {  // the rest of a long list, in place
+                    const uint32_t p0 = sm_p0[e];
+                    for (uint32_t x = 256u * kPostQ + tid; x < len; x += 256) {
+                        const int j = post_doc[p0 + x];
+                        if (j >= c0 && j < c1) acc[j - c0] = __builtin_fmaf(wi, post_w[p0 + x], acc[j - c0]);
+                    }
+                }
+                __syncthreads();
+            };
+            load(0, std::integral_constant<int, 0>{});
+            load(1, std::integral_constant<int, 1>{});
+            for (int e = 0; e < nb; e += 3) {
+                load(e + 2, std::integral_constant<int, 2>{});
+                apply(e, std::integral_constant<int, 0>{});
+                if (e + 1 >= nb) break;
+                load(e + 3, std::integral_constant<int, 0>{});
+                apply(e + 1, std::integral_constant<int, 1>{});
+                if (e + 2 >= nb) break;
+                load(e + 4, std::integral_constant<int, 1>{});
+                apply(e + 2, std::integral_constant<int, 2>{});
+            }
         }
-        for (int j = c0 + threadIdx.x; j < c1; j += 256) {
+        for (int j = c0 + tid; j < c1; j += 256) {
             const float v = acc[j - c0];
             if (v >= tau) {
                 const int slot = atomicAdd(&scount, 1);
@@ -201,9 +257,9 @@ __global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ G,
         }
         __syncthreads();
         const int cnt = min(scount, kRowStage);
-        if (threadIdx.x == 0 && cnt > 0) sbase = atomicAdd(sink.counter, (unsigned long long)cnt);
+        if (tid == 0 && cnt > 0) sbase = atomicAdd(sink.counter, (unsigned long long)cnt);
         __syncthreads();
-        for (int e = threadIdx.x; e < cnt; e += 256) {
+        for (int e = tid; e < cnt; e += 256) {
             const int64_t dst = (int64_t)sbase + e;
             if (dst < sink.capacity) sink.pairs[dst] = stage[e];
         }
