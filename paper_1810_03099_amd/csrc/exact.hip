@@ -155,13 +155,24 @@ __global__ __launch_bounds__(256) void k_gram_head(const float* __restrict__ wh,
 // then every j > i with score >= tau is emitted. Terms are applied one at a
 // time (a workgroup barrier after each keeps every accumulator's terms in
 // rank order); their posting ranges and weights are staged in LDS 512 terms
-// at a time, and each thread's posting entries are loaded two terms ahead
-// (up to kPostQ per thread; a longer list loads the rest in place), so a term
-// costs a barrier rather than three dependent global loads.
+// at a time, and each thread's posting entries are loaded kRing - 1 terms
+// ahead (up to kPostQ per thread; a longer list loads the rest in place), so
+// a term costs a barrier rather than three dependent global loads.
+// f(integral_constant<int, 0>), ..., f(integral_constant<int, N - 1>) in order
+// (compile-time ring slots).
+template <int N, int I = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<N, I + 1>(f);
+    }
+}
+
 constexpr int kRowChunk = 16384;
 constexpr int kRowStage = 512;
 constexpr int kMetaTerms = 512;
-constexpr int kPostQ = 4;
+constexpr int kPostQ = 2;   // posting entries per thread and term in the ring
+constexpr int kRing = 6;    // terms in flight: entries of term e + kRing - 1 load while term e is applied
 
 __global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ G, int64_t ldg, int r0, int n,
                                                     const int64_t* __restrict__ off,
@@ -183,8 +194,8 @@ __global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ G,
     const int64_t o = off[i];
     const int m = nnz_tail[i];
     const float* grow = G + (int64_t)blockIdx.x * ldg;
-    int dq[3][kPostQ];
-    float wq[3][kPostQ];
+    int dq[kRing][kPostQ];
+    float wq[kRing][kPostQ];
     for (int c0 = i + 1; c0 < n; c0 += kRowChunk) {
         const int c1 = min(n, c0 + kRowChunk);
         for (int j = c0 + tid; j < c1; j += 256) acc[j - c0] = grow[j];
@@ -230,17 +241,19 @@ __global__ __launch_bounds__(256) void k_exact_rows(const float* __restrict__ G,
                 }
                 __syncthreads();
             };
-            load(0, std::integral_constant<int, 0>{});
-            load(1, std::integral_constant<int, 1>{});
-            for (int e = 0; e < nb; e += 3) {
-                load(e + 2, std::integral_constant<int, 2>{});
-                apply(e, std::integral_constant<int, 0>{});
-                if (e + 1 >= nb) break;
-                load(e + 3, std::integral_constant<int, 0>{});
-                apply(e + 1, std::integral_constant<int, 1>{});
-                if (e + 2 >= nb) break;
-                load(e + 4, std::integral_constant<int, 1>{});
-                apply(e + 2, std::integral_constant<int, 2>{});
+            static_for<kRing - 1>([&](auto sl) { load(sl.value, sl); });
+            for (int e = 0; e < nb; e += kRing) {
+                bool done = false;
+                static_for<kRing>([&](auto sl) {
+                    constexpr int S = decltype(sl)::value;
+                    if (done || e + S >= nb) {
+                        done = true;
+                        return;
+                    }
+                    load(e + S + kRing - 1, std::integral_constant<int, (S + kRing - 1) % kRing>{});
+                    apply(e + S, sl);
+                });
+                if (done) break;
             }
         }
         for (int j = c0 + tid; j < c1; j += 256) {
