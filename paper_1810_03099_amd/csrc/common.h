@@ -54,6 +54,11 @@ struct mrc_ctx {
     size_t used = 0;             // bytes held by scratch + owned objects
     mrc_status sticky = MRC_OK;  // a HIP failure poisons the context
     std::map<std::string, std::pair<void*, size_t>> scratch;
+    // buffers a scratch entry outgrew: queued work may still use them, so they
+    // are freed at teardown (or all at once, after one device-wide wait, when
+    // they pass kRetiredMax) rather than each behind a device-wide wait
+    std::vector<std::pair<void*, size_t>> retired;
+    size_t retired_bytes = 0;
     int64_t* d_flags = nullptr;  // small device word array: counters + error flags
     int64_t* h_flags = nullptr;  // pinned host mirror
     bool timing = false;

@@ -58,6 +58,8 @@ void dev_free(mrc_ctx* ctx, void* p, size_t bytes) {
     ctx->used -= bytes;
 }
 
+constexpr size_t kRetiredMax = (size_t)1 << 30;  // retired scratch kept before one synchronised sweep
+
 mrc_status scratch(mrc_ctx* ctx, const char* name, size_t bytes, void** p) {
     bytes = (bytes + 255) & ~size_t(255);
     if (bytes == 0) bytes = 256;
@@ -67,10 +69,19 @@ mrc_status scratch(mrc_ctx* ctx, const char* name, size_t bytes, void** p) {
         return MRC_OK;
     }
     if (it != ctx->scratch.end()) {
-        // grow: the old buffer may still be in use by queued work
-        MRC_HIP_TRY(ctx, hipDeviceSynchronize());
-        dev_free(ctx, it->second.first, it->second.second);
+        // grow: the old buffer may still be in use by queued work on this
+        // context's streams. Retire it instead of waiting for the whole
+        // device (a device-wide wait, and hipFree, would also stall every
+        // other context's work, e.g. the other serving slots)
+        ctx->retired.push_back(it->second);
+        ctx->retired_bytes += it->second.second;
         ctx->scratch.erase(it);
+        if (ctx->retired_bytes > kRetiredMax) {
+            MRC_HIP_TRY(ctx, hipDeviceSynchronize());
+            for (auto& r : ctx->retired) dev_free(ctx, r.first, r.second);
+            ctx->retired.clear();
+            ctx->retired_bytes = 0;
+        }
     }
     size_t want = bytes + bytes / 4;  // headroom against repeated growth
     void* q = nullptr;
@@ -305,6 +316,7 @@ void ctx_free_now(mrc_ctx* ctx) {
     (void)hipDeviceSynchronize();
     timer_collect(ctx);
     for (auto& kv : ctx->scratch) (void)hipFree(kv.second.first);
+    for (auto& r : ctx->retired) (void)hipFree(r.first);
     if (ctx->model_spare) (void)hipFree(ctx->model_spare);
     for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
     if (ctx->d_flags) (void)hipFree(ctx->d_flags);

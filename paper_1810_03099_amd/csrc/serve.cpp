@@ -27,8 +27,12 @@ struct GpuSlot {
     int32_t* d_hits = nullptr;
     float* d_sig = nullptr;
     int64_t out_cap = 0;
-    std::vector<mrc_hit> top;
-    std::vector<int32_t> hits;
+    // query results come back into pinned host buffers: an asynchronous copy
+    // into pageable memory goes through the runtime's staging path, which can
+    // hold one slot's copies behind another slot's batch
+    mrc_hit* h_top = nullptr;
+    int32_t* h_hits = nullptr;
+    double prep_ms = 0, work_ms = 0, fetch_ms = 0;  // phases of the last batch (structured log, level 3)
 };
 
 class GpuExecutor : public mrc_serve::Executor {
@@ -39,6 +43,8 @@ class GpuExecutor : public mrc_serve::Executor {
             if (sl.s) (void)hipStreamSynchronize(sl.s);
             if (sl.h_tok) (void)hipHostFree(sl.h_tok);
             if (sl.h_off) (void)hipHostFree(sl.h_off);
+            if (sl.h_top) (void)hipHostFree(sl.h_top);
+            if (sl.h_hits) (void)hipHostFree(sl.h_hits);
             if (sl.ctx) {
                 dev_free(sl.ctx, sl.d_tok, (size_t)sl.d_tok_cap * 4);
                 dev_free(sl.ctx, sl.d_off, (size_t)sl.d_off_cap * 8);
@@ -72,12 +78,18 @@ class GpuExecutor : public mrc_serve::Executor {
         log_line("serve_batch", "\"slot\": " + std::to_string(slot) + ", \"kind\": \"" +
                                     (b.kind == mrc_serve::kInsert ? "insert" : "query") + "\", \"docs\": " +
                                     std::to_string(b.reqs.size()) + ", \"tokens\": " + std::to_string(b.tokens) +
-                                    ", \"status\": " + std::to_string(rc) + ", \"ms\": " + std::to_string(ms));
+                                    ", \"status\": " + std::to_string(rc) + ", \"ms\": " + std::to_string(ms) +
+                                    ", \"prep_ms\": " + std::to_string(slots_[slot].prep_ms) + ", \"work_ms\": " +
+                                    std::to_string(slots_[slot].work_ms) + ", \"fetch_ms\": " +
+                                    std::to_string(slots_[slot].fetch_ms));
         return rc;
     }
 
     int run_batch(int slot, mrc_serve::Batch& b, std::vector<mrc_serve::Result>& out) {
         GpuSlot& sl = slots_[slot];
+        using clk = std::chrono::steady_clock;
+        const auto t0 = clk::now();
+        auto since = [](clk::time_point a) { return std::chrono::duration<double, std::milli>(clk::now() - a).count(); };
         const int64_t n = (int64_t)b.reqs.size(), T = std::max<int64_t>(1, b.tokens);
         mrc_status st = reserve(sl, n, T);
         if (st != MRC_OK) return st;
@@ -93,6 +105,8 @@ class GpuExecutor : public mrc_serve::Executor {
             hipMemcpyAsync(sl.d_off, sl.h_off, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, sl.s) != hipSuccess)
             return MRC_E_HIP;
         mrc_docs d{n, sl.d_off, sl.d_tok, std::max<int64_t>(pos, 1)};
+        sl.prep_ms = since(t0);
+        const auto t1 = clk::now();
         if (b.kind == mrc_serve::kInsert) {
             st = mrc_sign(sl.ctx, model_, &d, sl.d_sig, nullptr, sl.s);
             int64_t first = -1;
@@ -107,19 +121,20 @@ class GpuExecutor : public mrc_serve::Executor {
         const int topk = o_.topk;
         st = mrc_query(sl.ctx, db_, model_, &d, topk, o_.tau, o_.precision, sl.d_top, sl.d_hits, sl.s);
         if (st != MRC_OK) return st;
-        sl.top.resize((size_t)n * topk);
-        sl.hits.resize((size_t)n);
-        if (hipMemcpyAsync(sl.top.data(), sl.d_top, (size_t)n * topk * sizeof(mrc_hit), hipMemcpyDeviceToHost, sl.s) != hipSuccess ||
-            hipMemcpyAsync(sl.hits.data(), sl.d_hits, (size_t)n * 4, hipMemcpyDeviceToHost, sl.s) != hipSuccess ||
+        sl.work_ms = since(t1);
+        const auto t2 = clk::now();
+        if (hipMemcpyAsync(sl.h_top, sl.d_top, (size_t)n * topk * sizeof(mrc_hit), hipMemcpyDeviceToHost, sl.s) != hipSuccess ||
+            hipMemcpyAsync(sl.h_hits, sl.d_hits, (size_t)n * 4, hipMemcpyDeviceToHost, sl.s) != hipSuccess ||
             hipStreamSynchronize(sl.s) != hipSuccess)
             return MRC_E_HIP;
+        sl.fetch_ms = since(t2);
         for (int64_t i = 0; i < n; ++i) {
             auto& r = out[i];
             r.status = MRC_OK;
-            r.n_hits = sl.hits[i];
+            r.n_hits = sl.h_hits[i];
             r.top.clear();
             for (int p = 0; p < topk; ++p) {
-                const mrc_hit& h = sl.top[(size_t)i * topk + p];
+                const mrc_hit& h = sl.h_top[(size_t)i * topk + p];
                 if (h.id >= 0) r.top.push_back({h.id, h.s});
             }
         }
@@ -160,13 +175,20 @@ class GpuExecutor : public mrc_serve::Executor {
             dev_free(sl.ctx, sl.d_top, (size_t)sl.out_cap * 16 * sizeof(mrc_hit));
             dev_free(sl.ctx, sl.d_hits, (size_t)sl.out_cap * 4);
             dev_free(sl.ctx, sl.d_sig, (size_t)sl.out_cap * db_->k * 4);
+            if (sl.h_top) (void)hipHostFree(sl.h_top);
+            if (sl.h_hits) (void)hipHostFree(sl.h_hits);
             sl.d_top = nullptr;
             sl.d_hits = nullptr;
             sl.d_sig = nullptr;
+            sl.h_top = nullptr;
+            sl.h_hits = nullptr;
+            sl.out_cap = 0;
             const int64_t c = std::max<int64_t>(2 * n, 64);
             MRC_TRY(dev_alloc(sl.ctx, (void**)&sl.d_top, (size_t)c * 16 * sizeof(mrc_hit)));
             MRC_TRY(dev_alloc(sl.ctx, (void**)&sl.d_hits, (size_t)c * 4));
             MRC_TRY(dev_alloc(sl.ctx, (void**)&sl.d_sig, (size_t)c * db_->k * 4));
+            MRC_HIP_TRY(sl.ctx, hipHostMalloc((void**)&sl.h_top, (size_t)c * 16 * sizeof(mrc_hit), hipHostMallocDefault));
+            MRC_HIP_TRY(sl.ctx, hipHostMalloc((void**)&sl.h_hits, (size_t)c * 4, hipHostMallocDefault));
             sl.out_cap = c;
         }
         return MRC_OK;
