@@ -480,7 +480,7 @@ static mrc_status compare_impl(mrc_ctx* ctx, const float* sig, int64_t n, int32_
                                           (unsigned int*)(ctx->d_flags + 23), d_lo, s));
             PairSink cs{(mrc_pair*)cand, cand_cap, (unsigned long long*)(ctx->d_flags + 16)};
             MRC_TRY(launch_compare_lowp(ctx, prec, (const uint8_t*)q, ldq * ebytes, (const float*)scale, n, k, d_lo,
-                                        cs, s));
+                                        err_p, opts->tau, opts->band, cs, s));
             PairSink out{pairs_out, capacity, counter};
             MRC_TRY(launch_rescore2(ctx, prec, (const mrc_pair*)cand, (const unsigned long long*)(ctx->d_flags + 16),
                                     cand_cap, (const float*)unit, k, err_p, opts->tau, opts->band, out,
@@ -488,6 +488,7 @@ static mrc_status compare_impl(mrc_ctx* ctx, const float* sig, int64_t n, int32_
         }
         MRC_TRY(sync_flags(ctx, s, 32, "mrc_compare"));
         const int64_t n_cand = ctx->h_flags[16];
+        ctx->lowp_candidates = n_cand;
         if (n_cand > cand_cap && attempt == 0) {
             cand_cap = n_cand + n_cand / 4;
             continue;
@@ -656,6 +657,7 @@ mrc_status mrc_compare(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, con
         L.add("band_pairs_nominal", cs.n_band_nominal);
         L.add("flips_outside_nominal", cs.n_flip_outside_nominal);
         L.add("max_abs_err", (double)cs.max_abs_err);
+        if (opts && opts->precision != MRC_PREC_FP32) L.add("candidates", ctx->lowp_candidates);
     }
     return L.done(st);
 }

@@ -67,8 +67,10 @@ struct mrc_ctx {
     std::vector<hipEvent_t> event_pool;
     std::mutex mu;               // guards `used` (databases may be touched by server threads)
     int tile_order_nb = -1;      // the band table in scratch "tile_order" is for this many tile rows
+    int tile_order_bh = -1;      // ... and this band height
     int scan_form = 0;           // MRC_SCAN_GRID or MRC_SCAN_PERSISTENT (query collection)
-    int query_attempts = 0;      // collection passes of the last mrc_query (above 1: capacity grew)
+    int query_attempts = 0;
+    int64_t lowp_candidates = 0;  // candidates of the last low-precision mrc_compare (structured log)      // collection passes of the last mrc_query (above 1: capacity grew)
     void* model_spare = nullptr; // table block of the last destroyed model, kept for the next build
     size_t model_spare_bytes = 0;
     // Models and databases hold their context: destroyed while any of them
@@ -271,9 +273,12 @@ mrc_status launch_compare_f32_small(mrc_ctx* ctx, const float* umfma, int64_t n,
 // Even number of 16x16 matrix-core steps (32 BF16 or 128 FP8 components)
 // covering k: the column padding of the query kernels' code layouts.
 int lowp_steps(int precision, int k);
+// err: the rows' errors of the form's codes (FP8: each 32-row block's
+// candidate threshold comes from its rows' largest error); tau, nominal: the
+// comparison's threshold and nominal band.
 mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q, int ldq_bytes,
                                const float* scale, int64_t n, int32_t k, const float* d_lo_thr,
-                               PairSink cand, hipStream_t s);
+                               const float* err, float tau, float nominal, PairSink cand, hipStream_t s);
 float lowp_acc_unit(int precision, int k);
 mrc_status launch_lowp_threshold(mrc_ctx* ctx, int precision, const float* err, int64_t n, float tau,
                                  float nominal, int k, unsigned int* d_emax, float* d_out, hipStream_t s);
@@ -358,7 +363,8 @@ struct TileOrder {
     int64_t blocks;         // workgroups that carry tiles
     int64_t per_xcd;        // ceil(blocks / 8)
     const int64_t* band_start;  // device [n_bands + 1]: first tile index of each band
-    static constexpr int kBand = 8;
+    int bh;                     // tile rows per band (the last band may hold fewer)
+    static constexpr int kBand = 8;  // default band height
 
     // Position of one wavefront in the band order: its current band and the
     // band's first and one-past-last tile indices (all wavefront-uniform).
@@ -386,8 +392,8 @@ struct TileOrder {
             c.start = c.next;
             c.next = band_start[c.band + 1];
         }
-        const int r0 = c.band * kBand;
-        const int h = min(kBand, nb - r0);
+        const int r0 = c.band * bh;
+        const int h = min(bh, nb - r0);
         int q = (int)(t - c.start);                     // < kBand * nb
         const int tri = h * (h + 1) / 2;
         if (q < tri) {                                  // columns r0 .. r0+h-1: J - r0 + 1 tiles each
@@ -407,7 +413,7 @@ struct TileOrder {
 // The band table goes to `table` (device, n_bands + 1 words) when given, else
 // to context scratch (kept for the next call with the same tile count).
 mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s,
-                           int64_t* table = nullptr);
+                           int64_t* table = nullptr, int band_h = TileOrder::kBand);
 // Low-precision candidate kernels (lds_allpairs.hip, LDS-tiled 256x256 blocks),
 // called by launch_compare_lowp. The codes need ceil(n / 256) * 256 rows of
 // ldq_bytes = 128 * lowp_lds_chunks(precision, k) bytes, zero padded; the FP8
@@ -415,8 +421,19 @@ mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, 
 int lowp_lds_chunks(int precision, int k);  // -1: k too large for the form
 mrc_status launch_compare_bf16(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, int64_t n, const float* d_lo_thr,
                                PairSink cand, hipStream_t s);
+// Candidate threshold of a 32x32 block of FP8 scores (rows of block x, columns
+// of block y): min(t_nom, c - g (1 + E_x)(1 + E_y)), E = the block's largest
+// row error. (1 + a)(1 + e_i)(1 + e_j) - 1 + 2^-20 is the pair band's bound
+// term, so with E >= e and the margin folded into c and t_nom it is at most
+// every pair's own lower threshold tau - band(e_i, e_j).
+struct BlockBand {
+    const float* blk_err;  // device [rows of the codes / 32]: largest row error per block (0 past the last row)
+    float c;               // tau + 1 - 2^-20 - margin
+    float t_nom;           // tau - nominal - margin
+    float g;               // 1 + accumulation allowance
+};
 mrc_status launch_compare_fp8(mrc_ctx* ctx, const uint8_t* q, int ldq_bytes, const float* scale, int64_t n,
-                              const float* d_lo_thr, PairSink cand, hipStream_t s);
+                              const float* d_lo_thr, BlockBand bb, PairSink cand, hipStream_t s);
 // Workgroups of a persistent launch: as many as are resident at once on the
 // device (occupancy x CUs), rounded down to a multiple of the 8 XCDs and at most
 // `cap`.

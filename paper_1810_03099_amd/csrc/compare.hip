@@ -314,6 +314,16 @@ __global__ __launch_bounds__(256) void k_lowp_errmax(const float* __restrict__ e
     if ((threadIdx.x & 63) == 0) atomicMax(emax, __float_as_uint(m));  // non-negative floats order like their bits
 }
 
+// Largest row error of each 32-row block (0 for rows past n).
+__global__ __launch_bounds__(256) void k_block_errmax(const float* __restrict__ err, int64_t n, int64_t nblk,
+                                                      float* __restrict__ out) {
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= nblk) return;
+    float m = 0.f;
+    for (int64_t r = 32 * b; r < 32 * b + 32 && r < n; ++r) m = fmaxf(m, err[r]);
+    out[b] = m;
+}
+
 __global__ void k_lowp_threshold(const unsigned int* __restrict__ emax, float tau, float nominal, float acc_unit,
                                  float* __restrict__ out) {
     const float e = __uint_as_float(*emax);
@@ -519,12 +529,25 @@ int lowp_steps(int precision, int k) {
 
 mrc_status launch_compare_lowp(mrc_ctx* ctx, int32_t precision, const uint8_t* q, int ldq_bytes,
                                const float* scale, int64_t n, int32_t k, const float* d_lo_thr,
-                               PairSink cand, hipStream_t s) {
-    (void)k;
+                               const float* err, float tau, float nominal, PairSink cand, hipStream_t s) {
     if (n < 2) return MRC_OK;
+    if (precision == MRC_PREC_BF16) {
+        ScopedTimer tm(ctx, "compare_lowp", s);
+        return launch_compare_bf16(ctx, q, ldq_bytes, n, d_lo_thr, cand, s);
+    }
+    // 32-row blocks of the 256-row padded codes; the margin (2^-16) covers the
+    // FP32 rounding of both threshold formulas (a few 1e-7 at most)
+    const int64_t nblk = ceil_div(n, 256) * 8;
+    void* be = nullptr;
+    MRC_TRY(scratch(ctx, "lp_blk_err", (size_t)nblk * sizeof(float), &be));
+    hipLaunchKernelGGL(k_block_errmax, dim3((unsigned)ceil_div(nblk, 256)), dim3(256), 0, s, err, n, nblk,
+                       (float*)be);
+    MRC_HIP_TRY(ctx, hipGetLastError());
+    const double margin = 1.52587890625e-05;
+    const BlockBand bb{(const float*)be, (float)((double)tau + 1.0 - 9.5367431640625e-07 - margin),
+                       (float)((double)tau - (double)nominal - margin), 1.f + lowp_acc_unit(precision, k)};
     ScopedTimer tm(ctx, "compare_lowp", s);
-    if (precision == MRC_PREC_BF16) return launch_compare_bf16(ctx, q, ldq_bytes, n, d_lo_thr, cand, s);
-    return launch_compare_fp8(ctx, q, ldq_bytes, scale, n, d_lo_thr, cand, s);
+    return launch_compare_fp8(ctx, q, ldq_bytes, scale, n, d_lo_thr, bb, cand, s);
 }
 
 // Accumulation slack of a low-precision score relative to |a_i||a_j|. BF16

@@ -231,10 +231,9 @@ void timer_collect(mrc_ctx* ctx) {
 
 // start[b] = first tile index of band b (b = 0 .. n_bands): one thread per band
 // sums the sizes of the bands before it.
-__global__ void k_band_starts(int nb, int n_bands, int64_t* __restrict__ start) {
+__global__ void k_band_starts(int nb, int n_bands, int B, int64_t* __restrict__ start) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b > n_bands) return;
-    const int B = TileOrder::kBand;
     int64_t t = 0;
     for (int x = 0; x < b; ++x) {
         const int r0 = x * B, h = min(B, nb - r0);
@@ -244,8 +243,9 @@ __global__ void k_band_starts(int nb, int n_bands, int64_t* __restrict__ start) 
 }
 
 mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, int64_t* grid, hipStream_t s,
-                           int64_t* table) {
-    const int B = TileOrder::kBand;
+                           int64_t* table, int band_h) {
+    if (band_h < 1) return fail(MRC_E_INVAL, "band height must be positive");
+    const int B = band_h;
     const int n_bands = (nb + B - 1) / B;
     int64_t t = 0;
     for (int b = 0; b < n_bands; ++b) {
@@ -256,21 +256,23 @@ mrc_status make_tile_order(mrc_ctx* ctx, int nb, int per_block, TileOrder* ord, 
     if (!table) {
         // the context keeps the table of the last tile count it was made for
         auto it = ctx->scratch.find("tile_order");
-        const bool cached = ctx->tile_order_nb == nb && it != ctx->scratch.end();
+        const bool cached = ctx->tile_order_nb == nb && ctx->tile_order_bh == B && it != ctx->scratch.end();
         MRC_TRY(scratch(ctx, "tile_order", (size_t)(n_bands + 1) * sizeof(int64_t), &d));
         if (!cached) {
             hipLaunchKernelGGL(k_band_starts, dim3((unsigned)ceil_div(n_bands + 1, 256)), dim3(256), 0, s, nb,
-                               n_bands, (int64_t*)d);
+                               n_bands, B, (int64_t*)d);
             MRC_HIP_TRY(ctx, hipGetLastError());
             ctx->tile_order_nb = nb;
+            ctx->tile_order_bh = B;
         }
     } else {
-        hipLaunchKernelGGL(k_band_starts, dim3((unsigned)ceil_div(n_bands + 1, 256)), dim3(256), 0, s, nb, n_bands,
+        hipLaunchKernelGGL(k_band_starts, dim3((unsigned)ceil_div(n_bands + 1, 256)), dim3(256), 0, s, nb, n_bands, B,
                            table);
         MRC_HIP_TRY(ctx, hipGetLastError());
     }
     ord->nb = nb;
     ord->n_bands = n_bands;
+    ord->bh = B;
     ord->per_block = per_block;
     ord->n_tiles = t;
     ord->blocks = (t + per_block - 1) / per_block;
