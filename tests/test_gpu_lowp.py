@@ -77,6 +77,29 @@ def test_lowp_decisions_equal_fp32(lib, ctx, prec_name, cfg, n_docs, k):
         assert st["n_flip_outside_nominal"] == 0     # the proven BF16 bound is inside the nominal band
 
 
+@pytest.mark.parametrize("cfg,n_docs,k", [(1, 3000, 64), (2, 2500, 256)])
+def test_fp8_decisions_across_tau(lib, ctx, cfg, n_docs, k):
+    """FP8 candidates pass each 32x32 block's own threshold (from its rows'
+    largest errors): at every tau, and down into the bulk of unrelated pairs'
+    scores, the flagged set still equals the FP32 path's and every rescored
+    score is the FP32 chain."""
+    c, sig = _signed(lib, ctx, cfg, n_docs, k)
+    q = lib.mrc_normalise(ctx, sig, unit=True)
+    unit = q["unit"].cpu().numpy()
+    n = c.n_docs
+    for tau in (0.7, 0.8, 0.85, 0.95):
+        flush(f"  fp8 n={n} k={k} tau={tau}")
+        p32, _ = lib.mrc_compare(ctx, sig, tau, lib.PREC_FP32)
+        p8, st = lib.mrc_compare(ctx, sig, tau, lib.PREC_FP8, 0.02)
+        i32, j32, _, _ = _pairset(lib, p32)
+        i8, j8, s8, f8 = _pairset(lib, p8)
+        np.testing.assert_array_equal(np.sort(i8 * n + j8), np.sort(i32 * n + j32))
+        resc = (f8 & 1) == 1
+        ref32 = om.score32_pairs(unit, i8[resc], j8[resc])
+        np.testing.assert_array_equal(s8[resc].view(np.uint32), ref32.view(np.uint32))
+        flush(f"    flagged={i8.size} rescored={st['n_band']}")
+
+
 def test_lowp_overflow_and_tiny(lib, ctx):
     import torch
     c, sig = _signed(lib, ctx, 0, None, 16)
