@@ -77,8 +77,11 @@ def counter_mean(path: str, counter: str, match) -> tuple[float, int]:
 
 
 def is_copy(name: str) -> bool:
+    """The calibration copy's kernel (a device-to-device copy), not the fill
+    that initialises its source (a fill reads nothing, and averaged in it
+    would understate the copy's FETCH_SIZE)."""
     n = name.lower()
-    return "copy" in n or "elementwise" in n
+    return "copy" in n and "fill" not in n
 
 
 def traffic(a) -> dict:
