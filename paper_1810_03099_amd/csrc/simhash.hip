@@ -62,8 +62,11 @@ __global__ void k_term_hashes(int32_t V, Md5Consts c, uint64_t* __restrict__ out
     if (t < V) out[t] = md5_first8((uint32_t)t, c);
 }
 
-// One wavefront per document; lane b accumulates bit column b over every
-// token occurrence (tokens are read 64 at a time, their hashes broadcast).
+// One wavefront per document, 64 tokens per round, one token per lane. The sum
+// over valid tokens of +1 / -1 for bit b of their hashes is 2 c_b - v, with c_b
+// the number of valid tokens whose bit b is set (one ballot and a popcount per
+// bit) and v the number of valid tokens; lane b keeps c_b, so no hash moves
+// between lanes, and bit b of the word is the sign of 2 c_b - v > 0.
 __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off, int64_t n,
                                                  const int32_t* __restrict__ tok, int32_t V,
                                                  const uint64_t* __restrict__ hash, uint64_t* __restrict__ out,
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off
     const int64_t waves = (int64_t)gridDim.x * 4;
     for (int64_t d = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); d < n; d += waves) {
         const int64_t o = off[d], L = off[d + 1] - o;
-        int acc = 0;
+        int cnt = 0, nvalid = 0;
         for (int64_t p0 = 0; p0 < L; p0 += 64) {
             const int64_t p = p0 + lane;
             uint64_t h = 0;
@@ -87,14 +90,16 @@ __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off
                     atomicOr(err, kErrToken);
                 }
             }
-            const unsigned long long vm = __ballot(valid);
-            const int cnt = (int)min<int64_t>(64, L - p0);
-            for (int j = 0; j < cnt; ++j) {
-                const uint64_t hj = __shfl(h, j, 64);
-                if ((vm >> j) & 1ull) acc += ((hj >> lane) & 1ull) ? 1 : -1;
+            nvalid += __popcll(__ballot(valid));
+            const uint32_t lo = (uint32_t)h, hi = (uint32_t)(h >> 32);
+#pragma unroll
+            for (int b = 0; b < 32; ++b) {
+                const int cl = __popcll(__ballot((lo >> b) & 1u));
+                const int ch = __popcll(__ballot((hi >> b) & 1u));
+                cnt += lane == b ? cl : (lane == b + 32 ? ch : 0);
             }
         }
-        const unsigned long long bits = __ballot(acc > 0);
+        const unsigned long long bits = __ballot(2 * cnt - nvalid > 0);
         if (lane == 0) out[d] = bits;
     }
 }
