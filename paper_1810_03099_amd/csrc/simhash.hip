@@ -105,14 +105,14 @@ __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off
 }
 
 // All pairs i < j with popcount(x_i ^ x_j) <= max_dist. A workgroup takes a
-// 256x256 tile of the upper triangle: column words in LDS, one row per
-// thread; hits are staged in LDS and reserved with one atomic per tile.
+// 256x256 tile of the upper triangle, one row per thread; the column words
+// are read by scalar loads (the same for the whole wavefront); hits are staged
+// in LDS and reserved with one atomic per tile.
 constexpr int kHT = 256;
 constexpr int kHStage = 4096;
 
 __global__ __launch_bounds__(256) void k_hamming(const uint64_t* __restrict__ sim, int n, int max_dist, int nb,
                                                  PairSink sink) {
-    __shared__ uint64_t cols[kHT];
     __shared__ mrc_pair stage[kHStage];
     __shared__ int scount;
     __shared__ unsigned long long sbase;
@@ -127,25 +127,41 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t* __restrict__ si
     const int bj = bi + (int)(t - start(bi));
     const int i = bi * kHT + threadIdx.x;
     const int j0 = bj * kHT;
-    cols[threadIdx.x] = j0 + (int)threadIdx.x < n ? sim[j0 + threadIdx.x] : 0ull;
     if (threadIdx.x == 0) scount = 0;
     __syncthreads();
+    // a hit (row i, column j0 + c): staged in LDS, or straight to the output
+    // when the tile has more hits than the stage holds
+    auto put = [&](int c, int dist) {
+        const int j = j0 + c;
+        const int slot = atomicAdd(&scount, 1);
+        if (slot < kHStage) {
+            stage[slot] = mrc_pair{i, j, (float)dist, 0};
+        } else {
+            const unsigned long long g = atomicAdd(sink.counter, 1ull);
+            if ((int64_t)g < sink.capacity) sink.pairs[g] = mrc_pair{i, j, (float)dist, 0};
+        }
+    };
     if (i < n) {
+        // the column words are the same for every thread: scalar loads, 16
+        // columns per group, the distances' tests gathered into a mask
         const uint64_t x = sim[i];
         const int jmax = min(kHT, n - j0);
-        for (int c = 0; c < jmax; ++c) {
-            const int j = j0 + c;
-            if (j <= i) continue;
-            const int dist = __popcll(x ^ cols[c]);
-            if (dist <= max_dist) {
-                const int slot = atomicAdd(&scount, 1);
-                if (slot < kHStage) {
-                    stage[slot] = mrc_pair{i, j, (float)dist, 0};
-                } else {  // a tile with more hits than the stage holds: direct reservation
-                    const unsigned long long g = atomicAdd(sink.counter, 1ull);
-                    if ((int64_t)g < sink.capacity) sink.pairs[g] = mrc_pair{i, j, (float)dist, 0};
-                }
+        const bool diag = bi == bj;  // only there can j <= i occur
+        int c0 = 0;
+        for (; c0 + 16 <= jmax; c0 += 16) {
+            uint32_t hit = 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                hit |= (__popcll(x ^ sim[j0 + c0 + u]) <= max_dist ? 1u : 0u) << u;
+            while (hit) {
+                const int u = __builtin_ctz(hit);
+                hit &= hit - 1;
+                if (!diag || j0 + c0 + u > i) put(c0 + u, __popcll(x ^ sim[j0 + c0 + u]));
             }
+        }
+        for (int c = c0; c < jmax; ++c) {
+            const int dist = __popcll(x ^ sim[j0 + c]);
+            if (dist <= max_dist && (!diag || j0 + c > i)) put(c, dist);
         }
     }
     __syncthreads();
