@@ -65,19 +65,19 @@ struct PairStage {
     }
 };
 
-// Exclusive prefix sum over the wavefront of a per-lane count below 64, and
-// the total: bit b of every lane's count is one ballot, whose set lanes below
-// this one (mbcnt) contribute 2^b; no data moves between lanes.
-__device__ __forceinline__ void wave_prefix6(int cnt, int* excl, int* total) {
-    int e = 0, t = 0;
+// Sum over the wavefront of a per-lane count below 64 (one ballot per bit).
+__device__ __forceinline__ int wave_total6(int cnt) {
+    int t = 0;
 #pragma unroll
-    for (int b = 0; b < 6; ++b) {
-        const uint64_t bal = __ballot((cnt >> b) & 1);
-        e += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u)) << b;
-        t += __popcll(bal) << b;
-    }
-    *excl = e;
-    *total = t;
+    for (int b = 0; b < 6; ++b) t += __popcll(__ballot((cnt >> b) & 1)) << b;
+    return t;
+}
+
+// Output position of this lane in a round of writes: the lanes of `act` take
+// consecutive positions from `base` in lane order.
+__device__ __forceinline__ int64_t round_pos(int64_t base, uint64_t act) {
+    return base + (int64_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(act >> 32),
+                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)act, 0u));
 }
 
 // Flag marks of one half of a 64x64 wavefront tile (accumulator rows x = 2H,
@@ -98,11 +98,12 @@ __device__ __forceinline__ uint32_t half_marks(const f32x4 (&acc)[4][4], float t
 // Epilogue of one 64x64 wavefront tile, half H (accumulator rows x = 2H, 2H+1),
 // from its marks m (half_marks). Lane (li, lg) holds acc[x][y][r] = score of
 // row ib + 16x + r, column jb + 16y (ib = row0 + 4lg, jb = col0 + li). Outside
-// interior tiles the marks keep only i < j < n; a wavefront scan of the
-// counts gives every lane its output positions; lanes with flags park their
+// interior tiles the marks keep only i < j < n. Lanes with flags park their
 // 32 scores in LDS (scr) so that the flagged ones can be read back by slot
-// index, and write their pairs to the stage (or, for more flags than the
-// stage holds, straight to the output).
+// index; the pairs go to the stage (or, for more flags than the stage holds,
+// straight to the output) in rounds: each lane with marks left writes its
+// lowest one, and a round's lanes take consecutive positions, so the stores
+// of a round are contiguous.
 template <int H>
 __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], uint32_t m, bool interior, int ib, int jb,
                                           int n, float* __restrict__ scr, PairStage& st, const PairSink& sink) {
@@ -116,9 +117,7 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], uint32_t m, 
         }
         m &= valid;
     }
-    const int cnt = __popc(m);
-    int excl, total;
-    wave_prefix6(cnt, &excl, &total);
+    const int total = wave_total6(__popc(m));
     if (total == 0) return;
     if (m) {
 #pragma unroll
@@ -128,28 +127,33 @@ __device__ __forceinline__ void tile_half(const f32x4 (&acc)[4][4], uint32_t m, 
     }
     if (st.n + total > kStage) st.flush(sink);
     const bool direct = total > kStage;
-    int64_t pos;
+    int64_t base;
     if (direct) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(sink.counter, (unsigned long long)total);
-        pos = (int64_t)__shfl(base, 0, 64) + excl;
+        unsigned long long b = 0;
+        if (lane == 0) b = atomicAdd(sink.counter, (unsigned long long)total);
+        base = (int64_t)__shfl(b, 0, 64);
     } else {
-        pos = st.n + excl;
+        base = st.n;
         st.n += total;
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    while (m) {
-        const int sl = __ffs(m) - 1;
-        m &= m - 1;
-        const int xx = sl >> 4, y = (sl >> 2) & 3, r = sl & 3;
-        const mrc_pair pr{ib + 16 * (2 * H + xx) + r, jb + 16 * y, scr[((xx * 4 + y) * 64 + lane) * 4 + r], 0};
-        if (direct) {
-            if (pos < sink.capacity) sink.pairs[pos] = pr;
-        } else {
-            stage_put(st.buf, (int)pos, pr);
+    while (true) {
+        const uint64_t act = __ballot(m != 0);
+        if (act == 0) break;
+        if (m) {
+            const int sl = __ffs(m) - 1;
+            m &= m - 1;
+            const int xx = sl >> 4, y = (sl >> 2) & 3, r = sl & 3;
+            const mrc_pair pr{ib + 16 * (2 * H + xx) + r, jb + 16 * y, scr[((xx * 4 + y) * 64 + lane) * 4 + r], 0};
+            const int64_t pos = round_pos(base, act);
+            if (direct) {
+                if (pos < sink.capacity) sink.pairs[pos] = pr;
+            } else {
+                stage_put(st.buf, (int)pos, pr);
+            }
         }
-        ++pos;
+        base += __popcll(act);
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();

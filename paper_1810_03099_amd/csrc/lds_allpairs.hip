@@ -368,34 +368,39 @@ __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restric
                         const int r = rb + 8 * (i >> 2) + (i & 3);
                         m |= (scr[i * 64 + lane] >= tb && r < cc && cc < n ? 1u : 0u) << i;
                     }
-                    const int cnt = __popc(m);
-                    int excl, total;
-                    wave_prefix6(cnt, &excl, &total);
+                    const int total = wave_total6(__popc(m));
                     if (total == 0) continue;
                     __builtin_amdgcn_sched_barrier(0);
                     if (st.n + total > kStageB) st.flush(cand);
                     const bool direct = total > kStageB;  // more than a stage: straight to the output
-                    int64_t pos;
+                    int64_t base;
                     if (direct) {
-                        unsigned long long base = 0;
-                        if (lane == 0) base = atomicAdd(cand.counter, (unsigned long long)total);
-                        pos = (int64_t)__shfl(base, 0, 64) + excl;
+                        unsigned long long b0 = 0;
+                        if (lane == 0) b0 = atomicAdd(cand.counter, (unsigned long long)total);
+                        base = (int64_t)__shfl(b0, 0, 64);
                     } else {
-                        pos = st.n + excl;
+                        base = st.n;
                         st.n += total;
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
-                    while (m) {
-                        const int i = __ffs(m) - 1;
-                        m &= m - 1;
-                        const mrc_pair pr{rb + 8 * (i >> 2) + (i & 3), cc, scr[i * 64 + lane], 0};
-                        if (direct) {
-                            if (pos < cand.capacity) cand.pairs[pos] = pr;
-                        } else {
-                            stage_put(st.buf, (int)pos, pr);
+                    // rounds: each lane with marks left writes its lowest one,
+                    // the round's lanes at consecutive positions
+                    while (true) {
+                        const uint64_t act = __ballot(m != 0);
+                        if (act == 0) break;
+                        if (m) {
+                            const int i = __ffs(m) - 1;
+                            m &= m - 1;
+                            const mrc_pair pr{rb + 8 * (i >> 2) + (i & 3), cc, scr[i * 64 + lane], 0};
+                            const int64_t pos = round_pos(base, act);
+                            if (direct) {
+                                if (pos < cand.capacity) cand.pairs[pos] = pr;
+                            } else {
+                                stage_put(st.buf, (int)pos, pr);
+                            }
                         }
-                        ++pos;
+                        base += __popcll(act);
                     }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();

@@ -113,6 +113,28 @@ def test_fp32_decisions_across_selections_and_k(lib, ctx, mode, k):
     flush(f"    flagged={gi.size} of {iu.size}")
 
 
+@pytest.mark.parametrize("k,tau", [(16, -2.0), (64, -2.0), (64, 0.5), (100, -2.0), (600, 0.0)])
+def test_fp32_dense_output(lib, ctx, k, tau):
+    """Thresholds that flag most or all pairs: the flag walk's dense paths
+    (tiles with more flagged pairs than a wavefront's stage holds write
+    straight to the output) still emit each flagged pair once, with the chain
+    score, for every tile kernel (k = 16, 64, 100, 600)."""
+    c, sig = _signed(lib, ctx, 1, 1500, k)
+    n = c.n_docs
+    q = lib.mrc_normalise(ctx, sig, unit=True)
+    unit = q["unit"].cpu().numpy()
+    iu, ju, s32 = all_pairs_score32(unit)
+    want = s32 >= np.float32(tau)
+    flush(f"  k={k} tau={tau}: {int(want.sum())} of {iu.size} pairs")
+    pairs, stats = lib.mrc_compare(ctx, sig, tau, lib.PREC_FP32, capacity=int(want.sum()) + 16)
+    gi, gj, gs, _ = lib.pairs_to_numpy(pairs)
+    assert gi.size == int(want.sum()) == stats["n_flagged"]
+    key = gi * n + gj
+    order = np.argsort(key)
+    np.testing.assert_array_equal(key[order], (iu * n + ju)[want])
+    np.testing.assert_array_equal(gs[order].view(np.uint32), s32[want].view(np.uint32))
+
+
 def test_fp32_overflow_protocol_and_tiny_inputs(lib, ctx):
     import torch
     c, sig = _signed(lib, ctx, 0, None, 16)
