@@ -16,8 +16,10 @@
 // reads of 16 consecutive rows hit distinct banks. The fragment reads of step
 // s + 1 are issued before the products of step s (scheduling fences keep the
 // compiler from sinking them), so LDS latency hides behind 16 products. Every
-// score is compared with the candidate threshold; blocks without any score at
-// or above it end after a max tree.
+// score is compared with the candidate threshold (FP8: a 32x32 block whose
+// maximum passes the global one is then held to its own, from its rows'
+// largest errors); blocks without any score at or above it end after a max
+// tree.
 //
 // 32x32 operand / result layouts (lane l): A fragment = row l % 32, the
 // (l / 32)-th half of the step's components (8 BF16 = 16 bytes, or 32 FP8 =
@@ -81,7 +83,9 @@ template <int V>
 using ic = std::integral_constant<int, V>;
 
 // NKC: 128-byte chunks per row (ldq_bytes = 128 NKC). scale: FP8 row scales
-// (powers of two), [rows of q]; unused for BF16.
+// (powers of two), [rows of q]; unused for BF16. lo_thr_ptr: the candidate
+// threshold for every pair (device, one float). bb: FP8 per-block thresholds
+// (BlockBand); unused for BF16.
 template <int PREC, int NKC>
 __global__ __launch_bounds__(256, 1) void k_compare_lds(const uint8_t* __restrict__ q, int ldq_bytes,
                                                         const float* __restrict__ scale, int n,
