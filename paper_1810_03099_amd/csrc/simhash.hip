@@ -64,9 +64,12 @@ __global__ void k_term_hashes(int32_t V, Md5Consts c, uint64_t* __restrict__ out
 
 // One wavefront per document, 64 tokens per round, one token per lane. The sum
 // over valid tokens of +1 / -1 for bit b of their hashes is 2 c_b - v, with c_b
-// the number of valid tokens whose bit b is set (one ballot and a popcount per
-// bit) and v the number of valid tokens; lane b keeps c_b, so no hash moves
-// between lanes, and bit b of the word is the sign of 2 c_b - v > 0.
+// the number of valid tokens whose bit b is set and v the number of valid
+// tokens. A round's 64 hashes (0 for invalid tokens) are a 64x64 bit matrix;
+// six exchange stages between lanes l and l ^ j (j = 32 .. 1) transpose it
+// (each stage swaps the off-diagonal j x j blocks of every 2j x 2j block), so
+// that lane b holds bit b of every token and c_b grows by its popcount; bit b
+// of the word is the sign of 2 c_b - v > 0.
 __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off, int64_t n,
                                                  const int32_t* __restrict__ tok, int32_t V,
                                                  const uint64_t* __restrict__ hash, uint64_t* __restrict__ out,
@@ -91,13 +94,22 @@ __global__ __launch_bounds__(256) void k_simhash(const int64_t* __restrict__ off
                 }
             }
             nvalid += __popcll(__ballot(valid));
-            const uint32_t lo = (uint32_t)h, hi = (uint32_t)(h >> 32);
+            uint64_t w = h;
 #pragma unroll
-            for (int b = 0; b < 32; ++b) {
-                const int cl = __popcll(__ballot((lo >> b) & 1u));
-                const int ch = __popcll(__ballot((hi >> b) & 1u));
-                cnt += lane == b ? cl : (lane == b + 32 ? ch : 0);
+            for (int j = 32; j >= 1; j >>= 1) {
+                // the low j bits of every 2j-bit group
+                const uint64_t m = j == 32 ? 0x00000000FFFFFFFFull
+                                 : j == 16 ? 0x0000FFFF0000FFFFull
+                                 : j == 8  ? 0x00FF00FF00FF00FFull
+                                 : j == 4  ? 0x0F0F0F0F0F0F0F0Full
+                                 : j == 2  ? 0x3333333333333333ull
+                                           : 0x5555555555555555ull;
+                const uint64_t p = __shfl_xor(w, j, 64);
+                const bool first = (lane & j) == 0;  // the pair's lower lane
+                const uint64_t t = (((first ? w : p) >> j) ^ (first ? p : w)) & m;
+                w ^= first ? (t << j) : t;
             }
+            cnt += __popcll(w);
         }
         const unsigned long long bits = __ballot(2 * cnt - nvalid > 0);
         if (lane == 0) out[d] = bits;
