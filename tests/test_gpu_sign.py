@@ -155,6 +155,24 @@ def test_build_and_sign_equals_build_then_sign(lib, ctx, which):
     assert np.abs(sig.cpu().numpy() - osig).max() <= SIG_TOL
 
 
+def test_build_and_sign_large_corpus(lib, ctx):
+    """From 65,536 documents on, the fused call signs through the form that
+    keeps the most frequent terms' information in LDS: the same model and the
+    same signature and norm bits as building, then signing separately."""
+    c = synth.generate(1, n_docs=70000)
+    _, gspec = _spec_pair(lib, 64, om.SEL_DROP_TOP)
+    o, t = device_docs(c)
+    flush(f"  fused build+sign n={c.n_docs}")
+    gm, sig, norm = lib.mrc_build_and_sign(ctx, o, t, c.vocab, gspec, with_norm=True)
+    gm2 = lib.mrc_build_vocab_idf(ctx, o, t, c.vocab, gspec)
+    sig2, norm2 = lib.mrc_sign(ctx, gm2, o, t, with_norm=True)
+    a, b = lib.mrc_model_get(gm), lib.mrc_model_get(gm2)
+    for key in ("df", "idf", "term_at", "rank_of", "part_of", "rnorm"):
+        np.testing.assert_array_equal(a[key], b[key])
+    np.testing.assert_array_equal(sig.cpu().numpy(), sig2.cpu().numpy())
+    np.testing.assert_array_equal(norm.cpu().numpy(), norm2.cpu().numpy())
+
+
 def test_norm_is_exact_sum_rounded_once(lib, ctx):
     """|w_d| is the square root of the exact sum of (tf * idf32)^2, rounded to
     float64 once, square-rooted in float64, then rounded to float32; checked
