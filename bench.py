@@ -894,9 +894,17 @@ def serve_run(mrc, srv, arrival_gaps, docs, mixed=False):
     # (after the saturation burst) shows as a p99 well above this one
     t_cut = first + 0.2 * (max(r.t_submit_ms for r, _ in ok) - first) if ok else first
     late = [r.t_done_ms - r.t_submit_ms for r, _ in ok if r.t_submit_ms >= t_cut]
+    # the worst latency of each tenth of the run by submit time: where a stall fell
+    t_last = max((r.t_submit_ms for r, _ in ok), default=first)
+    span = max(t_last - first, 1e-9)
+    worst = [0.0] * 10
+    for r, _ in ok:
+        w = min(9, int((r.t_submit_ms - first) / span * 10))
+        worst[w] = max(worst[w], r.t_done_ms - r.t_submit_ms)
     out = {"offered": n_req, "admitted": len(res), "completed": len(lat),
            "p50_ms": percentile_ms(lat, 50), "p99_ms": percentile_ms(lat, 99),
            "p99_after_first_fifth_ms": percentile_ms(late, 99), "max_ms": max(lat) if lat else None,
+           "max_ms_by_tenth": [round(x, 3) for x in worst],
            "docs_per_s": len(lat) / ((last - first) / 1e3), "wall_s": wall, "lag_ms": lag * 1e3}
     if mixed:
         out["query_p50_ms"] = percentile_ms(latq, 50)
