@@ -437,8 +437,9 @@ static mrc_status compare_impl(mrc_ctx* ctx, const float* sig, int64_t n, int32_
         const int64_t n_pad = ceil_div(n > 0 ? n : 1, 128) * 128, kp = 16 * (int64_t)mfma_chunks(k);  // 128-row tiles
         void* umfma = nullptr;
         MRC_TRY(scratch(ctx, "cmp_unit_mfma", (size_t)(n_pad * kp) * sizeof(float), &umfma));
-        MRC_TRY(clear_words(ctx, ctx->d_flags, 16, s));
-        MRC_TRY(launch_normalise(ctx, sig, n, k, nullptr, nullptr, nullptr, nullptr, nullptr, s, (float*)umfma));
+        // (the normalising launch also zeroes the flag words the comparison counts into)
+        MRC_TRY(launch_normalise(ctx, sig, n, k, nullptr, nullptr, nullptr, nullptr, nullptr, s, (float*)umfma,
+                                 ctx->d_flags, 16));
         PairSink sink{pairs_out, capacity, counter};
         MRC_TRY(launch_compare_f32(ctx, (const float*)umfma, n, k, opts->tau, sink, s));
         MRC_TRY(sync_flags(ctx, s, 16, "mrc_compare"));
@@ -467,10 +468,11 @@ static mrc_status compare_impl(mrc_ctx* ctx, const float* sig, int64_t n, int32_
     for (int attempt = 0; attempt < 2; ++attempt) {
         void* cand = nullptr;
         MRC_TRY(scratch(ctx, "lp_cand", (size_t)cand_cap * sizeof(mrc_pair), &cand));
-        MRC_TRY(clear_words(ctx, ctx->d_flags, 32, s));
         NormLayout o{(float*)unit, k, prec == MRC_PREC_BF16 ? (uint16_t*)q : nullptr, ldq,
                      prec == MRC_PREC_FP8 ? (uint8_t*)q : nullptr, ldq, (float*)scale, (float*)err, n_pad,
                      nullptr, 0, n_pad, 0, prec == MRC_PREC_BF16 ? 1 : 2};
+        o.clear = ctx->d_flags;  // (zeroed by the normalising launch: the candidate and pair counters)
+        o.n_clear = 32;
         MRC_TRY(launch_normalise_rows(ctx, sig, n, k, o, s));
         const float* err_p = (const float*)err + (prec == MRC_PREC_BF16 ? 0 : n_pad);
         float* d_lo = (float*)(ctx->d_flags + 22);

@@ -253,7 +253,7 @@ mrc_status launch_sign(mrc_ctx* ctx, const mrc_model* m, const mrc_docs* docs, f
 // with transposed 4x4 sub-blocks in each 16-column block and zero padding.
 mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit,
                             uint16_t* bf16, uint8_t* fp8, float* scale, float* err,
-                            hipStream_t s, float* umfma = nullptr);
+                            hipStream_t s, float* umfma = nullptr, int64_t* clear = nullptr, int n_clear = 0);
 
 // Pair output buffer shared by the all-pairs kernels.
 struct PairSink {
@@ -303,6 +303,8 @@ struct NormLayout {
     int64_t n_pad;
     int frag = 0;
     int errs = 3;     // row errors formed: bit 0 BF16, bit 1 FP8 (the other half of err is 0)
+    int64_t* clear = nullptr;  // words (at most 256) zeroed by the normalising launch: the
+    int n_clear = 0;           // counters of the kernels that follow it on the stream
 };
 
 // Offset of component c of row r in the fragment-major FP32 layout with nc

@@ -67,6 +67,7 @@ using mrc_dev::mfma_col;
 using NormOut = NormLayout;
 
 __global__ __launch_bounds__(256) void k_normalise(const float* __restrict__ sig, int64_t n, int k, NormOut o) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < o.n_clear) o.clear[threadIdx.x] = 0;
     const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (row >= o.n_pad) return;
@@ -175,6 +176,7 @@ __device__ __forceinline__ float group_max(float v) {
 template <int LPR, int VPL>
 __global__ __launch_bounds__(256) void k_normalise_vec(const float* __restrict__ sig, int64_t n, int k, NormOut o,
                                                        int wide) {
+    if (blockIdx.x == 0 && (int)threadIdx.x < o.n_clear) o.clear[threadIdx.x] = 0;
     constexpr int RPW = 64 / LPR;
     const int lane = threadIdx.x & 63, li = lane % LPR;
     const int64_t row = ((int64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * RPW + lane / LPR;
@@ -448,9 +450,11 @@ int mfma_chunks(int k);
 
 mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, float* unit,
                             uint16_t* bf16, uint8_t* fp8, float* scale, float* err, hipStream_t s,
-                            float* umfma) {
+                            float* umfma, int64_t* clear, int n_clear) {
     if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
     NormOut o{unit, k, bf16, k, fp8, k, scale, err, n, umfma, 16 * mfma_chunks(k), n, 1};
+    o.clear = clear;
+    o.n_clear = n_clear;
     if (umfma) o.n_pad = ceil_div(n, 128) * 128;  // the FP32 kernel's 128-row tiles
     return launch_normalise_rows(ctx, sig, n, k, o, s);
 }
@@ -458,7 +462,8 @@ mrc_status launch_normalise(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k
 mrc_status launch_normalise_rows(mrc_ctx* ctx, const float* sig, int64_t n, int32_t k, const NormLayout& o,
                                  hipStream_t s) {
     if (k > 64 * kMaxPerLane) return fail(MRC_E_INVAL, "k exceeds 1024");
-    if (o.n_pad == 0) return MRC_OK;
+    if (o.n_clear > 256) return fail(MRC_E_INVAL, "normalise: at most 256 words to clear");
+    if (o.n_pad == 0) return o.n_clear > 0 ? clear_words(ctx, o.clear, o.n_clear, s) : MRC_OK;
     ScopedTimer tm(ctx, "normalise", s);
     // k a multiple of 4: four components per lane, vector accesses where the
     // rows are aligned for them (the results do not depend on which)
