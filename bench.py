@@ -170,7 +170,7 @@ def main():
         copy_probe(a.copy_probe)
         return
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is designed but not launched",
+        print(json.dumps({"error": "the library runs on one GPU; multi-GPU sharding is designed but not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch
