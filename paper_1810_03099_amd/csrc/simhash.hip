@@ -161,10 +161,13 @@ __global__ __launch_bounds__(256) void k_hamming(const uint64_t* __restrict__ si
         const bool diag = bi == bj;  // only there can j <= i occur
         int c0 = 0;
         for (; c0 + 16 <= jmax; c0 += 16) {
-            uint32_t hit = 0;
+            // bit u: the sign of max_dist - distance (distances and max_dist are
+            // small non-negative integers), shifted in by a funnel shift
+            uint32_t far = 0;
 #pragma unroll
-            for (int u = 0; u < 16; ++u)
-                hit |= (__popcll(x ^ sim[j0 + c0 + u]) <= max_dist ? 1u : 0u) << u;
+            for (int u = 15; u >= 0; --u)
+                far = __builtin_amdgcn_alignbit(far, (uint32_t)(max_dist - __popcll(x ^ sim[j0 + c0 + u])), 31);
+            uint32_t hit = ~far & 0xFFFFu;
             while (hit) {
                 const int u = __builtin_ctz(hit);
                 hit &= hit - 1;
