@@ -100,6 +100,41 @@ def test_fp8_decisions_across_tau(lib, ctx, cfg, n_docs, k):
         flush(f"    flagged={i8.size} rescored={st['n_band']}")
 
 
+def test_fp8_decisions_with_mixed_row_errors(lib, ctx):
+    """Rows whose FP8 errors differ widely (half of them with a few large
+    components over many tiny ones, which quantise coarsely), in clusters of
+    near-duplicates so that many pairs lie near every tau: each 32x32 block's
+    own candidate threshold still keeps every pair the FP32 path flags."""
+    import torch
+    rng = np.random.default_rng(7)
+    n, k = 3000, 128
+    base = rng.random((n // 10, k)) ** 3
+    spiky = rng.random(n // 10) < 0.5
+    base[spiky] = rng.random((int(spiky.sum()), k)) ** 12 * 1e-3
+    for r in np.nonzero(spiky)[0]:
+        base[r, rng.choice(k, 4, replace=False)] += rng.random(4) + 0.5
+    sig = np.repeat(base, 10, axis=0) + rng.normal(0, 0.03, (n, k)) ** 2
+    perm = rng.permutation(n)
+    sig = np.ascontiguousarray(sig[perm], dtype=np.float32)
+    dsig = torch.from_numpy(sig).cuda()
+    q = lib.mrc_normalise(ctx, dsig, unit=True, fp8=True, err=True)
+    e8 = q["err"].cpu().numpy()[1]
+    flush(f"  FP8 row errors: min {e8.min():.4f} median {np.median(e8):.4f} max {e8.max():.4f}")
+    assert e8.max() > 4 * e8.min()
+    unit = q["unit"].cpu().numpy()
+    # the dense rows' pairs score about 0.55-0.65, the near-duplicates' about 0.97-1
+    for tau in (0.55, 0.6, 0.65, 0.97, 0.99):
+        p32, _ = lib.mrc_compare(ctx, dsig, tau, lib.PREC_FP32)
+        p8, st = lib.mrc_compare(ctx, dsig, tau, lib.PREC_FP8, 0.02)
+        i32, j32, _, _ = _pairset(lib, p32)
+        i8, j8, s8, f8 = _pairset(lib, p8)
+        flush(f"    tau={tau}: flagged {i32.size}, FP8 rescored {st['n_band']}")
+        np.testing.assert_array_equal(np.sort(i8 * n + j8), np.sort(i32 * n + j32))
+        resc = (f8 & 1) == 1
+        ref32 = om.score32_pairs(unit, i8[resc], j8[resc])
+        np.testing.assert_array_equal(s8[resc].view(np.uint32), ref32.view(np.uint32))
+
+
 def test_lowp_overflow_and_tiny(lib, ctx):
     import torch
     c, sig = _signed(lib, ctx, 0, None, 16)
