@@ -100,11 +100,13 @@ def test_fp8_decisions_across_tau(lib, ctx, cfg, n_docs, k):
         flush(f"    flagged={i8.size} rescored={st['n_band']}")
 
 
-def test_fp8_decisions_with_mixed_row_errors(lib, ctx):
-    """Rows whose FP8 errors differ widely (half of them with a few large
-    components over many tiny ones, which quantise coarsely), in clusters of
-    near-duplicates so that many pairs lie near every tau: each 32x32 block's
-    own candidate threshold still keeps every pair the FP32 path flags."""
+@pytest.mark.parametrize("prec_name", ["fp8", "bf16"])
+def test_lowp_decisions_with_mixed_row_errors(lib, ctx, prec_name):
+    """Rows whose low-precision errors differ widely (half of them with a few
+    large components over many tiny ones), in clusters of near-duplicates so
+    that many pairs lie near every tau: the candidate thresholds (FP8: each
+    32x32 block's own) still keep every pair the FP32 path flags."""
+    prec = {"bf16": lib.PREC_BF16, "fp8": lib.PREC_FP8}[prec_name]
     import torch
     rng = np.random.default_rng(7)
     n, k = 3000, 128
@@ -125,10 +127,10 @@ def test_fp8_decisions_with_mixed_row_errors(lib, ctx):
     # the dense rows' pairs score about 0.55-0.65, the near-duplicates' about 0.97-1
     for tau in (0.55, 0.6, 0.65, 0.97, 0.99):
         p32, _ = lib.mrc_compare(ctx, dsig, tau, lib.PREC_FP32)
-        p8, st = lib.mrc_compare(ctx, dsig, tau, lib.PREC_FP8, 0.02)
+        p8, st = lib.mrc_compare(ctx, dsig, tau, prec, 0.02)
         i32, j32, _, _ = _pairset(lib, p32)
         i8, j8, s8, f8 = _pairset(lib, p8)
-        flush(f"    tau={tau}: flagged {i32.size}, FP8 rescored {st['n_band']}")
+        flush(f"    {prec_name} tau={tau}: flagged {i32.size}, rescored {st['n_band']}")
         np.testing.assert_array_equal(np.sort(i8 * n + j8), np.sort(i32 * n + j32))
         resc = (f8 & 1) == 1
         ref32 = om.score32_pairs(unit, i8[resc], j8[resc])
